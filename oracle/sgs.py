@@ -1,0 +1,150 @@
+"""One imaginary-time step of the SGS method, written out from the paper.
+
+Steps, in the paper's order (Sec. III.C: alternate the amplitude solve and the
+covariance-matrix step):
+
+1. Gram matrix G and projected Hamiltonian h (Sec. II.C):
+   G_ab = <phi_a|phi_b>, h_ab = <phi_a|H|phi_b> = G_ab * <H>_t(Delta^{ba}).
+2. Amplitudes from h lambda = E G lambda, Eq. (eigLambda), lowest E,
+   normalized lambda^dag G lambda = 1; renormalized amplitudes
+   lambda~_mu = <phi_mu|psi> = (G lambda)_mu (Sec. III.A).
+3. Covariance-matrix force, Eq. (EOM-Gamma3), read with lambda~_mu^* as in
+   Eq. (EOM-Gamma2) (the printed lambda~_mu in Eq. (EOM-Gamma3) drops the star):
+   dG_mu = sum_b lambda_b lambda~_mu^* c_mu [ 2i G_mb [D, F] + 2 G_mb (D F D + F)
+           - h_mb D + sum_g G_mg (G^-1 h)_gb Delta^{g mu} ] + c.c.,
+   with D = Delta^{b mu}, F = F^{b mu};
+   c_mu = 1 / (lambda_mu lambda~_mu^*) (printed choice, Sec. III.A) or the
+   unit-modulus choice lambda~_mu lambda_mu^* / |lambda~_mu lambda_mu|.
+4. First-order step, Eq. (RKstep), Gamma + ds dGamma, then the canonical form
+   Eq. (CM-normal-form) with every lambda_j rescaled to unit modulus, i.e. the
+   polar factor of the updated matrix (computed exactly with eigh).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Optional
+
+import numpy as np
+
+from .gaussian import delta, fock_matrix, overlap_table, poly_value, quartic_tensor
+
+
+@dataclass
+class PairTables:
+    G: np.ndarray          # (R, R) complex Gram matrix
+    h: np.ndarray          # (R, R) complex <phi_a|H|phi_b>
+    logabs: np.ndarray     # log|G|
+    arg: np.ndarray        # arg G
+    eps: np.ndarray        # h_ab / G_ab
+
+
+def pair_tables(ham, gammas: np.ndarray, use_direct: bool = False, hpoly=None) -> PairTables:
+    R = gammas.shape[0]
+    la, ar = overlap_table(gammas, use_direct)
+    G = np.exp(la) * np.exp(1j * ar)
+    hp = ham.poly() if hpoly is None else hpoly
+    eps = np.zeros((R, R), dtype=complex)
+    for a in range(R):
+        for b in range(R):
+            d = gammas[a] if a == b else delta(gammas[b], gammas[a])  # Delta^{ba}
+            eps[a, b] = poly_value(d, hp)
+    h = G * eps
+    return PairTables(G=G, h=h, logabs=la, arg=ar, eps=eps)
+
+
+def solve_amplitudes(G: np.ndarray, h: np.ndarray, rel_threshold: float = 1e-12):
+    """Lowest (E, lambda) of h lambda = E G lambda after canonical orthogonalization
+    (eigenvectors of G below rel_threshold * max eigenvalue are dropped)."""
+    Gh = 0.5 * (G + G.conj().T)
+    hh = 0.5 * (h + h.conj().T)
+    s, U = np.linalg.eigh(Gh)
+    keep = s > rel_threshold * s.max()
+    X = U[:, keep] / np.sqrt(s[keep])[None, :]
+    hp = X.conj().T @ hh @ X
+    e, y = np.linalg.eigh(0.5 * (hp + hp.conj().T))
+    lam = X @ y[:, 0]
+    return float(e[0]), lam
+
+
+def weights(lam: np.ndarray, lamt: np.ndarray, mode: str = "printed") -> np.ndarray:
+    """c_mu of Eq. (Bmu)."""
+    if mode == "printed":
+        return 1.0 / (lam * lamt.conj())
+    if mode == "unit":
+        return lamt * lam.conj() / np.abs(lamt * lam)
+    raise ValueError(mode)
+
+
+def forces(ham, gammas: np.ndarray, tab: PairTables, E: float, lam: np.ndarray,
+           mode: str = "printed") -> np.ndarray:
+    """dGamma_mu / ds for every state, Eq. (EOM-Gamma3) in its printed long form."""
+    R, n, _ = gammas.shape
+    G, h = tab.G, tab.h
+    lamt = G @ lam
+    c = weights(lam, lamt, mode)
+    Ginv_h = np.linalg.solve(G, h)
+    qt = quartic_tensor(ham)
+    out = np.zeros((R, n, n))
+    for mu in range(R):
+        D = [gammas[mu] if b == mu else delta(gammas[b], gammas[mu]) for b in range(R)]  # Delta^{b mu}
+        acc = np.zeros((n, n), dtype=complex)
+        for b in range(R):
+            F = fock_matrix(ham, D[b], qt)
+            DF = D[b] @ F
+            FD = F @ D[b]
+            term = (2j * G[mu, b] * (DF - FD)
+                    + 2.0 * G[mu, b] * (DF @ D[b] + F)
+                    - h[mu, b] * D[b])
+            for g in range(R):
+                term = term + G[mu, g] * Ginv_h[g, b] * D[g]
+            acc += lam[b] * np.conj(lamt[mu]) * c[mu] * term
+        out[mu] = (acc + acc.conj()).real
+    return out
+
+
+def purify(x: np.ndarray) -> np.ndarray:
+    """Polar factor of a real skew matrix: canonical form with unit lambda_j."""
+    x = 0.5 * (x - x.T)
+    s, V = np.linalg.eigh(1j * x)  # i x is Hermitian
+    g = (-1j * (V * np.sign(s)[None, :]) @ V.conj().T).real
+    return 0.5 * (g - g.T)
+
+
+@dataclass
+class StepResult:
+    gammas: np.ndarray
+    E: float
+    lam: np.ndarray
+    tables: PairTables
+    dgamma: np.ndarray
+
+
+def step(ham, gammas: np.ndarray, dtau: float, mode: str = "printed",
+         rel_threshold: float = 1e-12, hpoly=None) -> StepResult:
+    tab = pair_tables(ham, gammas, hpoly=hpoly)
+    E, lam = solve_amplitudes(tab.G, tab.h, rel_threshold)
+    dg = forces(ham, gammas, tab, E, lam, mode)
+    new = np.stack([purify(gammas[m] + dtau * dg[m]) for m in range(gammas.shape[0])])
+    return StepResult(gammas=new, E=E, lam=lam, tables=tab, dgamma=dg)
+
+
+def energy(ham, gammas: np.ndarray, hpoly=None):
+    tab = pair_tables(ham, gammas, hpoly=hpoly)
+    E, lam = solve_amplitudes(tab.G, tab.h)
+    return E, lam, tab
+
+
+def run(ham, gammas: np.ndarray, dtau: float, nsteps: int, mode: str = "printed",
+        callback=None) -> tuple:
+    """nsteps steps; returns (final gammas, energies of the states entering each step)."""
+    hp = ham.poly()
+    es: List[float] = []
+    g = gammas
+    for k in range(nsteps):
+        r = step(ham, g, dtau, mode, hpoly=hp)
+        es.append(r.E)
+        g = r.gammas
+        if callback is not None:
+            callback(k, r)
+    return g, np.array(es)

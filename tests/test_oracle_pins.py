@@ -1,0 +1,329 @@
+"""Pins of the CPU oracle against facts fixed outside it.
+
+Every check here compares the oracle with something it does not compute itself:
+brute-force Fock-space vectors (Jordan-Wigner), the defining Pfaffian
+expansion, closed forms, exact diagonalization and invariants stated in the
+paper.  A wrong sign, dropped term, swapped index or transposed operand in the
+oracle fails at least one of them.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import sgs_inputs as si
+from oracle import ed, fock, gaussian as ga, observables as ob, sgs
+from oracle.pfaffian import pfaffian, pfaffian_expand, pfaffian_log
+
+
+def _rand_skew(n, rng, cplx=False):
+    a = rng.standard_normal((n, n))
+    if cplx:
+        a = a + 1j * rng.standard_normal((n, n))
+    return a - a.T
+
+
+# ----------------------------------------------------------------- Pfaffian
+
+@pytest.mark.parametrize("n", [2, 4, 6, 8])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_pfaffian_matches_expansion(n, cplx):
+    rng = np.random.default_rng(n + 10 * cplx)
+    a = _rand_skew(n, rng, cplx)
+    assert abs(pfaffian(a) - pfaffian_expand(a)) < 1e-12 * max(1.0, abs(pfaffian_expand(a)))
+
+
+@pytest.mark.parametrize("n", [10, 40])
+def test_pfaffian_square_is_det_and_congruence(n):
+    rng = np.random.default_rng(n)
+    a = _rand_skew(n, rng, True)
+    p = pfaffian(a)
+    assert abs(p * p - np.linalg.det(a)) < 1e-9 * abs(p * p)
+    q = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    p2 = pfaffian(q.T @ a @ q)
+    assert abs(p2 - np.linalg.det(q) * p) < 1e-8 * abs(p2)
+
+
+def test_pfaffian_canonical_block_form():
+    # Pf of (+) [[0, a_j], [-a_j, 0]] is prod a_j; a basis swap flips the sign
+    a = np.array([0.5, -2.0, 3.0])
+    m = np.zeros((6, 6))
+    for j, x in enumerate(a):
+        m[2 * j, 2 * j + 1], m[2 * j + 1, 2 * j] = x, -x
+    assert abs(pfaffian(m) - np.prod(a)) < 1e-14
+    perm = [1, 0, 2, 3, 4, 5]
+    assert abs(pfaffian(m[np.ix_(perm, perm)]) + np.prod(a)) < 1e-14
+    assert pfaffian_log(np.zeros((4, 4)))[0] == -math.inf
+
+
+# ------------------------------------------------------- models and states
+
+@pytest.mark.parametrize("builder", [
+    lambda: si.anderson_terms(1, 1.3, 0.7),
+    lambda: si.anderson_terms(2, 2.0, 0.4, t=0.8, mu=0.1),
+    lambda: si.two_channel_kondo_terms(1, 0.7, U=3.0),
+])
+def test_majorana_form_equals_fermionic_operator(builder):
+    N, terms = builder()
+    poly = si.fermion_terms_to_majorana(terms)
+    ham = si.MajoranaHamiltonian.from_poly(N, poly)
+    hm = fock.majorana_poly_operator(N, ham.poly())
+    hf = fock.fermion_operator(N, terms)
+    assert np.abs(hm - hf).max() < 1e-13
+
+
+def test_anderson_closed_form_coefficients():
+    # -t (a_j^dag a_k + h.c.) -> A[2j, 2k+1] = -t/4, A[2j+1, 2k] = t/4;
+    # U n_up n_dn at eps_d = -U/2 -> no impurity quadratic term, e0 = -U/4, u = -U/4
+    h = si.anderson(3, 2.0, 0.6)
+    assert h.A[0, 5] == pytest.approx(-0.6 / 4) and h.A[1, 4] == pytest.approx(0.6 / 4)
+    assert h.A[4, 9] == pytest.approx(-0.25) and h.A[5, 8] == pytest.approx(0.25)
+    assert h.A[0, 1] == 0.0 and h.A[2, 3] == 0.0
+    assert h.e0 == pytest.approx(-0.5)
+    assert h.quartic_idx.tolist() == [[0, 1, 2, 3]] and h.quartic_val[0] == pytest.approx(-0.5)
+    assert np.abs(h.A + h.A.T).max() == 0.0
+
+
+def test_two_channel_kondo_structure():
+    h = si.two_channel_kondo(150, 0.3)
+    assert h.N == 602 and h.n == 1204
+    assert len(h.quartic_val) == 25
+    assert sorted(set(np.round(np.abs(h.quartic_val[1:]), 12))) == [round(0.3 / 16, 12)]
+    assert len(h.impurity_majoranas()) == 12
+
+
+def test_spin_dot_poly_equals_fermionic():
+    N = 4
+    poly = si.spin_dot_poly((0, 1), (2, 3))
+    hm = fock.majorana_poly_operator(N, poly)
+    hf = fock.fermion_operator(N, si.spin_dot_terms((0, 1), (2, 3)))
+    assert np.abs(hm - hf).max() < 1e-14
+
+
+def test_random_states_pure_even_and_vacuum_convention():
+    g = si.random_states(4, 3, seed=7)
+    for x in g:
+        assert np.abs(x + x.T).max() == 0.0
+        assert np.abs(x @ x + np.eye(8)).max() < 1e-13
+        assert pfaffian(x) == pytest.approx(1.0, abs=1e-12)
+    vac = np.zeros(2 ** 4)
+    vac[0] = 1.0
+    assert np.abs(fock.covariance(vac, 4) - si.vacuum_cm(4)).max() < 1e-15
+    for x in g:
+        psi = fock.gaussian_state(x)
+        assert np.abs(fock.covariance(psi, 4) - x).max() < 1e-12
+        par = np.vdot(psi, fock.parity_operator(4) @ psi).real
+        assert par == pytest.approx(1.0, abs=1e-12)
+
+
+# -------------------------------------------------------- overlaps and Wick
+
+@pytest.fixture(scope="module")
+def tiny():
+    ham = si.anderson(1, 1.3, 0.7)
+    g = si.random_states(ham.N, 3, seed=3)
+    vecs = [fock.gaussian_state(x) for x in g]
+    vecs = fock.fix_gauge(vecs, vecs[0])
+    return ham, g, vecs
+
+
+def test_overlap_magnitude_and_pfaffian_sign(tiny):
+    ham, g, vecs = tiny
+    N = ham.N
+    for a in range(3):
+        for b in range(3):
+            if a == b:
+                continue
+            ov = abs(np.vdot(vecs[a], vecs[b]))
+            assert math.exp(ga.log_abs_overlap(g[a], g[b])) == pytest.approx(ov, rel=1e-12)
+            # same-parity states: Pf(G_a + G_b) = 2^N |<a|b>|^2 >= 0 (no sign ambiguity)
+            assert pfaffian(g[a] + g[b]) == pytest.approx(2 ** N * ov ** 2, rel=1e-12)
+
+
+@pytest.mark.parametrize("direct", [False, True])
+def test_triple_product_phase(tiny, direct):
+    ham, g, vecs = tiny
+    t = np.vdot(vecs[0], vecs[1]) * np.vdot(vecs[1], vecs[2]) * np.vdot(vecs[2], vecs[0])
+    f = ga.triple_product_direct if direct else ga.triple_product_schur
+    la, ph = f(g[0], g[1], g[2])
+    assert abs(ph * math.exp(la) - t) < 1e-13
+
+
+def test_gram_matrix_in_reference_gauge(tiny):
+    ham, g, vecs = tiny
+    V = np.stack(vecs, 1)
+    assert np.abs(ga.gram(g) - V.conj().T @ V).max() < 1e-13
+    assert np.abs(ga.gram(g, use_direct=True) - V.conj().T @ V).max() < 1e-13
+
+
+def test_transition_matrix(tiny):
+    ham, g, vecs = tiny
+    N, n = ham.N, ham.n
+    c = fock.majoranas(N)
+    for a, b in [(1, 2), (2, 0), (0, 1)]:
+        d = ga.delta(g[a], g[b])
+        gba = np.vdot(vecs[b], vecs[a])
+        for k in range(n):
+            for l in range(n):
+                if k != l:
+                    v = np.vdot(vecs[b], c[k] @ c[l] @ vecs[a])
+                    assert abs(v - 1j * gba * d[k, l]) < 1e-13
+        assert np.abs(d + d.T).max() < 1e-12                         # skew
+        assert np.abs(d - ga.delta(g[b], g[a]).conj()).max() < 1e-12  # D^{ab} = conj D^{ba}
+        assert np.abs(d @ d + np.eye(n)).max() < 1e-11               # D^2 = -1
+    assert np.abs(ga.delta(g[1], g[1]) - g[1]).max() < 1e-13          # D^{aa} = Gamma_a
+
+
+@pytest.mark.parametrize("model", ["anderson", "tck"])
+def test_projected_hamiltonian(model):
+    if model == "anderson":
+        N, terms = si.anderson_terms(1, 1.3, 0.7)
+    else:
+        N, terms = si.two_channel_kondo_terms(1, 0.9, U=2.0)
+    ham = si.MajoranaHamiltonian.from_poly(N, si.fermion_terms_to_majorana(terms))
+    g = si.random_states(N, 3, seed=11)
+    vecs = fock.fix_gauge([fock.gaussian_state(x) for x in g], fock.gaussian_state(g[0]))
+    vecs = fock.fix_gauge(vecs, vecs[0])
+    V = np.stack(vecs, 1)
+    H = fock.fermion_operator(N, terms)
+    tab = sgs.pair_tables(ham, g)
+    assert np.abs(tab.G - V.conj().T @ V).max() < 1e-13
+    assert np.abs(tab.h - V.conj().T @ H @ V).max() < 1e-12
+
+
+# ------------------------------------------------------------------- force
+
+def _bruteforce_force(ham, g, mode):
+    N, n, R = ham.N, ham.n, g.shape[0]
+    vecs = fock.fix_gauge([fock.gaussian_state(x) for x in g], fock.gaussian_state(g[0]))
+    vecs = fock.fix_gauge(vecs, vecs[0])
+    V = np.stack(vecs, 1)
+    H = fock.majorana_poly_operator(N, ham.poly())
+    Gb, hb = V.conj().T @ V, V.conj().T @ H @ V
+    E, lam = sgs.solve_amplitudes(Gb, hb)
+    psi = V @ lam
+    lamt = Gb @ lam
+    c = sgs.weights(lam, lamt, mode)
+    pperp = np.eye(2 ** N) - V @ np.linalg.inv(Gb) @ V.conj().T  # projector of Eq. (projImEvol)
+    cm = fock.majoranas(N)
+    out = np.zeros((R, n, n))
+    for mu in range(R):
+        B = c[mu] * np.outer(pperp @ H @ psi, psi.conj())       # Eq. (Bmu)
+        B = B + B.conj().T
+        dphi = -B @ vecs[mu]                                     # Eq. (PhiMu)
+        for k in range(n):
+            for l in range(n):
+                if k != l:
+                    v = -1j * np.vdot(vecs[mu], cm[k] @ cm[l] @ dphi)
+                    out[mu, k, l] = 2 * v.real
+    return out
+
+
+@pytest.mark.parametrize("mode", ["printed", "unit"])
+@pytest.mark.parametrize("model", ["anderson", "tck"])
+def test_force_matches_bruteforce_derivative(mode, model):
+    if model == "anderson":
+        ham = si.anderson(1, 1.3, 0.7)
+    else:
+        ham = si.two_channel_kondo(1, 0.9, U=2.0)
+    g = si.random_states(ham.N, 3, seed=3)
+    tab = sgs.pair_tables(ham, g)
+    E, lam = sgs.solve_amplitudes(tab.G, tab.h)
+    dg = sgs.forces(ham, g, tab, E, lam, mode)
+    ref = _bruteforce_force(ham, g, mode)
+    assert np.abs(dg - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+    for mu in range(3):  # purity preservation, Sec. III.B
+        assert np.abs(dg[mu] @ g[mu] + g[mu] @ dg[mu]).max() < 1e-12
+
+
+def test_rank_one_is_ghf_imaginary_time():
+    # R = 1: the normalization line cancels and dGamma = 4 (F + Gamma F Gamma)
+    ham = si.anderson(2, 1.5, 0.6)
+    g = si.random_states(ham.N, 1, seed=2)
+    tab = sgs.pair_tables(ham, g)
+    E, lam = sgs.solve_amplitudes(tab.G, tab.h)
+    dg = sgs.forces(ham, g, tab, E, lam, "printed")
+    F = ga.fock_matrix(ham, g[0]).real
+    assert np.abs(dg[0] - 4 * (F + g[0] @ F @ g[0])).max() < 1e-12
+
+
+def test_purify_is_canonical_form_rescaling():
+    rng = np.random.default_rng(0)
+    g = si.random_states(5, 1, seed=1)[0]
+    x = g + 0.05 * _rand_skew(10, rng)
+    p = sgs.purify(x)
+    assert np.abs(p @ p + np.eye(10)).max() < 1e-13
+    # polar factor: p^T x is symmetric positive definite
+    s = p.T @ x
+    assert np.abs(s - s.T).max() < 1e-12 and np.linalg.eigvalsh(0.5 * (s + s.T)).min() > 0
+
+
+def test_reference_state_choice_does_not_change_physics():
+    ham = si.anderson(1, 1.3, 0.7)
+    g = si.random_states(ham.N, 3, seed=4)
+    r1 = sgs.step(ham, g, 0.05)
+    perm = [2, 0, 1]
+    r2 = sgs.step(ham, g[perm], 0.05)
+    assert r1.E == pytest.approx(r2.E, abs=1e-13)
+    assert np.abs(r1.gammas[perm] - r2.gammas).max() < 1e-12
+
+
+# ------------------------------------------------------- whole-loop checks
+
+def test_tiny_system_reaches_exact_ground_state():
+    N, terms = si.anderson_terms(1, 1.3, 0.7)
+    ham = si.anderson(1, 1.3, 0.7)
+    e_ed = ed.even_sector_ground_energy(N, terms)
+    _, es = sgs.run(ham, si.random_states(N, 3, seed=5), 0.05, 300)
+    assert np.all(np.diff(es) <= 1e-12)
+    assert es[-1] == pytest.approx(e_ed, abs=1e-10)
+
+
+def test_free_fermion_closed_form():
+    # U = 0, R = 1: E -> -Tr sqrt(A^T A) + e0, Gamma -> polar(A) (even parity here)
+    ham = si.anderson(3, 0.0, 0.5)
+    s = np.linalg.svd(ham.A, compute_uv=False)
+    e_exact = -s.sum() + ham.e0
+    polarA = sgs.purify(ham.A)
+    assert pfaffian(polarA) == pytest.approx(1.0)
+    g, es = sgs.run(ham, si.random_states(ham.N, 1, seed=0), 0.1, 400)
+    assert es[-1] == pytest.approx(e_exact, abs=1e-9)
+    assert np.abs(g[0] - polarA).max() < 1e-6
+
+
+def test_variational_bound_and_monotone_descent_c1_size():
+    # N = 16 modes (L = 7): E_k >= E_ED(even) and non-increasing
+    N, terms = si.anderson_terms(7, 1.0, 0.5)
+    ham = si.anderson(7, 1.0, 0.5)
+    e_ed = ed.even_sector_ground_energy(N, terms)
+    _, es = sgs.run(ham, si.random_states(N, 4, seed=0), 0.05, 8)
+    assert np.all(es >= e_ed - 1e-12)
+    assert np.all(np.diff(es) <= 1e-12)
+
+
+# ------------------------------------------------------------- observables
+
+def test_observables_match_bruteforce(tiny):
+    ham, g, vecs = tiny
+    N = ham.N
+    E, lam, tab = sgs.energy(ham, g)
+    psi = np.stack(vecs, 1) @ lam
+    poly = si.spin_dot_poly((0, 1), (2, 3))
+    ref = np.vdot(psi, fock.majorana_poly_operator(N, poly) @ psi)
+    assert abs(ob.expectation(g, lam, tab.G, poly) - ref) < 1e-13
+    for NA in (1, 2, 3):
+        rho = np.outer(psi, psi.conj()).reshape(2 ** NA, 2 ** (N - NA), 2 ** NA, 2 ** (N - NA))
+        rA = np.einsum("ajbj->ab", rho)
+        assert ob.renyi2(g, lam, tab.G, 2 * NA) == pytest.approx(-math.log(np.trace(rA @ rA).real), abs=1e-12)
+
+
+def test_integrated_correlation_sum_rule_for_singlet():
+    # Sigma(L-1) = 0 when the total spin vanishes: check on the exact singlet
+    N, terms = si.anderson_terms(1, 1.3, 0.7)
+    ham = si.anderson(1, 1.3, 0.7)
+    g, _ = sgs.run(ham, si.random_states(N, 3, seed=5), 0.05, 300)
+    E, lam, tab = sgs.energy(ham, g)
+    C = np.array([ob.expectation(g, lam, tab.G, si.spin_dot_poly((0, 1), (2 * r, 2 * r + 1))).real
+                  for r in range(2)])
+    assert ob.integrated_correlation(C)[-1] == pytest.approx(0.0, abs=1e-9)
