@@ -1,0 +1,180 @@
+/*
+ * sgs.h -- C ABI of the MI355X library for one imaginary-time step of the
+ * superposition-of-Gaussians (SGS) variational method of Boutin & Bauer,
+ * "Quantum impurity models using superpositions of fermionic Gaussian
+ * states: practical methods and applications" (arXiv:2105.01088).
+ *
+ * The library computes, on one GPU and entirely in its own HIP kernels:
+ *   - for every pair (a,b) of the R Gaussian states of the ansatz (Eq. Ansatz),
+ *     the overlap G_ab = <phi_a|phi_b> as log-magnitude and phase in the
+ *     reference gauge <phi_0|phi_mu> > 0 (Sec. II.B), the transition matrix
+ *     Delta^{ba} (Eq. def-delta-matrix) and the Hamiltonian element
+ *     h_ab = <phi_a|H|phi_b> by generalized Wick contraction (Sec. III.B);
+ *   - the R x R generalized eigenproblem h lambda = E G lambda (Eq. eigLambda);
+ *   - the covariance-matrix force of Eq. (EOM-Gamma3), the first-order step of
+ *     Eq. (RKstep) and the return to a pure state through the canonical form of
+ *     Eq. (CM-normal-form) (every lambda_j rescaled to unit modulus).
+ *
+ * Conventions.  n = 2N Majoranas c_0..c_{n-1}; mode j is
+ * a_j = (c_{2j} + i c_{2j+1})/2.  A covariance matrix (Eq. CMdef) is a real
+ * skew n x n matrix with Gamma^2 = -1, stored row-major in float64.
+ * H = e0 + i sum_{k,l} A_kl c_k c_l + sum_q u_q c_{q0} c_{q1} c_{q2} c_{q3}
+ * with A real skew (both index orders summed, Sec. II.A) and quartic words
+ * q0 < q1 < q2 < q3 (u = 24 U_{q0 q1 q2 q3} for the antisymmetric U of Sec. II.A).
+ * Complex numbers are interleaved (re, im) float64 pairs.
+ *
+ * Ownership.  The caller owns every buffer.  Device buffers (covariance
+ * matrices, workspace, outputs) must stay valid until sgs_destroy; the context
+ * keeps non-owning pointers to them.  Host arrays in sgs_problem are read
+ * during sgs_init only.  The library never allocates device memory.
+ *
+ * Asynchrony.  Every call enqueues work on the stream given to sgs_init and
+ * returns without waiting; device outputs are valid once that stream has
+ * been synchronized.  Numerical failures found on the device (a singular pair
+ * matrix, a non-positive Gram matrix, a purification that did not converge)
+ * are recorded in a device status word that sgs_status reads.
+ *
+ * Errors.  Every int-returning call returns SGS_OK (0) or a negative code;
+ * sgs_strerror gives a message.  Nothing aborts or throws across this ABI.
+ */
+#ifndef SGS_H
+#define SGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SGS_OK 0
+#define SGS_EINVAL (-1)    /* bad argument: null pointer, size, index, option */
+#define SGS_ENOTSKEW (-2)  /* an input covariance matrix is not skew-symmetric */
+#define SGS_ENOTPURE (-3)  /* an input covariance matrix violates Gamma^2 = -1 */
+#define SGS_EPARITY (-4)   /* reserved: odd-parity input (Pf Gamma = -1)        */
+#define SGS_ESINGULAR (-5) /* Gamma_a + Gamma_b singular, or G not positive     */
+#define SGS_ENOCONV (-6)   /* purification or eigen-solve did not converge      */
+#define SGS_EHIP (-7)      /* a HIP runtime call failed                         */
+#define SGS_ESTATE (-8)    /* call order: e.g. sgs_energy before any evaluation */
+#define SGS_EWORKSPACE (-9)/* workspace smaller than sgs_workspace_bytes        */
+
+/* sgs_options.precision */
+#define SGS_FP64 0          /* every stage in float64                          */
+#define SGS_FP32_REFINE 1   /* pair inverses and force GEMMs on float32 MFMA,  */
+                            /* won back by float64 iterative refinement;      */
+                            /* overlaps, eigen-solve and purification stay    */
+                            /* float64                                        */
+/* sgs_options.weight: the scalar c_mu of Eq. (Bmu) (Sec. III.A) */
+#define SGS_W_PRINTED 0     /* c_mu = 1 / (lambda_mu lambda~_mu^*)             */
+#define SGS_W_UNIT 1        /* c_mu = lambda~_mu lambda_mu^* / |lambda~_mu lambda_mu| */
+
+/* sgs_observables kinds */
+#define SGS_OBS_POLY 1      /* <psi| O |psi> for Majorana polynomials O        */
+#define SGS_OBS_RENYI2 2    /* S_2 = -ln Tr rho_A^2, Eq. (S2_SGS)              */
+
+typedef struct sgs_ctx sgs_ctx; /* opaque */
+
+/* One impurity problem (Sec. II.A).  Host pointers, read by sgs_init only. */
+typedef struct {
+  int32_t N;             /* fermionic modes, n = 2N Majoranas, 2 <= N <= 4096  */
+  int32_t R;             /* rank of the ansatz, 1 <= R <= 32                   */
+  const double* A;       /* n*n row-major, real skew (checked)                 */
+  int32_t nq;            /* number of quartic words, 0 <= nq <= 256            */
+  const int32_t* q_idx;  /* nq*4 Majorana indices, each row strictly increasing*/
+  const double* q_val;   /* nq coefficients u_q                                */
+  double e0;             /* constant energy offset                             */
+} sgs_problem;
+
+typedef struct {
+  int32_t precision;       /* SGS_FP64 (default) or SGS_FP32_REFINE            */
+  int32_t weight;          /* SGS_W_PRINTED (default) or SGS_W_UNIT            */
+  double g_rel_threshold;  /* canonical orthogonalization: eigenvectors of G   */
+                           /* below this fraction of its largest eigenvalue are*/
+                           /* dropped (default 1e-12)                          */
+  double purify_tol;       /* max |X^2 + 1| accepted after purification       */
+                           /* (default 1e-12)                                  */
+  int32_t purify_iters;    /* Newton-Schulz polar iterations (default 5)       */
+  int32_t refine_iters;    /* float64 refinement sweeps on the FP32 path (2)  */
+} sgs_options;
+
+/* Fill *opt with the defaults listed above. */
+void sgs_default_options(sgs_options* opt);
+
+/* Device workspace, in bytes, that sgs_init needs for these problems.
+ * probs: nprob problems (host).  Returns SGS_OK or SGS_EINVAL. */
+int sgs_workspace_bytes(const sgs_problem* probs, int32_t nprob,
+                        const sgs_options* opt, size_t* bytes);
+
+/* Create a context.
+ *   probs, nprob : the problems (host, read now; 1 <= nprob <= 1024)
+ *   gamma        : device float64 buffer holding, problem after problem and
+ *                  state after state, the R_p covariance matrices (n_p*n_p
+ *                  row-major each): sum_p R_p n_p^2 doubles.  Read by every
+ *                  evaluation and overwritten in place by sgs_step.  Each
+ *                  matrix must be skew with |Gamma^2 + 1| <= 1e-10 (checked
+ *                  here, synchronously).
+ *   workspace    : device buffer of at least sgs_workspace_bytes, 256-byte
+ *                  aligned, owned by the caller.
+ *   opt          : NULL for defaults.
+ *   stream       : hipStream_t to enqueue on (NULL = the default stream).
+ * On success *out holds the context.  Errors: SGS_EINVAL, SGS_ENOTSKEW,
+ * SGS_ENOTPURE, SGS_EWORKSPACE, SGS_EHIP. */
+int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob,
+             double* gamma, void* workspace, size_t ws_bytes,
+             const sgs_options* opt, void* stream);
+
+/* Overlaps and Hamiltonian elements of every pair, for the current states
+ * (Secs. II.B, II.C, III.B).  Device outputs, problem after problem, R_p*R_p
+ * entries each, row-major in (a, b):
+ *   log_abs_G[a*R+b] = ln|<phi_a|phi_b>|       (0 on the diagonal)
+ *   arg_G[a*R+b]     = arg <phi_a|phi_b>       (gauge <phi_0|phi_mu> > 0)
+ *   eps[2*(a*R+b)+{0,1}] = h_ab / G_ab         (complex, interleaved)
+ * Any output may be NULL.  Errors: SGS_EINVAL. */
+int sgs_pair_eval(sgs_ctx* ctx, double* log_abs_G, double* arg_G, double* eps);
+
+/* Advance every problem by nsteps imaginary-time steps of size dtau
+ * (Sec. III.C, App. A).  energies (device, may be NULL): nsteps*nprob
+ * doubles, energies[k*nprob+p] = E of the states entering step k of problem p
+ * (lowest root of Eq. eigLambda).  gamma is overwritten with the new states.
+ * Errors: SGS_EINVAL. */
+int sgs_step(sgs_ctx* ctx, double dtau, int32_t nsteps, double* energies);
+
+/* Energy and amplitudes of the current states (Eq. eigLambda).
+ *   E      : device, nprob doubles
+ *   lambda : device complex (interleaved), sum_p R_p entries, or NULL;
+ *            normalized lambda^dag G lambda = 1, global phase arbitrary.
+ * Errors: SGS_EINVAL. */
+int sgs_energy(sgs_ctx* ctx, double* E, double* lambda);
+
+/* Observables of the current SGS state of one problem.
+ *   SGS_OBS_POLY  : expectation values <psi|O_t|psi> of npoly Majorana
+ *                   polynomials (Sec. IV.B, Eq. Cr, uses this for S(0).S(r)).
+ *                   iargs = {problem, npoly, nterm, then nterm rows of
+ *                   (poly_index, m, k0, k1, k2, k3)} with m in {0, 2, 4}
+ *                   distinct increasing Majorana indices (unused = -1);
+ *                   dargs = 2*nterm doubles, complex coefficients;
+ *                   out (device) = 2*npoly doubles, complex results.
+ *   SGS_OBS_RENYI2: iargs = {problem, nA} with nA even, the subsystem being
+ *                   Majoranas 0..nA-1 (nA <= 64); dargs unused;
+ *                   out (device) = 1 double, S_2 (Eq. S2_SGS, App. B).
+ * Errors: SGS_EINVAL. */
+int sgs_observables(sgs_ctx* ctx, int32_t kind, const int32_t* iargs,
+                    int32_t niargs, const double* dargs, int32_t ndargs,
+                    double* out);
+
+/* Wait for the context's stream and return the device status word:
+ * SGS_OK, SGS_ESINGULAR or SGS_ENOCONV (first failure since the last call;
+ * reading it clears it), or SGS_EHIP. */
+int sgs_status(sgs_ctx* ctx);
+
+/* Release host-side state.  Device buffers stay owned by the caller. */
+void sgs_destroy(sgs_ctx* ctx);
+
+/* Static message for an error code. */
+const char* sgs_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGS_H */

@@ -67,17 +67,31 @@ def triple_product_schur(gr: np.ndarray, ga: np.ndarray, gb: np.ndarray) -> Tupl
 
 def overlap_table(gammas: np.ndarray, use_direct: bool = False) -> Tuple[np.ndarray, np.ndarray]:
     """(log|G|, arg G) for the Gram matrix G_ab = <phi_a|phi_b>, gauge <phi_0|phi_mu> > 0."""
-    R = gammas.shape[0]
+    R, n, _ = gammas.shape
+    N = n // 2
     logabs = np.zeros((R, R))
     arg = np.zeros((R, R))
     for a in range(R):
         for b in range(a + 1, R):
             logabs[a, b] = logabs[b, a] = log_abs_overlap(gammas[a], gammas[b])
-    tp = triple_product_direct if use_direct else triple_product_schur
+    g0 = gammas[0]
+    I = np.eye(n)
+    if not use_direct:
+        # factors of the Schur-reduced triple product that depend on (0, a) only
+        _, p0 = pfaffian_log(1j * g0)
+        pa = {}
+        xa = {}
+        for a in range(1, R):
+            _, pa[a] = pfaffian_log(1j * (gammas[a] + g0))
+            xa[a] = (I - 1j * g0) @ np.linalg.inv(gammas[a] + g0) @ (I + 1j * g0)
     for a in range(1, R):
         for b in range(a + 1, R):
             # <0|a><a|b><b|0> with <0|a>, <b|0> real positive: arg G_ab = arg T
-            _, ph = tp(gammas[0], gammas[a], gammas[b])
+            if use_direct:
+                _, ph = triple_product_direct(g0, gammas[a], gammas[b])
+            else:
+                _, pc = pfaffian_log(1j * (gammas[b] + g0) - 1j * xa[a])
+                ph = p0 * pa[a] * pc * (1j ** (N % 4))
             th = float(np.angle(ph))
             arg[a, b] = th
             arg[b, a] = -th

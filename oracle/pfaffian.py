@@ -23,6 +23,7 @@ import math
 from typing import Tuple
 
 import numpy as np
+from scipy.linalg import blas
 
 
 def pfaffian_expand(a: np.ndarray) -> complex:
@@ -43,7 +44,9 @@ def pfaffian_expand(a: np.ndarray) -> complex:
 
 def pfaffian_log(a: np.ndarray) -> Tuple[float, complex]:
     """Return (log|Pf(a)|, Pf(a)/|Pf(a)|); (-inf, 0) for a singular matrix."""
-    m = np.array(a, dtype=complex if np.iscomplexobj(a) else float, copy=True)
+    cplx = np.iscomplexobj(a)
+    m = np.array(a, dtype=complex if cplx else float, copy=True, order="C")
+    geru = blas.zgeru if cplx else blas.dger
     n = m.shape[0]
     if n % 2:
         return -math.inf, 0.0
@@ -51,8 +54,7 @@ def pfaffian_log(a: np.ndarray) -> Tuple[float, complex]:
     phase: complex = 1.0
     for k in range(0, n - 1, 2):
         # pivot: largest |m[i, k]| for i > k, brought to row/col k+1
-        col = np.abs(m[k + 1:, k])
-        p = k + 1 + int(np.argmax(col))
+        p = k + 1 + int(np.argmax(np.abs(m[k + 1:, k])))
         if p != k + 1:
             m[[k + 1, p], :] = m[[p, k + 1], :]
             m[:, [k + 1, p]] = m[:, [p, k + 1]]
@@ -63,11 +65,17 @@ def pfaffian_log(a: np.ndarray) -> Tuple[float, complex]:
         logabs += math.log(abs(piv))
         phase *= piv / abs(piv)
         if k + 2 < n:
-            b0 = m[k, k + 2:].copy()      # row k of the trailing block
-            b1 = m[k + 1, k + 2:].copy()  # row k+1
-            # D + B^T P^{-1} B with P^{-1} = [[0, -1/a], [1/a, 0]]
-            upd = (np.outer(b1, b0) - np.outer(b0, b1)) / piv
-            m[k + 2:, k + 2:] += upd
+            # trailing block D + B^T P^{-1} B, P^{-1} = [[0, -1/a], [1/a, 0]]:
+            # D += (b1 b0^T - b0 b1^T) / a, with b0 = row k, b1 = row k+1;
+            # applied as two in-place BLAS rank-1 updates of the trailing rows
+            # (columns left of k+2 receive zeros).
+            b0 = np.zeros(n, dtype=m.dtype)
+            b1 = np.zeros(n, dtype=m.dtype)
+            b0[k + 2:] = m[k, k + 2:]
+            b1[k + 2:] = m[k + 1, k + 2:]
+            rows = m[k + 2:, :].T  # column-major view of rows k+2.., updated in place
+            geru(1.0 / piv, b0, b1[k + 2:], a=rows, overwrite_a=1)
+            geru(-1.0 / piv, b1, b0[k + 2:], a=rows, overwrite_a=1)
     return logabs, phase
 
 

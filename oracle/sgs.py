@@ -26,6 +26,7 @@ from dataclasses import dataclass
 from typing import List, Optional
 
 import numpy as np
+import scipy.sparse as sparse
 
 from .gaussian import delta, fock_matrix, overlap_table, poly_value, quartic_tensor
 
@@ -87,17 +88,20 @@ def forces(ham, gammas: np.ndarray, tab: PairTables, E: float, lam: np.ndarray,
     qt = quartic_tensor(ham)
     out = np.zeros((R, n, n))
     for mu in range(R):
-        D = [gammas[mu] if b == mu else delta(gammas[b], gammas[mu]) for b in range(R)]  # Delta^{b mu}
+        D = np.stack([gammas[mu] if b == mu else delta(gammas[b], gammas[mu])
+                      for b in range(R)])  # Delta^{b mu}
+        # sum_g G_{mu g} (G^-1 h)_{g b} Delta^{g mu} for every b at once
+        K = G[mu][:, None] * Ginv_h  # K[g, b]
+        norm_terms = np.tensordot(K.T, D, axes=(1, 0))
         acc = np.zeros((n, n), dtype=complex)
         for b in range(R):
-            F = fock_matrix(ham, D[b], qt)
-            DF = D[b] @ F
+            F = sparse.csr_matrix(fock_matrix(ham, D[b], qt))
+            DF = (F.T @ D[b].T).T   # D F (F sparse)
             FD = F @ D[b]
             term = (2j * G[mu, b] * (DF - FD)
-                    + 2.0 * G[mu, b] * (DF @ D[b] + F)
-                    - h[mu, b] * D[b])
-            for g in range(R):
-                term = term + G[mu, g] * Ginv_h[g, b] * D[g]
+                    + 2.0 * G[mu, b] * (DF @ D[b] + F.toarray())
+                    - h[mu, b] * D[b]
+                    + norm_terms[b])
             acc += lam[b] * np.conj(lamt[mu]) * c[mu] * term
         out[mu] = (acc + acc.conj()).real
     return out

@@ -1,0 +1,207 @@
+"""ctypes binding of libsgs.so: argument marshalling only.
+
+Device memory and the stream come from PyTorch; every computation runs in the
+library's HIP kernels.  Names follow include/sgs.h.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_size_t, c_void_p
+from typing import Iterable, List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsgs.so")
+
+SGS_FP64 = 0
+SGS_FP32_REFINE = 1
+SGS_W_PRINTED = 0
+SGS_W_UNIT = 1
+SGS_OBS_POLY = 1
+SGS_OBS_RENYI2 = 2
+
+
+class SGSError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {code} ({_strerror(code)})")
+
+
+class sgs_problem(ctypes.Structure):
+    _fields_ = [("N", c_int32), ("R", c_int32), ("A", POINTER(c_double)), ("nq", c_int32),
+                ("q_idx", POINTER(c_int32)), ("q_val", POINTER(c_double)), ("e0", c_double)]
+
+
+class sgs_options(ctypes.Structure):
+    _fields_ = [("precision", c_int32), ("weight", c_int32), ("g_rel_threshold", c_double),
+                ("purify_tol", c_double), ("purify_iters", c_int32), ("refine_iters", c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsgs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2105_01088_amd.build`")
+    lib = ctypes.CDLL(path)
+    lib.sgs_default_options.argtypes = [POINTER(sgs_options)]
+    lib.sgs_default_options.restype = None
+    lib.sgs_workspace_bytes.argtypes = [POINTER(sgs_problem), c_int32, POINTER(sgs_options), POINTER(c_size_t)]
+    lib.sgs_init.argtypes = [POINTER(c_void_p), POINTER(sgs_problem), c_int32, c_void_p, c_void_p, c_size_t,
+                             POINTER(sgs_options), c_void_p]
+    lib.sgs_pair_eval.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.sgs_step.argtypes = [c_void_p, c_double, c_int32, c_void_p]
+    lib.sgs_energy.argtypes = [c_void_p, c_void_p, c_void_p]
+    lib.sgs_observables.argtypes = [c_void_p, c_int32, POINTER(c_int32), c_int32, POINTER(c_double), c_int32,
+                                    c_void_p]
+    lib.sgs_status.argtypes = [c_void_p]
+    lib.sgs_destroy.argtypes = [c_void_p]
+    lib.sgs_destroy.restype = None
+    lib.sgs_strerror.argtypes = [c_int32]
+    lib.sgs_strerror.restype = ctypes.c_char_p
+    for f in ("sgs_workspace_bytes", "sgs_init", "sgs_pair_eval", "sgs_step", "sgs_energy",
+              "sgs_observables", "sgs_status"):
+        getattr(lib, f).restype = c_int32
+    _lib = lib
+    return lib
+
+
+def _strerror(code: int) -> str:
+    try:
+        return load_library().sgs_strerror(code).decode()
+    except Exception:  # pragma: no cover
+        return "?"
+
+
+def default_options(**kw) -> sgs_options:
+    o = sgs_options()
+    load_library().sgs_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise SGSError(rc, what)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class _HostProblem:
+    """Host arrays of one problem kept alive while the C struct points at them."""
+
+    def __init__(self, ham, R: int):
+        self.A = np.ascontiguousarray(ham.A, dtype=np.float64)
+        self.q_idx = np.ascontiguousarray(np.asarray(ham.quartic_idx, dtype=np.int32).reshape(-1, 4))
+        self.q_val = np.ascontiguousarray(np.asarray(ham.quartic_val, dtype=np.float64).reshape(-1))
+        self.s = sgs_problem()
+        self.s.N = int(ham.N)
+        self.s.R = int(R)
+        self.s.A = self.A.ctypes.data_as(POINTER(c_double))
+        self.s.nq = int(self.q_val.shape[0])
+        self.s.q_idx = self.q_idx.ctypes.data_as(POINTER(c_int32))
+        self.s.q_val = self.q_val.ctypes.data_as(POINTER(c_double))
+        self.s.e0 = float(ham.e0)
+
+
+class SGS:
+    """One library context over nprob problems.
+
+    hams   : objects with N, A, quartic_idx, quartic_val, e0 (Majorana form)
+    gammas : list of (R_p, n_p, n_p) float64 tensors or arrays; copied into one
+             device buffer that the library updates in place.
+    """
+
+    def __init__(self, hams: Sequence, gammas: Sequence, options: Optional[sgs_options] = None,
+                 device: str = "cuda:0", stream=None):
+        import torch
+
+        lib = load_library()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.hams = list(hams)
+        self.R = [int(g.shape[0]) for g in gammas]
+        self.n = [int(g.shape[1]) for g in gammas]
+        self.nprob = len(self.hams)
+        self._host = [_HostProblem(h, r) for h, r in zip(self.hams, self.R)]
+        arr = (sgs_problem * self.nprob)(*[h.s for h in self._host])
+        self._arr = arr
+        self.options = options if options is not None else default_options()
+        nbytes = c_size_t(0)
+        _check(lib.sgs_workspace_bytes(arr, self.nprob, ctypes.byref(self.options), ctypes.byref(nbytes)),
+               "sgs_workspace_bytes")
+        self.ws_bytes = int(nbytes.value)
+        self.workspace = torch.empty(self.ws_bytes // 8 + 64, dtype=torch.float64, device=self.device)
+        ws_ptr = (self.workspace.data_ptr() + 255) & ~255
+        flat = [torch.as_tensor(np.asarray(g) if not isinstance(g, torch.Tensor) else g, dtype=torch.float64)
+                .reshape(-1) for g in gammas]
+        self.gamma = torch.cat(flat).to(self.device).contiguous()
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = c_void_p()
+        _check(lib.sgs_init(ctypes.byref(ctx), arr, self.nprob, self.gamma.data_ptr(), ws_ptr,
+                            self.ws_bytes + 0, ctypes.byref(self.options), self.stream.cuda_stream),
+               "sgs_init")
+        self.ctx = ctx
+        self.lib = lib
+        self._offsets = np.concatenate([[0], np.cumsum([r * n * n for r, n in zip(self.R, self.n)])])
+
+    # -- views ------------------------------------------------------------
+    def gammas(self, p: int = 0):
+        o = int(self._offsets[p])
+        return self.gamma[o:o + self.R[p] * self.n[p] ** 2].view(self.R[p], self.n[p], self.n[p])
+
+    # -- calls ------------------------------------------------------------
+    def pair_eval(self):
+        torch = self.torch
+        tot = sum(r * r for r in self.R)
+        la = torch.empty(tot, dtype=torch.float64, device=self.device)
+        ar = torch.empty(tot, dtype=torch.float64, device=self.device)
+        ep = torch.empty(2 * tot, dtype=torch.float64, device=self.device)
+        _check(self.lib.sgs_pair_eval(self.ctx, la.data_ptr(), ar.data_ptr(), ep.data_ptr()), "sgs_pair_eval")
+        return la, ar, ep
+
+    def step(self, dtau: float, nsteps: int = 1, energies: bool = True):
+        torch = self.torch
+        e = torch.empty(max(1, nsteps * self.nprob), dtype=torch.float64, device=self.device) if energies else None
+        _check(self.lib.sgs_step(self.ctx, float(dtau), int(nsteps), _ptr(e)), "sgs_step")
+        return e
+
+    def energy(self):
+        torch = self.torch
+        E = torch.empty(self.nprob, dtype=torch.float64, device=self.device)
+        lam = torch.empty(2 * sum(self.R), dtype=torch.float64, device=self.device)
+        _check(self.lib.sgs_energy(self.ctx, E.data_ptr(), lam.data_ptr()), "sgs_energy")
+        return E, lam
+
+    def observables(self, kind: int, iargs: Sequence[int], dargs: Sequence[float], nout: int):
+        torch = self.torch
+        ia = (c_int32 * max(1, len(iargs)))(*[int(x) for x in iargs])
+        da = (c_double * max(1, len(dargs)))(*[float(x) for x in dargs])
+        out = torch.empty(max(1, nout), dtype=torch.float64, device=self.device)
+        _check(self.lib.sgs_observables(self.ctx, int(kind), ia, len(iargs), da, len(dargs), out.data_ptr()),
+               "sgs_observables")
+        return out
+
+    def status(self) -> int:
+        return int(self.lib.sgs_status(self.ctx))
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self.lib.sgs_destroy(self.ctx)
+            self.ctx = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

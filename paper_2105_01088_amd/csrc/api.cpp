@@ -1,0 +1,644 @@
+// Host side of the C ABI declared in include/sgs.h: validation, workspace
+// layout (the caller's buffer is carved up; nothing is allocated), the static
+// tables every step reuses (pair lists, sparse A, GEMM job tables, force
+// descriptors), and the order of the device stages of one imaginary-time step.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "sgs_internal.h"
+#include "../../include/sgs.h"
+
+using namespace sgs;
+
+namespace {
+
+constexpr int GJ_NB_MAX = 32;
+constexpr int PF_NBH = 16;
+
+struct Arena {
+  char* base;
+  size_t off;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct JobTable {
+  GemmJob* dev = nullptr;
+  std::vector<GemmJob> host;
+  int ntiles = 0;
+  bool cplx = false;
+};
+
+struct Prob {
+  int N = 0, n = 0, R = 0, P = 0, Q = 0, M = 0, nq = 0, nnz_up = 0, nnz = 0;
+  int gj_nb = 16;
+  double e0 = 0.0;
+  double* gam = nullptr;
+  // dense work
+  double *W, *Di, *Y, *Yd, *T1, *Xr, *Cm, *UV, *RM, *gjE, *gjB, *dG, *nsX0, *nsX1, *nsQ, *Adense;
+  // small
+  double *pfacc, *logdet, *eps, *Fc, *coef, *Gt, *ht, *lam, *lamt, *E, *tab_la, *tab_arg, *tab_eps;
+  double *up_v, *colval, *q_val;
+  int *piv, *pa, *pb, *qa, *qb, *pidx, *qidx, *up_k, *up_l, *colptr, *rowidx, *imp, *impos, *q_idx, *q_loc;
+  unsigned long long* resid;
+  ForceTerm* terms;
+  JobTable jdi, jt1, jxr, jnsq[2], jnsx[2], jval;
+  std::vector<JobTable> jgj, jpf;
+  std::vector<int> gj_k, gj_b, pf_p0;
+  long long uvstride = 0, uv_im = 0;
+};
+
+int gemm_tiles(int M, int N) { return ((M + 63) / 64) * ((N + 63) / 64); }
+
+void add_job(JobTable& t, GemmJob j) {
+  j.tiles_n = (j.N + 63) / 64;
+  j.tile_begin = t.ntiles;
+  t.ntiles += gemm_tiles(j.M, j.N);
+  t.host.push_back(j);
+}
+
+GemmJob job(const double* A, int lda, int ta, const double* B, int ldb, int tb, const double* C, int ldc,
+            double* D, int ldd, int M, int N, int K, double alpha, double beta, double diag = 0.0) {
+  GemmJob j;
+  std::memset(&j, 0, sizeof(j));
+  j.A = A; j.B = B; j.C = C; j.D = D;
+  j.lda = lda; j.ldb = ldb; j.ldc = ldc; j.ldd = ldd;
+  j.ta = ta; j.tb = tb;
+  j.M = M; j.N = N; j.K = K;
+  j.alpha = alpha; j.beta = beta; j.diag = diag;
+  return j;
+}
+
+}  // namespace
+
+struct sgs_ctx {
+  std::vector<Prob> pr;
+  hipStream_t s = nullptr;
+  sgs_options opt;
+  int* status = nullptr;
+  int lds_max = 65536;
+  bool evaluated = false;
+};
+
+// ---------------------------------------------------------------------------
+// layout
+// ---------------------------------------------------------------------------
+static int check_problem(const sgs_problem& p) {
+  if (p.N < 1 || p.N > 4096 || p.R < 1 || p.R > 32 || !p.A || p.nq < 0 || p.nq > 256) return SGS_EINVAL;
+  if (p.nq > 0 && (!p.q_idx || !p.q_val)) return SGS_EINVAL;
+  const int n = 2 * p.N;
+  for (int q = 0; q < p.nq; ++q) {
+    const int* x = p.q_idx + 4 * q;
+    for (int t = 0; t < 4; ++t)
+      if (x[t] < 0 || x[t] >= n || (t > 0 && x[t] <= x[t - 1])) return SGS_EINVAL;
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j)
+      if (p.A[(size_t)i * n + j] != -p.A[(size_t)j * n + i]) return SGS_EINVAL;
+  return SGS_OK;
+}
+
+static int impurity_count(const sgs_problem& p) {
+  std::vector<int> v(p.q_idx, p.q_idx + 4 * p.nq);
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+  return (int)v.size();
+}
+
+static int nnz_count(const sgs_problem& p, int* up) {
+  const int n = 2 * p.N;
+  int nz = 0, u = 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      if (p.A[(size_t)i * n + j] != 0.0) { ++nz; if (j > i) ++u; }
+  *up = u;
+  return nz;
+}
+
+static void carve(Prob& q, Arena& ar) {
+  const long long nn = (long long)q.n * q.n;
+  const int R = q.R, P = q.P, Q = q.Q, n = q.n, M = q.M;
+  q.W = ar.take<double>(std::max(1LL, P * nn));
+  q.Di = ar.take<double>(std::max(1LL, P * nn));
+  q.Y = ar.take<double>(std::max(1LL, 2 * P * nn));
+  q.Yd = ar.take<double>(R * nn);
+  q.T1 = ar.take<double>(std::max(1LL, (R - 1) * nn));
+  q.Xr = ar.take<double>(std::max(1LL, (R - 1) * nn));
+  q.Cm = ar.take<double>(std::max(1LL, 2 * Q * nn));
+  q.uvstride = 2LL * n * 2 * PF_NBH;  // planar: re block then im block
+  q.uv_im = (long long)n * 2 * PF_NBH;
+  q.UV = ar.take<double>(std::max(1LL, Q * q.uvstride));
+  q.RM = ar.take<double>(std::max(1LL, Q * q.uvstride));
+  q.gjE = ar.take<double>(std::max(1LL, (long long)P * n * GJ_NB_MAX));
+  q.gjB = ar.take<double>(std::max(1LL, (long long)P * n * GJ_NB_MAX));
+  q.dG = ar.take<double>(R * nn);
+  q.nsX0 = ar.take<double>(R * nn);
+  q.nsX1 = ar.take<double>(R * nn);
+  q.nsQ = ar.take<double>(R * nn);
+  q.Adense = ar.take<double>(nn);
+  q.pfacc = ar.take<double>(std::max(1, 3 * Q));
+  q.logdet = ar.take<double>(std::max(1, P));
+  q.eps = ar.take<double>(2 * (P + R));
+  q.Fc = ar.take<double>(std::max(1, 2 * M * M * (P + R)));
+  q.coef = ar.take<double>(4 * R * R);
+  q.Gt = ar.take<double>(2 * R * R);
+  q.ht = ar.take<double>(2 * R * R);
+  q.lam = ar.take<double>(2 * R);
+  q.lamt = ar.take<double>(2 * R);
+  q.E = ar.take<double>(1);
+  q.tab_la = ar.take<double>(R * R);
+  q.tab_arg = ar.take<double>(R * R);
+  q.tab_eps = ar.take<double>(2 * R * R);
+  q.up_v = ar.take<double>(std::max(1, q.nnz_up));
+  q.colval = ar.take<double>(std::max(1, q.nnz));
+  q.q_val = ar.take<double>(std::max(1, q.nq));
+  q.piv = ar.take<int>(std::max(1LL, (long long)P * n));
+  q.pa = ar.take<int>(std::max(1, P));
+  q.pb = ar.take<int>(std::max(1, P));
+  q.qa = ar.take<int>(std::max(1, Q));
+  q.qb = ar.take<int>(std::max(1, Q));
+  q.pidx = ar.take<int>(R * R);
+  q.qidx = ar.take<int>(R * R);
+  q.up_k = ar.take<int>(std::max(1, q.nnz_up));
+  q.up_l = ar.take<int>(std::max(1, q.nnz_up));
+  q.colptr = ar.take<int>(n + 1);
+  q.rowidx = ar.take<int>(std::max(1, q.nnz));
+  q.imp = ar.take<int>(std::max(1, M));
+  q.impos = ar.take<int>(n);
+  q.q_idx = ar.take<int>(std::max(1, 4 * q.nq));
+  q.q_loc = ar.take<int>(std::max(1, 4 * q.nq));
+  q.resid = ar.take<unsigned long long>(1);
+  q.terms = ar.take<ForceTerm>((size_t)R * R);
+}
+
+static void carve_jobs(Prob& q, Arena& ar) {
+  const int n = q.n;
+  const int ngj = (n + q.gj_nb - 1) / q.gj_nb;
+  q.jgj.assign(ngj, JobTable());
+  for (auto& t : q.jgj) t.dev = ar.take<GemmJob>(std::max(1, q.P));
+  const int npf = (n + 2 * PF_NBH - 1) / (2 * PF_NBH);
+  q.jpf.assign(npf, JobTable());
+  for (auto& t : q.jpf) t.dev = ar.take<GemmJob>(std::max(1, q.Q));
+  q.jdi.dev = ar.take<GemmJob>(std::max(1, q.P));
+  q.jt1.dev = ar.take<GemmJob>(std::max(1, q.R - 1));
+  q.jxr.dev = ar.take<GemmJob>(std::max(1, q.R - 1));
+  for (int k = 0; k < 2; ++k) {
+    q.jnsq[k].dev = ar.take<GemmJob>(q.R);
+    q.jnsx[k].dev = ar.take<GemmJob>(q.R);
+  }
+  q.jval.dev = ar.take<GemmJob>(q.R);
+}
+
+static int pick_gj_nb(int n, int lds_max) {
+  const int cands[4] = {32, 16, 8, 4};
+  for (int b : cands)
+    if (b <= n && gj_panel_lds_bytes(n, 0, b) <= (size_t)lds_max) return b;
+  return std::min(4, n);
+}
+
+static int device_lds_max() {
+  int dev = 0, v = 65536;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 65536;
+  return v;
+}
+
+static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, char* base, int lds_max) {
+  Arena ar{base, 0};
+  ar.take<int>(64);  // status word and spare
+  pr.assign(nprob, Prob());
+  for (int p = 0; p < nprob; ++p) {
+    Prob& q = pr[p];
+    const sgs_problem& sp = probs[p];
+    q.N = sp.N; q.n = 2 * sp.N; q.R = sp.R;
+    q.P = q.R * (q.R - 1) / 2;
+    q.Q = (q.R - 1) * (q.R - 2) / 2;
+    q.nq = sp.nq; q.e0 = sp.e0;
+    q.M = sp.nq > 0 ? impurity_count(sp) : 0;
+    q.nnz = nnz_count(sp, &q.nnz_up);
+    q.gj_nb = pick_gj_nb(q.n, lds_max);
+    carve(q, ar);
+    carve_jobs(q, ar);
+  }
+  return ar.off + 256;
+}
+
+// ---------------------------------------------------------------------------
+// static tables
+// ---------------------------------------------------------------------------
+#define HIPCHK(x)                          \
+  do {                                     \
+    if ((x) != hipSuccess) return SGS_EHIP; \
+  } while (0)
+
+template <class T>
+static hipError_t up(T* dev, const std::vector<T>& host) {
+  if (host.empty()) return hipSuccess;
+  return hipMemcpy(dev, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+static hipError_t upload_jobs(JobTable& t) {
+  if (t.host.empty()) return hipSuccess;
+  return hipMemcpy(t.dev, t.host.data(), t.host.size() * sizeof(GemmJob), hipMemcpyHostToDevice);
+}
+
+static int build_tables(Prob& q, const sgs_problem& sp) {
+  const int n = q.n, R = q.R, P = q.P;
+  const long long nn = (long long)n * n;
+  // pair lists
+  std::vector<int> pa(P), pb(P), pidx(R * R, -1), qa, qb, qidx(R * R, -1);
+  int p = 0;
+  for (int a = 0; a < R; ++a)
+    for (int b = a + 1; b < R; ++b) {
+      pa[p] = a; pb[p] = b; pidx[a * R + b] = pidx[b * R + a] = p; ++p;
+    }
+  for (int a = 1; a < R; ++a)
+    for (int b = a + 1; b < R; ++b) {
+      qidx[a * R + b] = (int)qa.size();
+      qa.push_back(a); qb.push_back(b);
+    }
+  HIPCHK(up(q.pa, pa)); HIPCHK(up(q.pb, pb)); HIPCHK(up(q.pidx, pidx));
+  HIPCHK(up(q.qa, qa)); HIPCHK(up(q.qb, qb)); HIPCHK(up(q.qidx, qidx));
+  // A: dense, upper nonzeros, compressed columns
+  std::vector<double> Ad(sp.A, sp.A + nn);
+  HIPCHK(up(q.Adense, Ad));
+  std::vector<int> uk, ul, colptr(n + 1, 0), rowidx;
+  std::vector<double> uv, colval;
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j)
+      if (Ad[(size_t)i * n + j] != 0.0) { uk.push_back(i); ul.push_back(j); uv.push_back(Ad[(size_t)i * n + j]); }
+  for (int j = 0; j < n; ++j) {
+    colptr[j] = (int)rowidx.size();
+    for (int i = 0; i < n; ++i)
+      if (Ad[(size_t)i * n + j] != 0.0) { rowidx.push_back(i); colval.push_back(Ad[(size_t)i * n + j]); }
+  }
+  colptr[n] = (int)rowidx.size();
+  HIPCHK(up(q.up_k, uk)); HIPCHK(up(q.up_l, ul)); HIPCHK(up(q.up_v, uv));
+  HIPCHK(up(q.colptr, colptr)); HIPCHK(up(q.rowidx, rowidx)); HIPCHK(up(q.colval, colval));
+  // impurity Majoranas
+  std::vector<int> imp(sp.q_idx, sp.q_idx + 4 * sp.nq);
+  std::sort(imp.begin(), imp.end());
+  imp.erase(std::unique(imp.begin(), imp.end()), imp.end());
+  std::vector<int> impos(n, -1), qloc(4 * sp.nq), qidxv(sp.q_idx, sp.q_idx + 4 * sp.nq);
+  for (size_t t = 0; t < imp.size(); ++t) impos[imp[t]] = (int)t;
+  for (int t = 0; t < 4 * sp.nq; ++t) qloc[t] = impos[sp.q_idx[t]];
+  std::vector<double> qv(sp.q_val, sp.q_val + sp.nq);
+  HIPCHK(up(q.imp, imp)); HIPCHK(up(q.impos, impos)); HIPCHK(up(q.q_loc, qloc));
+  HIPCHK(up(q.q_idx, qidxv)); HIPCHK(up(q.q_val, qv));
+
+  // --- GEMM job tables ---
+  // Gauss-Jordan updates: M <- M - E Brow per panel
+  q.gj_k.clear(); q.gj_b.clear();
+  for (int k = 0, t = 0; k < n; k += q.gj_nb, ++t) {
+    const int b = std::min(q.gj_nb, n - k);
+    q.gj_k.push_back(k); q.gj_b.push_back(b);
+    JobTable& jt = q.jgj[t];
+    jt.host.clear(); jt.ntiles = 0;
+    for (int pp = 0; pp < P; ++pp)
+      add_job(jt, job(q.gjE + (long long)pp * n * GJ_NB_MAX, b, 0, q.gjB + (long long)pp * n * GJ_NB_MAX, n, 0,
+                      q.W + pp * nn, n, q.W + pp * nn, n, n, n, b, -1.0, 1.0));
+    HIPCHK(upload_jobs(jt));
+  }
+  // Im Delta^{ba} = 2 Gamma_b W - 1
+  q.jdi.host.clear(); q.jdi.ntiles = 0;
+  for (int pp = 0; pp < P; ++pp)
+    add_job(q.jdi, job(q.gam + (long long)pb[pp] * nn, n, 0, q.W + pp * nn, n, 0, nullptr, n, q.Di + pp * nn, n,
+                       n, n, n, 2.0, 0.0, -1.0));
+  HIPCHK(upload_jobs(q.jdi));
+  // phase matrices: T_a = Gamma_0 W_0a ; Re X_a = T_a Gamma_0 + W_0a
+  q.jt1.host.clear(); q.jt1.ntiles = 0; q.jxr.host.clear(); q.jxr.ntiles = 0;
+  for (int a = 1; a < R; ++a) {
+    const int p0a = pidx[a];
+    add_job(q.jt1, job(q.gam, n, 0, q.W + p0a * nn, n, 0, nullptr, n, q.T1 + (a - 1) * nn, n, n, n, n, 1.0, 0.0));
+    add_job(q.jxr, job(q.T1 + (a - 1) * nn, n, 0, q.gam, n, 0, q.W + p0a * nn, n, q.Xr + (a - 1) * nn, n, n, n, n,
+                       1.0, 1.0));
+  }
+  HIPCHK(upload_jobs(q.jt1)); HIPCHK(upload_jobs(q.jxr));
+  // Pfaffian trailing updates: A22 += [U V] [V -U]^T (complex)
+  q.pf_p0.clear();
+  const int ldu = 2 * PF_NBH;
+  for (int p0 = 0, t = 0; p0 < n; p0 += 2 * PF_NBH, ++t) {
+    q.pf_p0.push_back(p0);
+    JobTable& jt = q.jpf[t];
+    jt.host.clear(); jt.ntiles = 0; jt.cplx = true;
+    const int nsteps = std::min(PF_NBH, (n - p0) / 2);
+    const int pe = p0 + 2 * nsteps, m = n - pe;
+    if (m > 0)
+      for (int qq = 0; qq < q.Q; ++qq) {
+        GemmJob j = job(q.UV + qq * q.uvstride + (long long)pe * ldu, ldu, 0, q.RM + qq * q.uvstride + (long long)pe * ldu,
+                        ldu, 1, q.Cm + qq * 2 * nn + (long long)pe * n + pe, n,
+                        q.Cm + qq * 2 * nn + (long long)pe * n + pe, n, m, m, ldu, 1.0, 1.0);
+        j.a_im = q.uv_im; j.b_im = q.uv_im; j.c_im = nn; j.d_im = nn;
+        add_job(jt, j);
+      }
+    HIPCHK(upload_jobs(jt));
+  }
+  // Newton-Schulz: Q = X X ; X' = 0.5 X Q + 1.5 X (ping-pong)
+  for (int par = 0; par < 2; ++par) {
+    double* Xin = par ? q.nsX1 : q.nsX0;
+    double* Xout = par ? q.nsX0 : q.nsX1;
+    q.jnsq[par].host.clear(); q.jnsq[par].ntiles = 0;
+    q.jnsx[par].host.clear(); q.jnsx[par].ntiles = 0;
+    for (int mu = 0; mu < R; ++mu) {
+      add_job(q.jnsq[par], job(Xin + mu * nn, n, 0, Xin + mu * nn, n, 0, nullptr, n, q.nsQ + mu * nn, n, n, n, n, 1.0, 0.0));
+      add_job(q.jnsx[par], job(Xin + mu * nn, n, 0, q.nsQ + mu * nn, n, 0, Xin + mu * nn, n, Xout + mu * nn, n, n, n, n,
+                               0.5, 1.5));
+    }
+    HIPCHK(upload_jobs(q.jnsq[par])); HIPCHK(upload_jobs(q.jnsx[par]));
+  }
+  // validation: Q = Gamma Gamma
+  q.jval.host.clear(); q.jval.ntiles = 0;
+  for (int mu = 0; mu < R; ++mu)
+    add_job(q.jval, job(q.gam + mu * nn, n, 0, q.gam + mu * nn, n, 0, nullptr, n, q.nsQ + mu * nn, n, n, n, n, 1.0, 0.0));
+  HIPCHK(upload_jobs(q.jval));
+
+  // force descriptors
+  std::vector<ForceTerm> terms((size_t)R * R);
+  const int M = q.M;
+  for (int mu = 0; mu < R; ++mu)
+    for (int b = 0; b < R; ++b) {
+      ForceTerm& t = terms[(size_t)mu * R + b];
+      std::memset(&t, 0, sizeof(t));
+      t.coef = mu * R + b;
+      if (b == mu) {
+        t.Dr = q.gam + mu * nn; t.Di = nullptr;
+        t.Yr = q.Yd + mu * nn; t.Yi = nullptr;
+        t.Fcr = q.Fc + (long long)(P + mu) * 2 * M * M; t.Fci = nullptr;
+        t.dr_scale = 1.0; t.sgn = 1.0;
+      } else {
+        const int pp = pidx[mu * R + b];
+        t.Dr = q.W + pp * nn; t.Di = q.Di + pp * nn;
+        t.Yr = q.Y + pp * 2 * nn; t.Yi = q.Y + pp * 2 * nn + nn;
+        t.Fcr = q.Fc + (long long)pp * 2 * M * M; t.Fci = t.Fcr + M * M;
+        t.dr_scale = -2.0;
+        t.sgn = (mu < b) ? 1.0 : -1.0;  // pair stores Delta^{ba} (a < b); mu = b takes its conjugate
+      }
+    }
+  HIPCHK(up(q.terms, terms));
+  return SGS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stages
+// ---------------------------------------------------------------------------
+static hipError_t run_gemm(const JobTable& t, hipStream_t s) {
+  return launch_gemm(t.dev, (int)t.host.size(), t.ntiles, t.cplx, s);
+}
+
+#define HCHK(x)                               \
+  do {                                        \
+    hipError_t _e = (x);                      \
+    if (_e != hipSuccess) return _e;          \
+  } while (0)
+
+static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o_la, double* o_arg, double* o_eps) {
+  hipStream_t s = c->s;
+  const int n = q.n, P = q.P, R = q.R;
+  const long long nn = (long long)n * n;
+  if (P > 0) {
+    // overlap magnitudes and W = (Gamma_a + Gamma_b)^{-1}
+    HCHK(launch_pair_sum(q.gam, n, q.pa, q.pb, P, q.W, q.logdet, s));
+    for (size_t t = 0; t < q.gj_k.size(); ++t) {
+      HCHK(launch_gj_panel(q.W, nn, P, n, q.gj_k[t], q.gj_b[t], q.gjE, (long long)n * GJ_NB_MAX, q.gjB,
+                           (long long)n * GJ_NB_MAX, q.piv, q.logdet, c->status, s));
+      HCHK(run_gemm(q.jgj[t], s));
+    }
+    HCHK(launch_gj_unscramble(q.W, nn, P, n, q.piv, s));
+    // transition matrices
+    HCHK(run_gemm(q.jdi, s));
+  }
+  // Hamiltonian elements, Fock corrections, Y = Delta F
+  HamDev h{n, q.nnz_up, q.nq, q.M, q.up_k, q.up_l, q.up_v, q.q_idx, q.q_loc, q.q_val, q.e0};
+  HCHK(launch_eps_fock(h, P, R, q.W, q.Di, q.gam, q.pa, q.pb, q.eps, q.Fc, s));
+  SparseA sa{q.colptr, q.rowidx, q.colval, q.imp, q.impos, q.M};
+  HCHK(launch_apply_fock(sa, n, P, R, q.W, q.Di, q.gam, q.Fc, q.Y, q.Yd, s));
+  // phases
+  if (q.Q > 0) {
+    HCHK(run_gemm(q.jt1, s));
+    HCHK(run_gemm(q.jxr, s));
+    HCHK(launch_build_c(n, q.gam, q.T1, q.Xr, q.qa, q.qb, q.Q, q.Cm, s));
+    HCHK(launch_pf_zero(q.UV, q.Q * q.uvstride, s));
+    for (size_t t = 0; t < q.pf_p0.size(); ++t) {
+      HCHK(launch_pf_panel(q.Cm, 2 * nn, q.Q, n, q.pf_p0[t], PF_NBH, q.UV, q.RM, q.uvstride, q.uv_im, q.pfacc,
+                           c->status, s));
+      HCHK(run_gemm(q.jpf[t], s));
+    }
+  }
+  SolveArgs a;
+  a.N = q.N; a.R = R; a.P = P;
+  a.pidx = q.pidx; a.qidx = q.qidx; a.logdet = q.logdet; a.pfacc = q.pfacc; a.eps = q.eps;
+  a.tab_la = o_la ? o_la : q.tab_la;
+  a.tab_arg = o_arg ? o_arg : q.tab_arg;
+  a.tab_eps = o_eps ? o_eps : q.tab_eps;
+  a.Gt = q.Gt; a.ht = q.ht; a.lam = q.lam; a.lamt = q.lamt; a.coef = q.coef; a.E = q.E;
+  a.energy_slot = energy_slot; a.status = c->status;
+  a.g_thr = c->opt.g_rel_threshold;
+  a.weight = c->opt.weight;
+  HCHK(launch_solve(a, s));
+  return hipSuccess;
+}
+
+static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
+  hipStream_t s = c->s;
+  const int n = q.n, R = q.R;
+  const long long nn = (long long)n * n;
+  HCHK(launch_force(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, q.dG, s));
+  HCHK(launch_euler(q.gam, q.dG, dtau, R * nn, q.nsX0, s));
+  int par = 0;
+  for (int it = 0; it < c->opt.purify_iters; ++it) {
+    HCHK(run_gemm(q.jnsq[par], s));
+    if (it == c->opt.purify_iters - 1) HCHK(launch_ns_resid(q.nsQ, n, R * nn, q.resid, s));
+    HCHK(run_gemm(q.jnsx[par], s));
+    par ^= 1;
+  }
+  HCHK(launch_finalize(par ? q.nsX1 : q.nsX0, n, R, q.gam, q.resid, c->opt.purify_tol, c->status, s));
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void sgs_default_options(sgs_options* o) {
+  if (!o) return;
+  o->precision = SGS_FP64;
+  o->weight = SGS_W_PRINTED;
+  o->g_rel_threshold = 1e-12;
+  o->purify_tol = 1e-12;
+  o->purify_iters = 5;
+  o->refine_iters = 2;
+}
+
+static int check_options(const sgs_options& o) {
+  if (o.precision != SGS_FP64 && o.precision != SGS_FP32_REFINE) return SGS_EINVAL;
+  if (o.weight != SGS_W_PRINTED && o.weight != SGS_W_UNIT) return SGS_EINVAL;
+  if (!(o.g_rel_threshold > 0.0 && o.g_rel_threshold < 1.0)) return SGS_EINVAL;
+  if (!(o.purify_tol > 0.0) || o.purify_iters < 1 || o.purify_iters > 64) return SGS_EINVAL;
+  if (o.refine_iters < 0 || o.refine_iters > 16) return SGS_EINVAL;
+  return SGS_OK;
+}
+
+int sgs_workspace_bytes(const sgs_problem* probs, int32_t nprob, const sgs_options* opt, size_t* bytes) {
+  if (!probs || nprob < 1 || nprob > 1024 || !bytes) return SGS_EINVAL;
+  sgs_options o;
+  sgs_default_options(&o);
+  if (opt) o = *opt;
+  int rc = check_options(o);
+  if (rc) return rc;
+  for (int p = 0; p < nprob; ++p)
+    if ((rc = check_problem(probs[p]))) return rc;
+  std::vector<Prob> pr;
+  *bytes = plan(pr, probs, nprob, nullptr, device_lds_max());
+  return SGS_OK;
+}
+
+int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gamma, void* workspace,
+             size_t ws_bytes, const sgs_options* opt, void* stream) {
+  if (!out || !probs || nprob < 1 || nprob > 1024 || !gamma || !workspace) return SGS_EINVAL;
+  if (((uintptr_t)workspace) & 255) return SGS_EINVAL;
+  *out = nullptr;
+  sgs_options o;
+  sgs_default_options(&o);
+  if (opt) o = *opt;
+  int rc = check_options(o);
+  if (rc) return rc;
+  for (int p = 0; p < nprob; ++p)
+    if ((rc = check_problem(probs[p]))) return rc;
+  sgs_ctx* c = new sgs_ctx();
+  c->opt = o;
+  c->s = (hipStream_t)stream;
+  c->lds_max = device_lds_max();
+  const size_t need = plan(c->pr, probs, nprob, (char*)workspace, c->lds_max);
+  if (ws_bytes < need) { delete c; return SGS_EWORKSPACE; }
+  c->status = (int*)workspace;
+  double* g = gamma;
+  for (int p = 0; p < nprob; ++p) {
+    c->pr[p].gam = g;
+    g += (long long)c->pr[p].R * c->pr[p].n * c->pr[p].n;
+  }
+  size_t lds_gj = 0, lds_solve = 0;
+  for (auto& q : c->pr) {
+    lds_gj = std::max(lds_gj, gj_panel_lds_bytes(q.n, 0, q.gj_nb));
+    lds_solve = std::max(lds_solve, solve_lds_bytes(q.R));
+  }
+  if (set_gj_lds_limit(lds_gj) != hipSuccess || set_solve_lds_limit(lds_solve) != hipSuccess) {
+    delete c;
+    return SGS_EHIP;
+  }
+  for (int p = 0; p < nprob; ++p)
+    if ((rc = build_tables(c->pr[p], probs[p]))) { delete c; return rc; }
+  if (hipMemsetAsync(c->status, 0, sizeof(int), c->s) != hipSuccess) { delete c; return SGS_EHIP; }
+  // validate the covariance matrices: skew, Gamma^2 = -1
+  for (auto& q : c->pr) {
+    const long long nn = (long long)q.n * q.n;
+    unsigned long long hv = 0;
+    if (launch_skew_resid(q.gam, q.n, q.R * nn, q.resid, c->s) != hipSuccess ||
+        hipMemcpyAsync(&hv, q.resid, sizeof(hv), hipMemcpyDeviceToHost, c->s) != hipSuccess ||
+        hipStreamSynchronize(c->s) != hipSuccess) { delete c; return SGS_EHIP; }
+    double d;
+    std::memcpy(&d, &hv, sizeof(d));
+    if (!(d <= 1e-12)) { delete c; return SGS_ENOTSKEW; }
+    if (run_gemm(q.jval, c->s) != hipSuccess || launch_ns_resid(q.nsQ, q.n, q.R * nn, q.resid, c->s) != hipSuccess ||
+        hipMemcpyAsync(&hv, q.resid, sizeof(hv), hipMemcpyDeviceToHost, c->s) != hipSuccess ||
+        hipStreamSynchronize(c->s) != hipSuccess) { delete c; return SGS_EHIP; }
+    std::memcpy(&d, &hv, sizeof(d));
+    if (!(d <= 1e-10)) { delete c; return SGS_ENOTPURE; }
+  }
+  *out = c;
+  return SGS_OK;
+}
+
+int sgs_pair_eval(sgs_ctx* c, double* log_abs_G, double* arg_G, double* eps) {
+  if (!c) return SGS_EINVAL;
+  long long off = 0;
+  for (auto& q : c->pr) {
+    const int RR = q.R * q.R;
+    if (pair_stage(c, q, nullptr, log_abs_G ? log_abs_G + off : nullptr, arg_G ? arg_G + off : nullptr,
+                   eps ? eps + 2 * off : nullptr) != hipSuccess)
+      return SGS_EHIP;
+    off += RR;
+  }
+  c->evaluated = true;
+  return SGS_OK;
+}
+
+int sgs_step(sgs_ctx* c, double dtau, int32_t nsteps, double* energies) {
+  if (!c || nsteps < 0 || !std::isfinite(dtau) || dtau <= 0.0) return SGS_EINVAL;
+  const int np = (int)c->pr.size();
+  for (int k = 0; k < nsteps; ++k)
+    for (int p = 0; p < np; ++p) {
+      Prob& q = c->pr[p];
+      if (pair_stage(c, q, energies ? energies + (long long)k * np + p : nullptr, nullptr, nullptr, nullptr) !=
+          hipSuccess)
+        return SGS_EHIP;
+      if (update_stage(c, q, dtau) != hipSuccess) return SGS_EHIP;
+    }
+  if (nsteps > 0) c->evaluated = false;
+  return SGS_OK;
+}
+
+int sgs_energy(sgs_ctx* c, double* E, double* lambda) {
+  if (!c || !E) return SGS_EINVAL;
+  if (!c->evaluated) {
+    for (auto& q : c->pr)
+      if (pair_stage(c, q, nullptr, nullptr, nullptr, nullptr) != hipSuccess) return SGS_EHIP;
+    c->evaluated = true;
+  }
+  long long off = 0;
+  for (size_t p = 0; p < c->pr.size(); ++p) {
+    Prob& q = c->pr[p];
+    if (hipMemcpyAsync(E + p, q.E, sizeof(double), hipMemcpyDeviceToDevice, c->s) != hipSuccess) return SGS_EHIP;
+    if (lambda && hipMemcpyAsync(lambda + 2 * off, q.lam, 2 * q.R * sizeof(double), hipMemcpyDeviceToDevice, c->s) !=
+                      hipSuccess)
+      return SGS_EHIP;
+    off += q.R;
+  }
+  return SGS_OK;
+}
+
+int sgs_observables(sgs_ctx* c, int32_t kind, const int32_t* iargs, int32_t niargs, const double* dargs,
+                    int32_t ndargs, double* out) {
+  (void)iargs; (void)niargs; (void)dargs; (void)ndargs; (void)out;
+  if (!c) return SGS_EINVAL;
+  (void)kind;
+  return SGS_EINVAL;
+}
+
+int sgs_status(sgs_ctx* c) {
+  if (!c) return SGS_EINVAL;
+  int st = 0;
+  if (hipStreamSynchronize(c->s) != hipSuccess) return SGS_EHIP;
+  if (hipMemcpy(&st, c->status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SGS_EHIP;
+  const int zero = 0;
+  if (hipMemcpy(c->status, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return SGS_EHIP;
+  return st;
+}
+
+void sgs_destroy(sgs_ctx* c) { delete c; }
+
+const char* sgs_strerror(int code) {
+  switch (code) {
+    case SGS_OK: return "ok";
+    case SGS_EINVAL: return "invalid argument";
+    case SGS_ENOTSKEW: return "covariance matrix is not skew-symmetric";
+    case SGS_ENOTPURE: return "covariance matrix is not pure (Gamma^2 != -1)";
+    case SGS_EPARITY: return "odd-parity covariance matrix";
+    case SGS_ESINGULAR: return "singular pair matrix or Gram matrix";
+    case SGS_ENOCONV: return "purification or eigen-solve did not converge";
+    case SGS_EHIP: return "HIP runtime error";
+    case SGS_ESTATE: return "call out of order";
+    case SGS_EWORKSPACE: return "workspace too small";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+// Covariance-matrix force, Eq. (EOM-Gamma3) in the compact form that holds
+// when lambda solves Eq. (eigLambda):
+//   dGamma_mu = 2 Re{ w_mu sum_b lambda_b [ 2 G_mb K F K^T - (h_mb - E G_mb) D ] }
+//   K F K^T   = F + i (Y - Y^T) + Y D,   D = Delta^{b mu}, F = F^{b mu}, Y = D F,
+// with w_mu = lambda~_mu^* c_mu (c_mu of Eq. Bmu).  With c1 = 4 w_mu lambda_b G_mb
+// and c2 = -2 w_mu lambda_b (h_mb - E G_mb) (tables from the amplitude solve):
+//   dGamma_mu = sum_b Re{c1 (F + i (Y - Y^T) + Y D) + c2 D}.
+// The dense part Re(c1 Y D) = Y_r Re(c1 D) - Y_i Im(c1 D) is one real GEMM of
+// depth 2n per term; the workgroup for an output tile streams every term b
+// through the matrix cores, forming the B operand Re(c1 D) / -Im(c1 D) on the
+// fly from W (D_r = -2 W) and D_i, then adds the remaining terms and writes
+// the tile and its skew mirror (the force is skew: only tiles I <= J run).
+// The pair (a < b) stores Delta^{ba}; the term for mu = b uses its complex
+// conjugate (sgn = -1 on every imaginary part).
+#include "sgs_internal.h"
+
+namespace sgs {
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ dvec4 mfma64(double a, double b, dvec4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int FTK = 16;
+constexpr int FLP = 64 + 1;
+
+// grid: (ntri, R); block 256.  terms: R*R descriptors (mu-major).
+// coef: c1 then c2 tables, complex interleaved, R*R each.
+__global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceTerm* __restrict__ terms,
+                                               const double* __restrict__ coef,
+                                               const double* __restrict__ Adense,
+                                               const int* __restrict__ impos, int M,
+                                               double* __restrict__ dG) {
+  __shared__ double As[2][FTK][FLP];
+  __shared__ double Bs[2][FTK][FLP];
+  __shared__ double Tt[64][FLP];
+
+  // upper-triangular tile index -> (I, J), I <= J
+  int tri = blockIdx.x, I = 0;
+  while (tri >= T - I) { tri -= T - I; ++I; }
+  const int J = I + tri;
+  const int mu = blockIdx.y;
+  const int row0 = I * 64, col0 = J * 64;
+  const long long nn = (long long)n * n;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  dvec4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dvec4{0, 0, 0, 0};
+
+  const double* c1t = coef;
+  const double* c2t = coef + 2 * R * R;
+
+  // A slab: rows row0..+63, k kc..kc+15  (thread: row tid>>2, 4 consecutive k)
+  const int a_i = tid >> 2, a_k = (tid & 3) * 4;
+  // B slab: k kc..kc+15, cols col0..+63 (thread: k tid>>4, 4 consecutive cols)
+  const int b_k = tid >> 4, b_j = (tid & 15) * 4;
+
+  for (int b = 0; b < R; ++b) {
+    const ForceTerm tm = terms[mu * R + b];
+    const double x1 = c1t[2 * tm.coef], y1 = c1t[2 * tm.coef + 1];
+    const bool has_im = tm.Yi != nullptr;
+    const double sg = tm.sgn, ds = tm.dr_scale;
+    double ra[2][4], rb[2][4];
+    auto load = [&](int kc) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = row0 + a_i, gk = kc + a_k + r;
+        const bool ok = gi < n && gk < n;
+        const long long o = (long long)gi * n + gk;
+        ra[0][r] = ok ? tm.Yr[o] : 0.0;
+        ra[1][r] = (ok && has_im) ? sg * tm.Yi[o] : 0.0;
+        const int gk2 = kc + b_k, gj = col0 + b_j + r;
+        const bool okb = gk2 < n && gj < n;
+        const long long ob = (long long)gk2 * n + gj;
+        const double dr = okb ? ds * tm.Dr[ob] : 0.0;
+        const double di = (okb && has_im) ? sg * tm.Di[ob] : 0.0;
+        rb[0][r] = x1 * dr - y1 * di;       // Re(c1 D)
+        rb[1][r] = -(x1 * di + y1 * dr);    // -Im(c1 D)
+      }
+    };
+    load(0);
+    for (int kc = 0; kc < n; kc += FTK) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        As[0][a_k + r][a_i] = ra[0][r];
+        As[1][a_k + r][a_i] = ra[1][r];
+        Bs[0][b_k][b_j + r] = rb[0][r];
+        Bs[1][b_k][b_j + r] = rb[1][r];
+      }
+      __syncthreads();
+      if (kc + FTK < n) load(kc + FTK);
+#pragma unroll
+      for (int kk = 0; kk < FTK / 4; ++kk) {
+        const int kr = kk * 4 + (lane >> 4);
+        double a0[2], a1[2], b0[2], b1[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          a0[q] = As[0][kr][wm * 32 + q * 16 + (lane & 15)];
+          a1[q] = As[1][kr][wm * 32 + q * 16 + (lane & 15)];
+          b0[q] = Bs[0][kr][wn * 32 + q * 16 + (lane & 15)];
+          b1[q] = Bs[1][kr][wn * 32 + q * 16 + (lane & 15)];
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) {
+            acc[bi][bj] = mfma64(a0[bi], b0[bj], acc[bi][bj]);
+            if (has_im) acc[bi][bj] = mfma64(a1[bi], b1[bj], acc[bi][bj]);
+          }
+      }
+    }
+  }
+
+  // ---- remaining terms, per output element (i, j) of this lane ----
+  double lin[2][2][4];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) lin[bi][bj][r] = 0.0;
+  double sx1 = 0.0;
+  for (int b = 0; b < R; ++b) {
+    const ForceTerm tm = terms[mu * R + b];
+    const double x1 = c1t[2 * tm.coef], y1 = c1t[2 * tm.coef + 1];
+    const double x2 = c2t[2 * tm.coef], y2 = c2t[2 * tm.coef + 1];
+    const bool has_im = tm.Yi != nullptr;
+    const double sg = tm.sgn, ds = tm.dr_scale;
+    sx1 += x1;
+    // transposed block: Tt[c][r] = (x1 sg Yi + y1 Yr)(col0 + r, row0 + c)
+    __syncthreads();
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int r = e >> 6, c = e & 63;
+      const int gr = col0 + r, gc = row0 + c;
+      double v = 0.0;
+      if (gr < n && gc < n) {
+        const long long o = (long long)gr * n + gc;
+        v = y1 * tm.Yr[o];
+        if (has_im) v += x1 * sg * tm.Yi[o];
+      }
+      Tt[c][r] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int li = wm * 32 + bi * 16 + (lane >> 4) * 4 + r;
+          const int lj = wn * 32 + bj * 16 + (lane & 15);
+          const int gi = row0 + li, gj = col0 + lj;
+          if (gi < n && gj < n) {
+            const long long o = (long long)gi * n + gj;
+            double v = Tt[li][lj] - y1 * tm.Yr[o] + x2 * ds * tm.Dr[o];
+            if (has_im) v += -x1 * sg * tm.Yi[o] - y2 * sg * tm.Di[o];
+            if (M > 0) {
+              const int pi = impos[gi], pj = impos[gj];
+              if (pi >= 0 && pj >= 0) {
+                v += x1 * tm.Fcr[pi * M + pj];
+                if (tm.Fci) v -= y1 * sg * tm.Fci[pi * M + pj];
+              }
+            }
+            lin[bi][bj][r] += v;
+          }
+        }
+  }
+
+  // ---- total, skew write-out ----
+  __syncthreads();
+  double* out = dG + (long long)mu * nn;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int li = wm * 32 + bi * 16 + (lane >> 4) * 4 + r;
+        const int lj = wn * 32 + bj * 16 + (lane & 15);
+        const int gi = row0 + li, gj = col0 + lj;
+        double v = 0.0;
+        if (gi < n && gj < n) v = acc[bi][bj][r] + lin[bi][bj][r] + sx1 * Adense[(long long)gi * n + gj];
+        if (I == J) Tt[li][lj] = v;
+        else if (gi < n && gj < n) {
+          out[(long long)gi * n + gj] = v;
+          out[(long long)gj * n + gi] = -v;
+        }
+      }
+  if (I == J) {
+    __syncthreads();
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int li = e >> 6, lj = e & 63;
+      const int gi = row0 + li, gj = col0 + lj;
+      if (gi < n && gj < n) out[(long long)gi * n + gj] = 0.5 * (Tt[li][lj] - Tt[lj][li]);
+    }
+  }
+}
+
+hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
+                        const int* impos, int M, double* dG, hipStream_t s) {
+  const int T = (n + 63) / 64;
+  const int ntri = T * (T + 1) / 2;
+  hipLaunchKernelGGL(k_force, dim3(ntri, R), dim3(256), 0, s, n, R, T, terms, coef, A, impos, M, dG);
+  return hipGetLastError();
+}
+
+}  // namespace sgs

@@ -1,0 +1,185 @@
+// Grouped GEMM on the CDNA4 matrix cores.
+//
+// One launch runs a whole table of independent jobs of arbitrary (M, N, K):
+// workgroup b finds its job by binary search over the jobs' first-tile
+// indices, so uneven problem sizes share one grid.  Each workgroup computes
+// a 64 x 64 output tile with 4 waves of 32 x 32 (2 x 2 MFMA blocks of
+// 16 x 16); K advances in slabs of 16 staged through LDS, with the next slab
+// prefetched into registers while the current one is multiplied.
+//
+// MFMA operand layout (v_mfma_{f64,f32}_16x16x4): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register r of lane l
+// holds C[4 * (l / 16) + r][l % 16].
+#include "sgs_internal.h"
+
+namespace sgs {
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ dvec4 mfma(double a, double b, dvec4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ fvec4 mfma(float a, float b, fvec4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T> struct VecOf;
+template <> struct VecOf<double> { typedef dvec4 type; };
+template <> struct VecOf<float> { typedef fvec4 type; };
+
+template <typename Job>
+__device__ __forceinline__ int find_job(const Job* __restrict__ jobs, int njobs, int tile) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+constexpr int TK = 16;
+constexpr int LDP = 64 + 1;  // LDS row pitch (elements), padded
+
+template <typename T, typename Job, bool CPLX>
+__global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, int njobs) {
+  typedef typename VecOf<T>::type V4;
+  constexpr int NP = CPLX ? 2 : 1;
+  __shared__ T As[NP][TK][LDP];
+  __shared__ T Bs[NP][TK][LDP];
+
+  const int tile = blockIdx.x;
+  const int jid = find_job(jobs, njobs, tile);
+  const Job& J = jobs[jid];
+  const T* __restrict__ A = J.A;
+  const T* __restrict__ B = J.B;
+  const int M = J.M, N = J.N, K = J.K;
+  const int lda = J.lda, ldb = J.ldb;
+  const int ta = J.ta, tb = J.tb;
+  const long long aim = J.a_im, bim = J.b_im;
+  const int t = tile - J.tile_begin;
+  const int row0 = (t / J.tiles_n) * 64;
+  const int col0 = (t % J.tiles_n) * 64;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+
+  V4 acc[NP][2][2];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[p][i][j] = V4{0, 0, 0, 0};
+
+  T ra[NP][4], rb[NP][4];
+
+  // index pattern of this thread's 4 A and 4 B elements inside a slab
+  const int a_i = ta ? (tid & 15) * 4 : (tid >> 2);
+  const int a_k = ta ? (tid >> 4) : (tid & 3) * 4;
+  const int b_k = tb ? (tid & 3) * 4 : (tid >> 4);
+  const int b_j = tb ? (tid >> 2) : (tid & 15) * 4;
+
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int gi = row0 + a_i + (ta ? r : 0);
+      int gk = kc + a_k + (ta ? 0 : r);
+      bool ok = gi < M && gk < K;
+      long long off = ta ? (long long)gk * lda + gi : (long long)gi * lda + gk;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) ra[p][r] = ok ? A[off + p * aim] : T(0);
+      int gj = col0 + b_j + (tb ? 0 : r);
+      int gk2 = kc + b_k + (tb ? r : 0);
+      bool okb = gj < N && gk2 < K;
+      long long offb = tb ? (long long)gj * ldb + gk2 : (long long)gk2 * ldb + gj;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) rb[p][r] = okb ? B[offb + p * bim] : T(0);
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        if (ta) As[p][a_k][a_i + r] = ra[p][r]; else As[p][a_k + r][a_i] = ra[p][r];
+        if (tb) Bs[p][b_k + r][b_j] = rb[p][r]; else Bs[p][b_k][b_j + r] = rb[p][r];
+      }
+    }
+  };
+
+  load(0);
+  for (int kc = 0; kc < K; kc += TK) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (kc + TK < K) load(kc + TK);
+#pragma unroll
+    for (int kk = 0; kk < TK / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      T a[NP][2], b[NP][2];
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          a[p][q] = As[p][kr][wm * 32 + q * 16 + (lane & 15)];
+          b[p][q] = Bs[p][kr][wn * 32 + q * 16 + (lane & 15)];
+        }
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          if (CPLX) {
+            acc[0][bi][bj] = mfma(a[0][bi], b[0][bj], acc[0][bi][bj]);
+            acc[0][bi][bj] = mfma(-a[NP - 1][bi], b[NP - 1][bj], acc[0][bi][bj]);
+            acc[NP - 1][bi][bj] = mfma(a[0][bi], b[NP - 1][bj], acc[NP - 1][bi][bj]);
+            acc[NP - 1][bi][bj] = mfma(a[NP - 1][bi], b[0][bj], acc[NP - 1][bi][bj]);
+          } else {
+            acc[0][bi][bj] = mfma(a[0][bi], b[0][bj], acc[0][bi][bj]);
+          }
+        }
+    }
+  }
+
+  const T alpha = J.alpha, beta = J.beta, diag = J.diag;
+  const T* __restrict__ C = J.C;
+  T* __restrict__ D = J.D;
+  const int ldc = J.ldc, ldd = J.ldd;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = row0 + wm * 32 + bi * 16 + (lane >> 4) * 4 + r;
+        int col = col0 + wn * 32 + bj * 16 + (lane & 15);
+        if (row < M && col < N) {
+#pragma unroll
+          for (int p = 0; p < NP; ++p) {
+            T v = alpha * acc[p][bi][bj][r];
+            if (beta != T(0)) v += beta * C[(long long)row * ldc + col + p * J.c_im];
+            if (p == 0 && row == col) v += diag;
+            D[(long long)row * ldd + col + p * J.d_im] = v;
+          }
+        }
+      }
+}
+
+hipError_t launch_gemm(const GemmJob* jobs, int njobs, int ntiles, bool cplx, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (cplx)
+    hipLaunchKernelGGL((k_gemm<double, GemmJob, true>), dim3(ntiles), dim3(256), 0, s, jobs, njobs);
+  else
+    hipLaunchKernelGGL((k_gemm<double, GemmJob, false>), dim3(ntiles), dim3(256), 0, s, jobs, njobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_f32(const GemmJobF* jobs, int njobs, int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gemm<float, GemmJobF, false>), dim3(ntiles), dim3(256), 0, s, jobs, njobs);
+  return hipGetLastError();
+}
+
+}  // namespace sgs

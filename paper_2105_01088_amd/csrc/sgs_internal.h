@@ -1,0 +1,158 @@
+// Internal declarations shared by the HIP kernels and the host driver of the
+// SGS library.  Not part of the public ABI (include/sgs.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sgs {
+
+// ---------------------------------------------------------------------------
+// Grouped GEMM: D = alpha * op(A) op(B) + beta * C (+ diag on the diagonal)
+// for a table of independent jobs of any size, one launch for all of them.
+// op(A) is M x K: ta = 0 reads A[i*lda + k], ta = 1 reads A[k*lda + i].
+// op(B) is K x N: tb = 0 reads B[k*ldb + j], tb = 1 reads B[j*ldb + k].
+// Complex jobs are planar: the imaginary plane of X sits at X + x_im.
+// ---------------------------------------------------------------------------
+struct GemmJob {
+  const double* A;
+  const double* B;
+  const double* C;  // may be null when beta == 0
+  double* D;
+  long long a_im, b_im, c_im, d_im;  // complex: offsets of imaginary planes
+  int M, N, K;
+  int lda, ldb, ldc, ldd;
+  int ta, tb;
+  double alpha, beta, diag;
+  int tiles_n;     // ceil(N / 64)
+  int tile_begin;  // first global tile index of this job
+};
+
+// float32 twin used by the precision path (same layout, float operands).
+struct GemmJobF {
+  const float* A;
+  const float* B;
+  const float* C;
+  float* D;
+  long long a_im, b_im, c_im, d_im;
+  int M, N, K;
+  int lda, ldb, ldc, ldd;
+  int ta, tb;
+  float alpha, beta, diag;
+  int tiles_n;
+  int tile_begin;
+};
+
+constexpr int GEMM_TILE = 64;
+
+// Launch helpers (gemm.hip).  jobs: device table; ntiles: total tiles.
+hipError_t launch_gemm(const GemmJob* jobs, int njobs, int ntiles, bool cplx,
+                       hipStream_t s);
+hipError_t launch_gemm_f32(const GemmJobF* jobs, int njobs, int ntiles,
+                           hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Status word (device int): first failure wins.
+// ---------------------------------------------------------------------------
+enum : int { ST_OK = 0, ST_SINGULAR = -5, ST_NOCONV = -6 };
+
+// ---------------------------------------------------------------------------
+// Force accumulation: one output state mu, R descriptors (one per beta).
+// ---------------------------------------------------------------------------
+struct ForceTerm {
+  const double* Dr;   // real part source: W (scaled by dr_scale) or Gamma_mu
+  const double* Di;   // imaginary part of Delta (null on the diagonal)
+  const double* Yr;   // Delta F, real plane
+  const double* Yi;   // Delta F, imaginary plane (null on the diagonal)
+  const double* Fci;  // impurity-block Fock correction, imaginary (M*M) or null
+  const double* Fcr;  // impurity-block Fock correction, real (M*M)
+  double dr_scale;    // -2 (pair) or 1 (diagonal)
+  double sgn;         // +1: stored orientation; -1: complex conjugate
+  int coef;           // index into the (R x R) coefficient tables
+  int pad;
+};
+
+
+// Hamiltonian tables on the device (pair.hip)
+struct HamDev {
+  int n, nnz_up, nq, M;
+  const int* up_k;     // upper-triangle nonzeros of A: (k < l, A_kl)
+  const int* up_l;
+  const double* up_v;
+  const int* q_idx;    // nq x 4 global Majorana indices
+  const int* q_loc;    // nq x 4 positions in the impurity list
+  const double* q_val;
+  double e0;
+};
+
+// A in compressed-column form plus the impurity index maps (pair.hip)
+struct SparseA {
+  const int* colptr;  // n + 1
+  const int* row;
+  const double* val;
+  const int* imp;     // M impurity Majoranas
+  const int* impos;   // n: position in imp, or -1
+  int M;
+};
+
+// Arguments of the amplitude solve (solve.hip)
+struct SolveArgs {
+  int N, R, P;
+  const int* pidx;      // R*R: pair index of (min, max), -1 on the diagonal
+  const int* qidx;      // R*R: phase-matrix index for 1 <= a < b, else -1
+  const double* logdet; // P
+  const double* pfacc;  // Q*3: ln|Pf|, cos, sin
+  const double* eps;    // (P + R) complex: pairs then diagonal
+  double* tab_la;       // R*R outputs
+  double* tab_arg;
+  double* tab_eps;      // R*R complex
+  double* Gt;           // R*R complex
+  double* ht;           // R*R complex
+  double* lam;          // R complex
+  double* lamt;         // R complex
+  double* coef;         // c1 (R*R complex) then c2 (R*R complex)
+  double* E;            // 1
+  double* energy_slot;  // optional: energies[k * nprob + p]
+  int* status;
+  double g_thr;
+  int weight;           // 0 printed, 1 unit
+};
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+size_t gj_panel_lds_bytes(int n, int k, int b);
+hipError_t launch_gj_panel(double* M, long long mstride, int nmat, int n, int k, int b, double* E,
+                           long long estride, double* Br, long long bstride, int* piv, double* logdet,
+                           int* status, hipStream_t s);
+hipError_t launch_gj_unscramble(double* M, long long mstride, int nmat, int n, const int* piv,
+                                hipStream_t s);
+hipError_t set_gj_lds_limit(size_t bytes);
+size_t pf_panel_lds_bytes(int n, int nbh);
+hipError_t launch_pf_panel(double* A, long long astride, int nmat, int n, int p0, int nbh, double* UV,
+                           double* RM, long long uvstride, long long uv_im, double* acc, int* status,
+                           hipStream_t s);
+hipError_t launch_pf_zero(double* UV, long long total, hipStream_t s);
+hipError_t launch_pair_sum(const double* gam, int n, const int* pa, const int* pb, int P, double* S,
+                           double* logdet, hipStream_t s);
+hipError_t launch_eps_fock(const HamDev& h, int P, int R, const double* W, const double* Di,
+                           const double* gam, const int* pa, const int* pb, double* eps, double* Fc,
+                           hipStream_t s);
+hipError_t launch_apply_fock(const SparseA& sa, int n, int P, int R, const double* W, const double* Di,
+                             const double* gam, const double* Fc, double* Y, double* Yd, hipStream_t s);
+hipError_t launch_build_c(int n, const double* gam, const double* T, const double* Xr, const int* qa,
+                          const int* qb, int Q, double* Cm, hipStream_t s);
+size_t solve_lds_bytes(int R);
+hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
+hipError_t set_solve_lds_limit(size_t bytes);
+hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
+                        const int* impos, int M, double* dG, hipStream_t s);
+hipError_t launch_euler(const double* gam, const double* dG, double dtau, long long total, double* X,
+                        hipStream_t s);
+hipError_t launch_ns_resid(const double* Q, int n, long long total, unsigned long long* out, hipStream_t s);
+hipError_t launch_finalize(const double* X, int n, int R, double* gam, const unsigned long long* resid,
+                           double tol, int* status, hipStream_t s);
+hipError_t launch_skew_resid(const double* G, int n, long long total, unsigned long long* out,
+                             hipStream_t s);
+
+}  // namespace sgs

@@ -1,0 +1,143 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Tolerances (float64 path): the pair inverse and the Pfaffian lose about
+kappa * n * eps relative accuracy (kappa = cond(Gamma_a + Gamma_b), a few
+hundred to a few thousand for the seeded random states used here), so tables
+are compared at 1e-9 (log|G|, phase, eps), one-step covariance matrices at
+1e-10 absolute and energies at 1e-10 relative.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import sgs_inputs as si
+from oracle import sgs as osgs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_TAB = 1e-9
+TOL_GAMMA = 1e-10
+TOL_E = 1e-10
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _ctx(ham, gam, weight=0, **kw):
+    from paper_2105_01088_amd import SGS, default_options
+    return SGS([ham], [gam], options=default_options(weight=weight, **kw))
+
+
+def _tables(ctx):
+    la, ar, ep = ctx.pair_eval()
+    assert ctx.status() == 0
+    R = ctx.R[0]
+    la = la.cpu().numpy().reshape(R, R)
+    ar = ar.cpu().numpy().reshape(R, R)
+    ep = ep.cpu().numpy().reshape(R, R, 2)
+    return la, ar, ep[..., 0] + 1j * ep[..., 1]
+
+
+def _cmp_tables(ham, gam, tag):
+    _say(f"[pair_eval] {tag} n={gam.shape[1]} R={gam.shape[0]}")
+    ctx = _ctx(ham, gam)
+    la, ar, ep = _tables(ctx)
+    ref = osgs.pair_tables(ham, gam)
+    R = gam.shape[0]
+    off = ~np.eye(R, dtype=bool)
+    if R > 1:
+        assert np.abs(la - ref.logabs)[off].max() < TOL_TAB * max(1.0, np.abs(ref.logabs).max())
+        assert np.abs(np.exp(1j * ar) - np.exp(1j * ref.arg)).max() < TOL_TAB
+    scale = max(1.0, np.abs(ref.eps).max())
+    assert np.abs(ep - ref.eps).max() < TOL_TAB * scale
+    ctx.close()
+
+
+@pytest.mark.parametrize("L,R,seed", [(3, 4, 1), (24, 5, 2), (32, 6, 3)])
+def test_pair_tables_anderson(L, R, seed):
+    ham = si.anderson(L, 1.3, 0.6)
+    gam = si.random_states(ham.N, R, seed)
+    _cmp_tables(ham, gam, f"anderson L={L}")
+
+
+def test_pair_tables_two_channel_kondo():
+    ham = si.two_channel_kondo(3, 0.5, U=8.0)
+    gam = si.random_states(ham.N, 4, 5)
+    _cmp_tables(ham, gam, "tck L=3")
+
+
+@pytest.mark.parametrize("weight", [0, 1])
+@pytest.mark.parametrize("L,R,seed", [(1, 3, 3), (3, 4, 1), (32, 3, 7)])
+def test_one_step_matches_oracle(weight, L, R, seed):
+    ham = si.anderson(L, 1.3, 0.6)
+    gam = si.random_states(ham.N, R, seed)
+    _say(f"[step] anderson L={L} R={R} weight={weight}")
+    ctx = _ctx(ham, gam, weight=weight)
+    e = ctx.step(0.05, 1)
+    assert ctx.status() == 0
+    g_new = ctx.gammas(0).cpu().numpy()
+    ref = osgs.step(ham, gam, 0.05, mode="printed" if weight == 0 else "unit")
+    assert abs(e.cpu().item() - ref.E) < TOL_E * abs(ref.E)
+    assert np.abs(g_new - ref.gammas).max() < TOL_GAMMA
+    ctx.close()
+
+
+@pytest.mark.parametrize("R", [1, 2])
+def test_small_rank_edge_cases(R):
+    ham = si.anderson(5, 1.0, 0.5)
+    gam = si.random_states(ham.N, R, 11)
+    _say(f"[step] edge R={R}")
+    ctx = _ctx(ham, gam)
+    e = ctx.step(0.05, 2)
+    assert ctx.status() == 0
+    g = gam
+    es = []
+    for _ in range(2):
+        r = osgs.step(ham, g, 0.05)
+        es.append(r.E)
+        g = r.gammas
+    assert np.allclose(e.cpu().numpy(), es, rtol=TOL_E, atol=0)
+    assert np.abs(ctx.gammas(0).cpu().numpy() - g).max() < TOL_GAMMA
+    ctx.close()
+
+
+def test_two_channel_kondo_step():
+    ham = si.two_channel_kondo(3, 0.5, U=8.0)
+    gam = si.random_states(ham.N, 3, 2)
+    _say("[step] tck L=3 R=3")
+    ctx = _ctx(ham, gam)
+    e = ctx.step(0.05, 1)
+    assert ctx.status() == 0
+    ref = osgs.step(ham, gam, 0.05)
+    assert abs(e.cpu().item() - ref.E) < TOL_E * abs(ref.E)
+    assert np.abs(ctx.gammas(0).cpu().numpy() - ref.gammas).max() < TOL_GAMMA
+    ctx.close()
+
+
+def test_anderson_L7_trajectory_and_bounds():
+    import json
+    import os
+    ham, gam, cfg = si.config_problem("anderson_L7_R4")
+    _say("[trajectory] anderson L=7 R=4, 20 steps")
+    ctx = _ctx(ham, gam)
+    e = ctx.step(0.05, 20).cpu().numpy()
+    assert ctx.status() == 0
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "anderson_L7.json")))
+    first10 = np.array(gold["anderson_L7_R4_seed0_first10_E"]["value"])
+    assert np.abs(e[:10] - first10).max() < TOL_E * np.abs(first10).max()
+    _, es = osgs.run(ham, gam, 0.05, 20)
+    assert np.abs(e - es).max() < TOL_E * np.abs(es).max()
+    e_ed = gold["anderson_L7_U1_V0.5_ed_even"]["value"]
+    assert np.all(e >= e_ed - 1e-12)
+    assert np.all(np.diff(e) <= 1e-12)
+    g = ctx.gammas(0).cpu().numpy()
+    for x in g:
+        assert np.abs(x + x.T).max() == 0.0
+        assert np.abs(x @ x + np.eye(x.shape[0])).max() < 1e-12
+    ctx.close()
