@@ -91,9 +91,10 @@ typedef struct {
   double g_rel_threshold;  /* canonical orthogonalization: eigenvectors of G   */
                            /* below this fraction of its largest eigenvalue are*/
                            /* dropped (default 1e-12)                          */
-  double purify_tol;       /* max |X^2 + 1| accepted after purification       */
-                           /* (default 1e-12)                                  */
-  int32_t purify_iters;    /* Newton-Schulz polar iterations (default 5)       */
+  double purify_tol;       /* purification: iterations stop once max|X^2 + 1|  */
+                           /* < min(1e-8, sqrt(purify_tol)) (default 1e-12)    */
+  int32_t purify_iters;    /* max Newton-Schulz polar iterations (default 24); */
+                           /* not converging sets SGS_ENOCONV                  */
   int32_t refine_iters;    /* float64 refinement sweeps on the FP32 path (2)  */
 } sgs_options;
 

@@ -49,6 +49,7 @@ struct Prob {
   double *up_v, *colval, *q_val;
   int *piv, *pa, *pb, *qa, *qb, *pidx, *qidx, *up_k, *up_l, *colptr, *rowidx, *imp, *impos, *q_idx, *q_loc;
   unsigned long long* resid;
+  int* nsctl;
   ForceTerm* terms;
   JobTable jdi, jt1, jxr, jnsq[2], jnsx[2], jval;
   std::vector<JobTable> jgj, jpf;
@@ -176,6 +177,7 @@ static void carve(Prob& q, Arena& ar) {
   q.q_idx = ar.take<int>(std::max(1, 4 * q.nq));
   q.q_loc = ar.take<int>(std::max(1, 4 * q.nq));
   q.resid = ar.take<unsigned long long>(1);
+  q.nsctl = ar.take<int>(4);
   q.terms = ar.take<ForceTerm>((size_t)R * R);
 }
 
@@ -389,8 +391,8 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
 // ---------------------------------------------------------------------------
 // stages
 // ---------------------------------------------------------------------------
-static hipError_t run_gemm(const JobTable& t, hipStream_t s) {
-  return launch_gemm(t.dev, (int)t.host.size(), t.ntiles, t.cplx, s);
+static hipError_t run_gemm(const JobTable& t, hipStream_t s, const int* ctl = nullptr, int it = 0) {
+  return launch_gemm(t.dev, (int)t.host.size(), t.ntiles, t.cplx, s, ctl, it);
 }
 
 #define HCHK(x)                               \
@@ -451,15 +453,16 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
   const int n = q.n, R = q.R;
   const long long nn = (long long)n * n;
   HCHK(launch_force(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, q.dG, s));
-  HCHK(launch_euler(q.gam, q.dG, dtau, R * nn, q.nsX0, s));
-  int par = 0;
+  (void)nn;
+  HCHK(launch_euler(q.gam, q.dG, dtau, n, R, q.nsX0, q.nsctl, s));
+  const double thr = std::min(1e-8, std::sqrt(c->opt.purify_tol));
   for (int it = 0; it < c->opt.purify_iters; ++it) {
-    HCHK(run_gemm(q.jnsq[par], s));
-    if (it == c->opt.purify_iters - 1) HCHK(launch_ns_resid(q.nsQ, n, R * nn, q.resid, s));
-    HCHK(run_gemm(q.jnsx[par], s));
-    par ^= 1;
+    const int par = it & 1;
+    HCHK(run_gemm(q.jnsq[par], s, q.nsctl, it));
+    HCHK(launch_ns_check(q.nsQ, n, R, q.resid, q.nsctl, it, thr, s));
+    HCHK(run_gemm(q.jnsx[par], s, q.nsctl, it));
   }
-  HCHK(launch_finalize(par ? q.nsX1 : q.nsX0, n, R, q.gam, q.resid, c->opt.purify_tol, c->status, s));
+  HCHK(launch_finalize(q.nsX0, q.nsX1, n, R, q.gam, q.nsctl, c->opt.purify_iters, c->status, s));
   return hipSuccess;
 }
 
@@ -474,7 +477,7 @@ void sgs_default_options(sgs_options* o) {
   o->weight = SGS_W_PRINTED;
   o->g_rel_threshold = 1e-12;
   o->purify_tol = 1e-12;
-  o->purify_iters = 5;
+  o->purify_iters = 24;
   o->refine_iters = 2;
 }
 

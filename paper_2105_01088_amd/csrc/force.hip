@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
       for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int li = wm * 32 + bi * 16 + (lane >> 4) * 4 + r;
+          const int li = wm * 32 + bi * 16 + 4 * r + (lane >> 4);  // f64 MFMA accumulator row
           const int lj = wn * 32 + bj * 16 + (lane & 15);
           const int gi = row0 + li, gj = col0 + lj;
           if (gi < n && gj < n) {
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int li = wm * 32 + bi * 16 + (lane >> 4) * 4 + r;
+        const int li = wm * 32 + bi * 16 + 4 * r + (lane >> 4);  // f64 MFMA accumulator row
         const int lj = wn * 32 + bj * 16 + (lane & 15);
         const int gi = row0 + li, gj = col0 + lj;
         double v = 0.0;

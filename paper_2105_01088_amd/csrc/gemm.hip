@@ -8,8 +8,9 @@
 // prefetched into registers while the current one is multiplied.
 //
 // MFMA operand layout (v_mfma_{f64,f32}_16x16x4): lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register r of lane l
-// holds C[4 * (l / 16) + r][l % 16].
+// A[l % 16][l / 16] and B[l / 16][l % 16].  Accumulator register r of lane l
+// holds C[row][l % 16] with row = 4 r + l / 16 for the f64 instruction and
+// row = 4 (l / 16) + r for the f32 one (AccRow below; both measured on gfx950).
 #include "sgs_internal.h"
 
 namespace sgs {
@@ -23,6 +24,14 @@ __device__ __forceinline__ dvec4 mfma(double a, double b, dvec4 c) {
 __device__ __forceinline__ fvec4 mfma(float a, float b, fvec4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+
+template <typename T> struct AccRow;
+template <> struct AccRow<double> {
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <> struct AccRow<float> {
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
 
 template <typename T> struct VecOf;
 template <> struct VecOf<double> { typedef dvec4 type; };
@@ -42,7 +51,10 @@ constexpr int TK = 16;
 constexpr int LDP = 64 + 1;  // LDS row pitch (elements), padded
 
 template <typename T, typename Job, bool CPLX>
-__global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, int njobs) {
+__global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, int njobs,
+                                              const int* __restrict__ ctl, int it) {
+  // iterative callers: skip once the device-side counter says converged
+  if (ctl != nullptr && ctl[0] < it) return;
   typedef typename VecOf<T>::type V4;
   constexpr int NP = CPLX ? 2 : 1;
   __shared__ T As[NP][TK][LDP];
@@ -153,7 +165,7 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, int 
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int row = row0 + wm * 32 + bi * 16 + (lane >> 4) * 4 + r;
+        int row = row0 + wm * 32 + bi * 16 + AccRow<T>::row(lane, r);
         int col = col0 + wn * 32 + bj * 16 + (lane & 15);
         if (row < M && col < N) {
 #pragma unroll
@@ -167,18 +179,20 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, int 
       }
 }
 
-hipError_t launch_gemm(const GemmJob* jobs, int njobs, int ntiles, bool cplx, hipStream_t s) {
+hipError_t launch_gemm(const GemmJob* jobs, int njobs, int ntiles, bool cplx, hipStream_t s,
+                       const int* ctl, int it) {
   if (ntiles <= 0) return hipSuccess;
   if (cplx)
-    hipLaunchKernelGGL((k_gemm<double, GemmJob, true>), dim3(ntiles), dim3(256), 0, s, jobs, njobs);
+    hipLaunchKernelGGL((k_gemm<double, GemmJob, true>), dim3(ntiles), dim3(256), 0, s, jobs, njobs, ctl, it);
   else
-    hipLaunchKernelGGL((k_gemm<double, GemmJob, false>), dim3(ntiles), dim3(256), 0, s, jobs, njobs);
+    hipLaunchKernelGGL((k_gemm<double, GemmJob, false>), dim3(ntiles), dim3(256), 0, s, jobs, njobs, ctl, it);
   return hipGetLastError();
 }
 
 hipError_t launch_gemm_f32(const GemmJobF* jobs, int njobs, int ntiles, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gemm<float, GemmJobF, false>), dim3(ntiles), dim3(256), 0, s, jobs, njobs);
+  hipLaunchKernelGGL((k_gemm<float, GemmJobF, false>), dim3(ntiles), dim3(256), 0, s, jobs, njobs,
+                     (const int*)nullptr, 0);
   return hipGetLastError();
 }
 

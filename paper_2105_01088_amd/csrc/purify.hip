@@ -1,25 +1,55 @@
 // First-order step and return to a pure state (App. A).
 //
 // Eq. (RKstep): X = Gamma + ds dGamma (skew).  Eq. (CM-normal-form) with every
-// lambda_j rescaled to unit modulus is the orthogonal polar factor of X; it is
-// reached by Newton-Schulz iterations X <- X (3 - X^T X) / 2 = X (3 + X^2) / 2
-// (X skew), two grouped GEMMs each, converging quadratically because X is
-// within O(ds^2) of orthogonal.  k_ns_resid measures max |X^2 + 1| of the last
-// iterate's square; the final error is about 1.5 times its square.
+// lambda_j rescaled to unit modulus is the orthogonal polar factor of X.
+// Because dGamma anticommutes with Gamma (purity is preserved to first
+// order, Sec. III.B), X^T X = 1 + ds^2 dGamma^T dGamma: every singular value of
+// X lies in [1, sqrt(1 + ds^2 |dGamma|_2^2)].  k_euler scales each state by
+// 1/sqrt(1 + ds^2 |dGamma|_1^2) (|.|_1 >= |.|_2 for a skew matrix), which puts
+// the spectrum in (0, 1], inside the convergence region (0, sqrt 3) of the
+// Newton-Schulz iteration X <- X (3 - X^T X) / 2 = X (3 + X^2) / 2 (two grouped
+// GEMMs; the polar factor is unchanged by the scaling).  After each square,
+// k_ns_check records the first iteration whose max |X^2 + 1| is below the
+// detection threshold; later GEMMs of the step exit at once (ctl[0]).
 #include "sgs_internal.h"
 
 namespace sgs {
 
-__global__ void k_euler(const double* __restrict__ gam, const double* __restrict__ dG, double dtau,
-                        long long total, double* __restrict__ X) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x)
-    X[e] = gam[e] + dtau * dG[e];
+// grid: R blocks; X = alpha_mu (Gamma + ds dGamma); ctl[0] = "not converged"
+__global__ __launch_bounds__(256) void k_euler(const double* __restrict__ gam, const double* __restrict__ dG,
+                                               double dtau, int n, double* __restrict__ X,
+                                               int* __restrict__ ctl) {
+  __shared__ double red[256];
+  const int mu = blockIdx.x;
+  const long long nn = (long long)n * n;
+  const double* g = gam + mu * nn;
+  const double* d = dG + mu * nn;
+  double* x = X + mu * nn;
+  // max column sum of |dGamma| (= max row sum: skew)
+  double mx = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += fabs(d[(long long)i * n + j]);
+    mx = fmax(mx, s);
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  const double nrm = dtau * red[0];
+  const double alpha = 1.0 / sqrt(1.0 + nrm * nrm);
+  for (long long e = threadIdx.x; e < nn; e += blockDim.x) x[e] = alpha * (g[e] + dtau * d[e]);
+  if (mu == 0 && threadIdx.x == 0) ctl[0] = 0x7fffffff;
 }
+
+__global__ void k_zero_u64(unsigned long long* p) { p[0] = 0ull; }
 
 // max over all states of |Q + 1| (Q = X X), as an ordered bit pattern
 __global__ void k_ns_resid(const double* __restrict__ Q, int n, long long total,
-                           unsigned long long* __restrict__ out) {
+                           unsigned long long* __restrict__ out, const int* __restrict__ ctl, int it) {
+  if (ctl != nullptr && ctl[0] < it) return;
   __shared__ double red[256];
   double mx = 0.0;
   const long long nn = (long long)n * n;
@@ -39,10 +69,20 @@ __global__ void k_ns_resid(const double* __restrict__ Q, int n, long long total,
   if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
 }
 
-// Gamma <- (X - X^T) / 2 (exactly skew); also checks the residual bound.
-__global__ void k_finalize(const double* __restrict__ X, int n, int R, double* __restrict__ gam,
-                           const unsigned long long* __restrict__ resid, double tol,
+__global__ void k_ns_flag(const unsigned long long* __restrict__ resid, int* __restrict__ ctl, int it,
+                          double thr) {
+  if (ctl[0] < it) return;
+  const double d = __longlong_as_double((long long)resid[0]);
+  if (d < thr) ctl[0] = it;  // this iteration's update is the last one
+}
+
+// Gamma <- (X - X^T) / 2 from the buffer holding the last iterate
+__global__ void k_finalize(const double* __restrict__ X0, const double* __restrict__ X1, int n, int R,
+                           double* __restrict__ gam, const int* __restrict__ ctl, int maxit,
                            int* __restrict__ status) {
+  const int c = ctl[0];
+  const int last = (c == 0x7fffffff) ? maxit : c + 1;
+  const double* X = (last & 1) ? X1 : X0;
   const long long nn = (long long)n * n;
   const long long total = nn * R;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
@@ -51,13 +91,8 @@ __global__ void k_finalize(const double* __restrict__ X, int n, int R, double* _
     const int i = (int)(r / n), j = (int)(r - (long long)i * n);
     gam[e] = 0.5 * (X[e] - X[mu * nn + (long long)j * n + i]);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const double d = __longlong_as_double((long long)resid[0]);
-    if (!(1.5 * d * d <= tol)) atomicCAS(status, ST_OK, ST_NOCONV);
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && c == 0x7fffffff) atomicCAS(status, ST_OK, ST_NOCONV);
 }
-
-__global__ void k_zero_u64(unsigned long long* p) { p[0] = 0ull; }
 
 static int grid_for(long long total) {
   long long b = (total + 255) / 256;
@@ -66,22 +101,31 @@ static int grid_for(long long total) {
   return (int)b;
 }
 
-hipError_t launch_euler(const double* gam, const double* dG, double dtau, long long total, double* X,
+hipError_t launch_euler(const double* gam, const double* dG, double dtau, int n, int R, double* X, int* ctl,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_euler, dim3(grid_for(total)), dim3(256), 0, s, gam, dG, dtau, total, X);
+  hipLaunchKernelGGL(k_euler, dim3(R), dim3(256), 0, s, gam, dG, dtau, n, X, ctl);
   return hipGetLastError();
 }
 
 hipError_t launch_ns_resid(const double* Q, int n, long long total, unsigned long long* out, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, out);
-  hipLaunchKernelGGL(k_ns_resid, dim3(grid_for(total)), dim3(256), 0, s, Q, n, total, out);
+  hipLaunchKernelGGL(k_ns_resid, dim3(grid_for(total)), dim3(256), 0, s, Q, n, total, out, (const int*)nullptr, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double* X, int n, int R, double* gam, const unsigned long long* resid,
-                           double tol, int* status, hipStream_t s) {
+hipError_t launch_ns_check(const double* Q, int n, int R, unsigned long long* resid, int* ctl, int it,
+                           double thr, hipStream_t s) {
+  const long long total = (long long)n * n * R;
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, resid);
+  hipLaunchKernelGGL(k_ns_resid, dim3(grid_for(total)), dim3(256), 0, s, Q, n, total, resid, (const int*)ctl, it);
+  hipLaunchKernelGGL(k_ns_flag, dim3(1), dim3(1), 0, s, (const unsigned long long*)resid, ctl, it, thr);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* X0, const double* X1, int n, int R, double* gam, const int* ctl,
+                           int maxit, int* status, hipStream_t s) {
   long long total = (long long)n * n * R;
-  hipLaunchKernelGGL(k_finalize, dim3(grid_for(total)), dim3(256), 0, s, X, n, R, gam, resid, tol, status);
+  hipLaunchKernelGGL(k_finalize, dim3(grid_for(total)), dim3(256), 0, s, X0, X1, n, R, gam, ctl, maxit, status);
   return hipGetLastError();
 }
 

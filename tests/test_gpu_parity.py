@@ -5,6 +5,13 @@ kappa * n * eps relative accuracy (kappa = cond(Gamma_a + Gamma_b), a few
 hundred to a few thousand for the seeded random states used here), so tables
 are compared at 1e-9 (log|G|, phase, eps), one-step covariance matrices at
 1e-10 absolute and energies at 1e-10 relative.
+
+With the printed weights c_mu = 1 / (lambda_mu lambda~_mu^*) the force on
+state mu carries lambda_b / lambda_mu: an absolute error of order eps in the
+eigenvector (any float64 eigen-solver) becomes a relative error eps / |lambda_mu|
+in that force.  Random states at large n are nearly orthogonal and some
+amplitudes are ~1e-9, so for that mode the covariance tolerance adds
+1e-14 * dtau * max|dGamma| * max|lambda| / min|lambda|.
 """
 
 import math
@@ -84,8 +91,16 @@ def test_one_step_matches_oracle(weight, L, R, seed):
     g_new = ctx.gammas(0).cpu().numpy()
     ref = osgs.step(ham, gam, 0.05, mode="printed" if weight == 0 else "unit")
     assert abs(e.cpu().item() - ref.E) < TOL_E * abs(ref.E)
-    assert np.abs(g_new - ref.gammas).max() < TOL_GAMMA
+    assert np.abs(g_new - ref.gammas).max() < _gamma_tol(ref, weight, 0.05)
     ctx.close()
+
+
+def _gamma_tol(ref, weight, dtau):
+    if weight != 0:
+        return TOL_GAMMA
+    lam = np.abs(ref.lam)
+    amp = lam.max() / lam.min()
+    return TOL_GAMMA + 1e-14 * dtau * np.abs(ref.dgamma).max() * amp
 
 
 @pytest.mark.parametrize("R", [1, 2])
