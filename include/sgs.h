@@ -168,6 +168,26 @@ int sgs_observables(sgs_ctx* ctx, int32_t kind, const int32_t* iargs,
  * reading it clears it), or SGS_EHIP. */
 int sgs_status(sgs_ctx* ctx);
 
+/* Diagnostics: device time per stage of the step.  After sgs_set_timing(ctx, 1)
+ * every later evaluation records a pair of HIP events on the context's stream
+ * around each stage (no device memory is allocated; events are pooled).
+ * sgs_stage_times waits for the stream, adds the elapsed times recorded since
+ * the previous call into ms[s] (milliseconds) and launches[s] (number of
+ * timed intervals; for SGS_STAGE_FORCE and SGS_STAGE_SOLVE one kernel
+ * launch each) for s < nstage, and clears the record.  Errors: SGS_EINVAL,
+ * SGS_EHIP. */
+#define SGS_STAGE_INVERSE 0   /* Gamma_a + Gamma_b, blocked Gauss-Jordan        */
+#define SGS_STAGE_DELTA 1     /* Im Delta^{ba} = 2 Gamma_b W - 1 (GEMM)          */
+#define SGS_STAGE_WICK 2      /* eps_ab, Fock blocks, Y = Delta F               */
+#define SGS_STAGE_PHASE 3     /* X_a and C_ab for the overlap phases            */
+#define SGS_STAGE_PFAFFIAN 4  /* complex Pfaffians of C_ab                       */
+#define SGS_STAGE_SOLVE 5     /* h lambda = E G lambda, weights, coefficients   */
+#define SGS_STAGE_FORCE 6     /* Eq. (EOM-Gamma3) accumulation                   */
+#define SGS_STAGE_PURIFY 7    /* Euler step and polar purification               */
+#define SGS_NSTAGE 8
+int sgs_set_timing(sgs_ctx* ctx, int32_t enable);
+int sgs_stage_times(sgs_ctx* ctx, double* ms, int32_t* launches, int32_t nstage);
+
 /* Release host-side state.  Device buffers stay owned by the caller. */
 void sgs_destroy(sgs_ctx* ctx);
 

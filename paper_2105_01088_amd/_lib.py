@@ -22,6 +22,7 @@ SGS_W_PRINTED = 0
 SGS_W_UNIT = 1
 SGS_OBS_POLY = 1
 SGS_OBS_RENYI2 = 2
+STAGES = ("inverse", "delta", "wick", "phase", "pfaffian", "solve", "force", "purify")
 
 
 class SGSError(RuntimeError):
@@ -62,12 +63,14 @@ def load_library(path: str = LIB_PATH):
     lib.sgs_observables.argtypes = [c_void_p, c_int32, POINTER(c_int32), c_int32, POINTER(c_double), c_int32,
                                     c_void_p]
     lib.sgs_status.argtypes = [c_void_p]
+    lib.sgs_set_timing.argtypes = [c_void_p, c_int32]
+    lib.sgs_stage_times.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int32), c_int32]
     lib.sgs_destroy.argtypes = [c_void_p]
     lib.sgs_destroy.restype = None
     lib.sgs_strerror.argtypes = [c_int32]
     lib.sgs_strerror.restype = ctypes.c_char_p
     for f in ("sgs_workspace_bytes", "sgs_init", "sgs_pair_eval", "sgs_step", "sgs_energy",
-              "sgs_observables", "sgs_status"):
+              "sgs_observables", "sgs_status", "sgs_set_timing", "sgs_stage_times"):
         getattr(lib, f).restype = c_int32
     _lib = lib
     return lib
@@ -191,6 +194,16 @@ class SGS:
         _check(self.lib.sgs_observables(self.ctx, int(kind), ia, len(iargs), da, len(dargs), out.data_ptr()),
                "sgs_observables")
         return out
+
+    def set_timing(self, on: bool = True):
+        _check(self.lib.sgs_set_timing(self.ctx, 1 if on else 0), "sgs_set_timing")
+
+    def stage_times(self):
+        """{stage: (milliseconds, launches)} recorded since the previous call."""
+        ms = (c_double * len(STAGES))()
+        ln = (c_int32 * len(STAGES))()
+        _check(self.lib.sgs_stage_times(self.ctx, ms, ln, len(STAGES)), "sgs_stage_times")
+        return {name: (ms[i], ln[i]) for i, name in enumerate(STAGES)}
 
     def status(self) -> int:
         return int(self.lib.sgs_status(self.ctx))

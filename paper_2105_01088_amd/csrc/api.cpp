@@ -80,6 +80,44 @@ GemmJob job(const double* A, int lda, int ta, const double* B, int ldb, int tb, 
 
 }  // namespace
 
+struct StageTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> rec;
+  int cur_stage = -1;
+  hipEvent_t cur = nullptr;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void begin(int stage, hipStream_t s) {
+    if (!on) return;
+    cur = get();
+    cur_stage = stage;
+    if (cur) (void)hipEventRecord(cur, s);
+  }
+  void end(hipStream_t s) {
+    if (!on || !cur) return;
+    hipEvent_t e = get();
+    if (!e) return;
+    (void)hipEventRecord(e, s);
+    rec.push_back({cur_stage, cur, e});
+    cur = nullptr;
+  }
+  ~StageTimer() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 struct sgs_ctx {
   std::vector<Prob> pr;
   hipStream_t s = nullptr;
@@ -87,6 +125,7 @@ struct sgs_ctx {
   int* status = nullptr;
   int lds_max = 65536;
   bool evaluated = false;
+  StageTimer timer;
 };
 
 // ---------------------------------------------------------------------------
@@ -176,7 +215,7 @@ static void carve(Prob& q, Arena& ar) {
   q.impos = ar.take<int>(n);
   q.q_idx = ar.take<int>(std::max(1, 4 * q.nq));
   q.q_loc = ar.take<int>(std::max(1, 4 * q.nq));
-  q.resid = ar.take<unsigned long long>(1);
+  q.resid = ar.take<unsigned long long>(72);  // [0]: validation; [8 + it]: polar iterations
   q.nsctl = ar.take<int>(4);
   q.terms = ar.take<ForceTerm>((size_t)R * R);
 }
@@ -391,8 +430,8 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
 // ---------------------------------------------------------------------------
 // stages
 // ---------------------------------------------------------------------------
-static hipError_t run_gemm(const JobTable& t, hipStream_t s, const int* ctl = nullptr, int it = 0) {
-  return launch_gemm(t.dev, (int)t.host.size(), t.ntiles, t.cplx, s, ctl, it);
+static hipError_t run_gemm(const JobTable& t, hipStream_t s) {
+  return launch_gemm(t.dev, (int)t.host.size(), t.ntiles, t.cplx, s);
 }
 
 #define HCHK(x)                               \
@@ -405,8 +444,10 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
   hipStream_t s = c->s;
   const int n = q.n, P = q.P, R = q.R;
   const long long nn = (long long)n * n;
+  StageTimer& tm = c->timer;
   if (P > 0) {
     // overlap magnitudes and W = (Gamma_a + Gamma_b)^{-1}
+    tm.begin(SGS_STAGE_INVERSE, s);
     HCHK(launch_pair_sum(q.gam, n, q.pa, q.pb, P, q.W, q.logdet, s));
     for (size_t t = 0; t < q.gj_k.size(); ++t) {
       HCHK(launch_gj_panel(q.W, nn, P, n, q.gj_k[t], q.gj_b[t], q.gjE, (long long)n * GJ_NB_MAX, q.gjB,
@@ -414,25 +455,34 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
       HCHK(run_gemm(q.jgj[t], s));
     }
     HCHK(launch_gj_unscramble(q.W, nn, P, n, q.piv, s));
+    tm.end(s);
     // transition matrices
+    tm.begin(SGS_STAGE_DELTA, s);
     HCHK(run_gemm(q.jdi, s));
+    tm.end(s);
   }
   // Hamiltonian elements, Fock corrections, Y = Delta F
+  tm.begin(SGS_STAGE_WICK, s);
   HamDev h{n, q.nnz_up, q.nq, q.M, q.up_k, q.up_l, q.up_v, q.q_idx, q.q_loc, q.q_val, q.e0};
   HCHK(launch_eps_fock(h, P, R, q.W, q.Di, q.gam, q.pa, q.pb, q.eps, q.Fc, s));
   SparseA sa{q.colptr, q.rowidx, q.colval, q.imp, q.impos, q.M};
   HCHK(launch_apply_fock(sa, n, P, R, q.W, q.Di, q.gam, q.Fc, q.Y, q.Yd, s));
+  tm.end(s);
   // phases
   if (q.Q > 0) {
+    tm.begin(SGS_STAGE_PHASE, s);
     HCHK(run_gemm(q.jt1, s));
     HCHK(run_gemm(q.jxr, s));
     HCHK(launch_build_c(n, q.gam, q.T1, q.Xr, q.qa, q.qb, q.Q, q.Cm, s));
+    tm.end(s);
+    tm.begin(SGS_STAGE_PFAFFIAN, s);
     HCHK(launch_pf_zero(q.UV, q.Q * q.uvstride, s));
     for (size_t t = 0; t < q.pf_p0.size(); ++t) {
       HCHK(launch_pf_panel(q.Cm, 2 * nn, q.Q, n, q.pf_p0[t], PF_NBH, q.UV, q.RM, q.uvstride, q.uv_im, q.pfacc,
                            c->status, s));
       HCHK(run_gemm(q.jpf[t], s));
     }
+    tm.end(s);
   }
   SolveArgs a;
   a.N = q.N; a.R = R; a.P = P;
@@ -444,7 +494,9 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
   a.energy_slot = energy_slot; a.status = c->status;
   a.g_thr = c->opt.g_rel_threshold;
   a.weight = c->opt.weight;
+  tm.begin(SGS_STAGE_SOLVE, s);
   HCHK(launch_solve(a, s));
+  tm.end(s);
   return hipSuccess;
 }
 
@@ -452,17 +504,27 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
   hipStream_t s = c->s;
   const int n = q.n, R = q.R;
   const long long nn = (long long)n * n;
+  StageTimer& tm = c->timer;
+  tm.begin(SGS_STAGE_FORCE, s);
   HCHK(launch_force(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, q.dG, s));
+  tm.end(s);
   (void)nn;
-  HCHK(launch_euler(q.gam, q.dG, dtau, n, R, q.nsX0, q.nsctl, s));
+  tm.begin(SGS_STAGE_PURIFY, s);
+  const int maxit = c->opt.purify_iters;
+  unsigned long long* rs = q.resid + 8;
+  HCHK(launch_euler(q.gam, q.dG, dtau, n, R, q.nsX0, q.nsctl, rs, maxit, s));
   const double thr = std::min(1e-8, std::sqrt(c->opt.purify_tol));
-  for (int it = 0; it < c->opt.purify_iters; ++it) {
+  for (int it = 0; it < maxit; ++it) {
     const int par = it & 1;
-    HCHK(run_gemm(q.jnsq[par], s, q.nsctl, it));
-    HCHK(launch_ns_check(q.nsQ, n, R, q.resid, q.nsctl, it, thr, s));
-    HCHK(run_gemm(q.jnsx[par], s, q.nsctl, it));
+    // Q = X X with max|Q + 1| into rs[it]; then X' = X (3 + Q) / 2, which
+    // marks this iteration as the last when rs[it] < thr
+    HCHK(launch_gemm(q.jnsq[par].dev, (int)q.jnsq[par].host.size(), q.jnsq[par].ntiles, false, s, q.nsctl, it,
+                     nullptr, 0.0, rs + it));
+    HCHK(launch_gemm(q.jnsx[par].dev, (int)q.jnsx[par].host.size(), q.jnsx[par].ntiles, false, s, q.nsctl, it,
+                     rs + it, thr, nullptr));
   }
   HCHK(launch_finalize(q.nsX0, q.nsX1, n, R, q.gam, q.nsctl, c->opt.purify_iters, c->status, s));
+  tm.end(s);
   return hipSuccess;
 }
 
@@ -624,6 +686,26 @@ int sgs_status(sgs_ctx* c) {
   const int zero = 0;
   if (hipMemcpy(c->status, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return SGS_EHIP;
   return st;
+}
+
+int sgs_set_timing(sgs_ctx* c, int32_t enable) {
+  if (!c) return SGS_EINVAL;
+  c->timer.on = enable != 0;
+  return SGS_OK;
+}
+
+int sgs_stage_times(sgs_ctx* c, double* ms, int32_t* launches, int32_t nstage) {
+  if (!c || nstage < 0 || (nstage > 0 && (!ms || !launches))) return SGS_EINVAL;
+  if (hipStreamSynchronize(c->s) != hipSuccess) return SGS_EHIP;
+  for (int i = 0; i < nstage; ++i) { ms[i] = 0.0; launches[i] = 0; }
+  for (auto& r : c->timer.rec) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return SGS_EHIP;
+    if (r.stage >= 0 && r.stage < nstage) { ms[r.stage] += t; launches[r.stage] += 1; }
+  }
+  c->timer.rec.clear();
+  c->timer.used = 0;
+  return SGS_OK;
 }
 
 void sgs_destroy(sgs_ctx* c) { delete c; }

@@ -50,11 +50,22 @@ __device__ __forceinline__ int find_job(const Job* __restrict__ jobs, int njobs,
 constexpr int TK = 16;
 constexpr int LDP = 64 + 1;  // LDS row pitch (elements), padded
 
+// Iterative callers (the polar iteration) pass a control word ctl: the launch
+// of iteration `it` exits at once when ctl[0] < it.  rchk (optional) is the
+// residual measured on this iteration's input: if it is below thr, this
+// iteration is the last one (ctl[0] = it).  rmax (optional) receives
+// max |D + 1| over the launch (D square), as an ordered bit pattern.
 template <typename T, typename Job, bool CPLX>
 __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, int njobs,
-                                              const int* __restrict__ ctl, int it) {
-  // iterative callers: skip once the device-side counter says converged
-  if (ctl != nullptr && ctl[0] < it) return;
+                                              int* __restrict__ ctl, int it,
+                                              const unsigned long long* __restrict__ rchk, double thr,
+                                              unsigned long long* __restrict__ rmax) {
+  if (ctl != nullptr) {
+    if (ctl[0] < it) return;
+    if (rchk != nullptr && __longlong_as_double((long long)rchk[0]) < thr) {
+      if (threadIdx.x == 0 && ctl[0] > it) ctl[0] = it;
+    }
+  }
   typedef typename VecOf<T>::type V4;
   constexpr int NP = CPLX ? 2 : 1;
   __shared__ T As[NP][TK][LDP];
@@ -159,6 +170,7 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, int 
   const T* __restrict__ C = J.C;
   T* __restrict__ D = J.D;
   const int ldc = J.ldc, ldd = J.ldd;
+  double rm = 0.0;
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -174,25 +186,39 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, int 
             if (beta != T(0)) v += beta * C[(long long)row * ldc + col + p * J.c_im];
             if (p == 0 && row == col) v += diag;
             D[(long long)row * ldd + col + p * J.d_im] = v;
+            if (rmax != nullptr) rm = fmax(rm, fabs((double)v + (row == col ? 1.0 : 0.0)));
           }
         }
       }
+  if (rmax != nullptr) {
+    __shared__ double red[256];
+    red[threadIdx.x] = rm;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(rmax, (unsigned long long)__double_as_longlong(red[0]));
+  }
 }
 
 hipError_t launch_gemm(const GemmJob* jobs, int njobs, int ntiles, bool cplx, hipStream_t s,
-                       const int* ctl, int it) {
+                       int* ctl, int it, const unsigned long long* rchk, double thr,
+                       unsigned long long* rmax) {
   if (ntiles <= 0) return hipSuccess;
   if (cplx)
-    hipLaunchKernelGGL((k_gemm<double, GemmJob, true>), dim3(ntiles), dim3(256), 0, s, jobs, njobs, ctl, it);
+    hipLaunchKernelGGL((k_gemm<double, GemmJob, true>), dim3(ntiles), dim3(256), 0, s, jobs, njobs, ctl, it,
+                       rchk, thr, rmax);
   else
-    hipLaunchKernelGGL((k_gemm<double, GemmJob, false>), dim3(ntiles), dim3(256), 0, s, jobs, njobs, ctl, it);
+    hipLaunchKernelGGL((k_gemm<double, GemmJob, false>), dim3(ntiles), dim3(256), 0, s, jobs, njobs, ctl, it,
+                       rchk, thr, rmax);
   return hipGetLastError();
 }
 
 hipError_t launch_gemm_f32(const GemmJobF* jobs, int njobs, int ntiles, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_gemm<float, GemmJobF, false>), dim3(ntiles), dim3(256), 0, s, jobs, njobs,
-                     (const int*)nullptr, 0);
+                     (int*)nullptr, 0, (const unsigned long long*)nullptr, 0.0, (unsigned long long*)nullptr);
   return hipGetLastError();
 }
 

@@ -149,30 +149,33 @@ __global__ __launch_bounds__(256) void k_gj_panel(double* __restrict__ Mall, lon
   }
   __syncthreads();
 
-  // multipliers E and the final panel columns (each thread owns whole rows:
-  // all reads of a row precede its writes)
-  for (int i = tid; i < n; i += nt) {
-    if (i < k) {
-      for (int c = 0; c < b; ++c) {
-        double s = 0.0;
-        for (int q = 0; q < b; ++q) s += M[(long long)i * n + k + q] * Dinv[q * b + c];
-        E[(long long)i * b + c] = s;
+  // multipliers E (one thread per (row, column); reads of a row's panel
+  // entries finish before the barrier, the panel columns are written after it)
+  const int rows_per = nt / b;
+  const int cc = tid % b, rs = tid / b;
+  if (rs < rows_per) {
+    for (int i = rs; i < n; i += rows_per) {
+      double sv;
+      if (i < k) {
+        sv = 0.0;
+        const double* mi = M + (long long)i * n + k;
+        for (int q = 0; q < b; ++q) sv += mi[q] * Dinv[q * b + cc];
+      } else if (i < k + b) {
+        const int r = i - k;
+        sv = (r == cc ? 1.0 : 0.0) - Dinv[r * b + cc];
+      } else {
+        const int r = i - k;
+        sv = 0.0;
+        for (int q = cc; q < b; ++q) sv += P[r * pitch + q] * Linv[q * b + cc];
       }
-      for (int c = 0; c < b; ++c) M[(long long)i * n + k + c] = -E[(long long)i * b + c];
-    } else if (i < k + b) {
-      const int r = i - k;
-      for (int c = 0; c < b; ++c) {
-        E[(long long)i * b + c] = (r == c ? 1.0 : 0.0) - Dinv[r * b + c];
-        M[(long long)i * n + k + c] = Dinv[r * b + c];
-      }
-    } else {
-      const int r = i - k;
-      for (int c = 0; c < b; ++c) {
-        double s = 0.0;
-        for (int q = c; q < b; ++q) s += P[r * pitch + q] * Linv[q * b + c];
-        E[(long long)i * b + c] = s;
-        M[(long long)i * n + k + c] = -s;
-      }
+      E[(long long)i * b + cc] = sv;
+    }
+  }
+  __syncthreads();
+  if (rs < rows_per) {
+    for (int i = rs; i < n; i += rows_per) {
+      const bool piv_row = (i >= k && i < k + b);
+      M[(long long)i * n + k + cc] = piv_row ? Dinv[(i - k) * b + cc] : -E[(long long)i * b + cc];
     }
   }
 }

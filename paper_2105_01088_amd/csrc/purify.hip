@@ -15,33 +15,41 @@
 
 namespace sgs {
 
-// grid: R blocks; X = alpha_mu (Gamma + ds dGamma); ctl[0] = "not converged"
+// grid: R blocks; X = alpha_mu (Gamma + ds dGamma); ctl[0] = "not converged";
+// resid[0..nresid) = 0
 __global__ __launch_bounds__(256) void k_euler(const double* __restrict__ gam, const double* __restrict__ dG,
                                                double dtau, int n, double* __restrict__ X,
-                                               int* __restrict__ ctl) {
-  __shared__ double red[256];
+                                               int* __restrict__ ctl, unsigned long long* __restrict__ resid,
+                                               int nresid) {
+  __shared__ double red[4];
+  __shared__ double alpha_s;
   const int mu = blockIdx.x;
   const long long nn = (long long)n * n;
   const double* g = gam + mu * nn;
   const double* d = dG + mu * nn;
   double* x = X + mu * nn;
-  // max column sum of |dGamma| (= max row sum: skew)
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // max row sum of |dGamma| (= max column sum: skew); one wave per row
   double mx = 0.0;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+  for (int i = wv; i < n; i += 4) {
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += fabs(d[(long long)i * n + j]);
+    for (int j = lane; j < n; j += 64) s += fabs(d[(long long)i * n + j]);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     mx = fmax(mx, s);
   }
-  red[threadIdx.x] = mx;
+  if (lane == 0) red[wv] = mx;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    const double nrm = dtau * fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    alpha_s = 1.0 / sqrt(1.0 + nrm * nrm);
   }
-  const double nrm = dtau * red[0];
-  const double alpha = 1.0 / sqrt(1.0 + nrm * nrm);
+  __syncthreads();
+  const double alpha = alpha_s;
   for (long long e = threadIdx.x; e < nn; e += blockDim.x) x[e] = alpha * (g[e] + dtau * d[e]);
-  if (mu == 0 && threadIdx.x == 0) ctl[0] = 0x7fffffff;
+  if (mu == 0) {
+    if (threadIdx.x == 0) ctl[0] = 0x7fffffff;
+    for (int t = threadIdx.x; t < nresid; t += blockDim.x) resid[t] = 0ull;
+  }
 }
 
 __global__ void k_zero_u64(unsigned long long* p) { p[0] = 0ull; }
@@ -102,8 +110,8 @@ static int grid_for(long long total) {
 }
 
 hipError_t launch_euler(const double* gam, const double* dG, double dtau, int n, int R, double* X, int* ctl,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_euler, dim3(R), dim3(256), 0, s, gam, dG, dtau, n, X, ctl);
+                        unsigned long long* resid, int nresid, hipStream_t s) {
+  hipLaunchKernelGGL(k_euler, dim3(R), dim3(256), 0, s, gam, dG, dtau, n, X, ctl, resid, nresid);
   return hipGetLastError();
 }
 

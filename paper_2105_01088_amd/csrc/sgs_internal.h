@@ -47,7 +47,9 @@ constexpr int GEMM_TILE = 64;
 
 // Launch helpers (gemm.hip).  jobs: device table; ntiles: total tiles.
 hipError_t launch_gemm(const GemmJob* jobs, int njobs, int ntiles, bool cplx,
-                       hipStream_t s, const int* ctl = nullptr, int it = 0);
+                       hipStream_t s, int* ctl = nullptr, int it = 0,
+                       const unsigned long long* rchk = nullptr, double thr = 0.0,
+                       unsigned long long* rmax = nullptr);
 hipError_t launch_gemm_f32(const GemmJobF* jobs, int njobs, int ntiles,
                            hipStream_t s);
 
@@ -148,7 +150,7 @@ hipError_t set_solve_lds_limit(size_t bytes);
 hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
                         const int* impos, int M, double* dG, hipStream_t s);
 hipError_t launch_euler(const double* gam, const double* dG, double dtau, int n, int R, double* X,
-                        int* ctl, hipStream_t s);
+                        int* ctl, unsigned long long* resid, int nresid, hipStream_t s);
 hipError_t launch_ns_resid(const double* Q, int n, long long total, unsigned long long* out, hipStream_t s);
 hipError_t launch_ns_check(const double* Q, int n, int R, unsigned long long* resid, int* ctl, int it,
                            double thr, hipStream_t s);
