@@ -16,7 +16,7 @@ using namespace sgs;
 namespace {
 
 constexpr int GJ_NB_MAX = 32;
-constexpr int PF_NBH = 16;
+constexpr int PF_NBH_MAX = 16;
 
 struct Arena {
   char* base;
@@ -43,17 +43,17 @@ struct Prob {
   double e0 = 0.0;
   double* gam = nullptr;
   // dense work
-  double *W, *Di, *Y, *Yd, *T1, *Xr, *Cm, *UV, *RM, *gjE, *gjB, *dG, *nsX0, *nsX1, *nsQ, *Adense;
+  double *W, *Di, *Y, *Yd, *T1, *Xr, *Cm, *Cm2, *UV, *RM, *gjE, *gjB, *dG, *nsX0, *nsX1, *nsQ, *Adense;
   // small
   double *pfacc, *logdet, *eps, *Fc, *coef, *Gt, *ht, *lam, *lamt, *E, *tab_la, *tab_arg, *tab_eps;
   double *up_v, *colval, *q_val;
-  int *piv, *pa, *pb, *qa, *qb, *pidx, *qidx, *up_k, *up_l, *colptr, *rowidx, *imp, *impos, *q_idx, *q_loc;
+  int *piv, *pa, *pb, *qa, *qb, *pidx, *qidx, *up_k, *up_l, *colptr, *rowidx, *imp, *impos, *q_idx, *q_loc, *pfperm;
   unsigned long long* resid;
   int* nsctl;
   ForceTerm* terms;
   JobTable jdi, jt1, jxr, jnsq[2], jnsx[2], jval;
   std::vector<JobTable> jgj, jpf;
-  std::vector<int> gj_k, gj_b, pf_p0;
+  std::vector<int> gj_k, gj_b, pf_m;
   long long uvstride = 0, uv_im = 0;
 };
 
@@ -173,8 +173,10 @@ static void carve(Prob& q, Arena& ar) {
   q.T1 = ar.take<double>(std::max(1LL, (R - 1) * nn));
   q.Xr = ar.take<double>(std::max(1LL, (R - 1) * nn));
   q.Cm = ar.take<double>(std::max(1LL, 2 * Q * nn));
-  q.uvstride = 2LL * n * 2 * PF_NBH;  // planar: re block then im block
-  q.uv_im = (long long)n * 2 * PF_NBH;
+  q.Cm2 = ar.take<double>(std::max(1LL, 2 * Q * nn));
+  q.uvstride = 2LL * n * 2 * PF_NBH_MAX;  // planar: re block then im block
+  q.uv_im = (long long)n * 2 * PF_NBH_MAX;
+  q.pfperm = ar.take<int>(std::max(1LL, (long long)Q * n));
   q.UV = ar.take<double>(std::max(1LL, Q * q.uvstride));
   q.RM = ar.take<double>(std::max(1LL, Q * q.uvstride));
   q.gjE = ar.take<double>(std::max(1LL, (long long)P * n * GJ_NB_MAX));
@@ -225,7 +227,8 @@ static void carve_jobs(Prob& q, Arena& ar) {
   const int ngj = (n + q.gj_nb - 1) / q.gj_nb;
   q.jgj.assign(ngj, JobTable());
   for (auto& t : q.jgj) t.dev = ar.take<GemmJob>(std::max(1, q.P));
-  const int npf = (n + 2 * PF_NBH - 1) / (2 * PF_NBH);
+  int npf = 0;
+  for (int m = n; m > 0; m -= 2 * pf_panel_shape(m).ns) ++npf;
   q.jpf.assign(npf, JobTable());
   for (auto& t : q.jpf) t.dev = ar.take<GemmJob>(std::max(1, q.Q));
   q.jdi.dev = ar.take<GemmJob>(std::max(1, q.P));
@@ -363,24 +366,31 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
                        1.0, 1.0));
   }
   HIPCHK(upload_jobs(q.jt1)); HIPCHK(upload_jobs(q.jxr));
-  // Pfaffian trailing updates: A22 += [U V] [V -U]^T (complex)
-  q.pf_p0.clear();
-  const int ldu = 2 * PF_NBH;
-  for (int p0 = 0, t = 0; p0 < n; p0 += 2 * PF_NBH, ++t) {
-    q.pf_p0.push_back(p0);
-    JobTable& jt = q.jpf[t];
-    jt.host.clear(); jt.ntiles = 0; jt.cplx = true;
-    const int nsteps = std::min(PF_NBH, (n - p0) / 2);
-    const int pe = p0 + 2 * nsteps, m = n - pe;
-    if (m > 0)
-      for (int qq = 0; qq < q.Q; ++qq) {
-        GemmJob j = job(q.UV + qq * q.uvstride + (long long)pe * ldu, ldu, 0, q.RM + qq * q.uvstride + (long long)pe * ldu,
-                        ldu, 1, q.Cm + qq * 2 * nn + (long long)pe * n + pe, n,
-                        q.Cm + qq * 2 * nn + (long long)pe * n + pe, n, m, m, ldu, 1.0, 1.0);
-        j.a_im = q.uv_im; j.b_im = q.uv_im; j.c_im = nn; j.d_im = nn;
-        add_job(jt, j);
-      }
-    HIPCHK(upload_jobs(jt));
+  // Pfaffian panels: panel t reads the compact trailing matrix from buffer
+  // t % 2 and its GEMM writes the next one, read through the panel's
+  // permutation, into the other buffer:  A' = A[perm, perm] + [U V] [V -U]^T
+  q.pf_m.clear();
+  {
+    int t = 0;
+    for (int m = n; m > 0; ++t) {
+      const PfPanelShape sh = pf_panel_shape(m);
+      const int mp = m - 2 * sh.ns, K = 2 * sh.nbh;
+      q.pf_m.push_back(m);
+      JobTable& jt = q.jpf[t];
+      jt.host.clear(); jt.ntiles = 0; jt.cplx = true;
+      double* cin = (t & 1) ? q.Cm2 : q.Cm;
+      double* cout = (t & 1) ? q.Cm : q.Cm2;
+      if (mp > 0)
+        for (int qq = 0; qq < q.Q; ++qq) {
+          GemmJob j = job(q.UV + qq * q.uvstride, K, 0, q.RM + qq * q.uvstride, K, 1, cin + qq * 2 * nn, n,
+                          cout + qq * 2 * nn, n, mp, mp, K, 1.0, 1.0);
+          j.a_im = q.uv_im; j.b_im = q.uv_im; j.c_im = nn; j.d_im = nn;
+          j.cperm = q.pfperm + (long long)qq * n;
+          add_job(jt, j);
+        }
+      HIPCHK(upload_jobs(jt));
+      m = mp;
+    }
   }
   // Newton-Schulz: Q = X X ; X' = 0.5 X Q + 1.5 X (ping-pong)
   for (int par = 0; par < 2; ++par) {
@@ -476,10 +486,10 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
     HCHK(launch_build_c(n, q.gam, q.T1, q.Xr, q.qa, q.qb, q.Q, q.Cm, s));
     tm.end(s);
     tm.begin(SGS_STAGE_PFAFFIAN, s);
-    HCHK(launch_pf_zero(q.UV, q.Q * q.uvstride, s));
-    for (size_t t = 0; t < q.pf_p0.size(); ++t) {
-      HCHK(launch_pf_panel(q.Cm, 2 * nn, q.Q, n, q.pf_p0[t], PF_NBH, q.UV, q.RM, q.uvstride, q.uv_im, q.pfacc,
-                           c->status, s));
+    for (size_t t = 0; t < q.pf_m.size(); ++t) {
+      const double* cin = (t & 1) ? q.Cm2 : q.Cm;
+      HCHK(launch_pf_panel(cin, 2 * nn, nn, n, q.pf_m[t], q.Q, q.UV, q.RM, q.uvstride, q.uv_im, q.pfperm, n,
+                           q.pfacc, t == 0, c->status, s));
       HCHK(run_gemm(q.jpf[t], s));
     }
     tm.end(s);

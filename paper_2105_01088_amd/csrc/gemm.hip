@@ -183,7 +183,11 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, int 
 #pragma unroll
           for (int p = 0; p < NP; ++p) {
             T v = alpha * acc[p][bi][bj][r];
-            if (beta != T(0)) v += beta * C[(long long)row * ldc + col + p * J.c_im];
+            if (beta != T(0)) {
+              const long long co = J.cperm ? (long long)J.cperm[row] * ldc + J.cperm[col]
+                                           : (long long)row * ldc + col;
+              v += beta * C[co + p * J.c_im];
+            }
             if (p == 0 && row == col) v += diag;
             D[(long long)row * ldd + col + p * J.d_im] = v;
             if (rmax != nullptr) rm = fmax(rm, fabs((double)v + (row == col ? 1.0 : 0.0)));

@@ -19,7 +19,7 @@
 namespace sgs {
 
 struct ArgMax {
-  double v;
+  double v;  // |value|
   int i;
 };
 
@@ -29,7 +29,7 @@ __device__ __forceinline__ ArgMax better(ArgMax a, ArgMax b) {
   return a;
 }
 
-// block-wide argmax over 256 threads; red: LDS scratch of 8 entries
+// block-wide argmax (up to 16 waves); red: LDS scratch of 16 entries
 __device__ ArgMax block_argmax(ArgMax x, ArgMax* red) {
   for (int off = 32; off > 0; off >>= 1) {
     ArgMax o;
@@ -46,16 +46,17 @@ __device__ ArgMax block_argmax(ArgMax x, ArgMax* red) {
   return r;
 }
 
-// grid: one workgroup per matrix; dynamic LDS: (n-k)*(b+1) + 3*b*b doubles
-__global__ __launch_bounds__(256) void k_gj_panel(double* __restrict__ Mall, long long mstride,
-                                                  int n, int k, int b,
-                                                  double* __restrict__ Eall, long long estride,
-                                                  double* __restrict__ Ball, long long bstride,
-                                                  int* __restrict__ pivall,
-                                                  double* __restrict__ logdet,
-                                                  int* __restrict__ status) {
+// grid: one workgroup per matrix (up to 1024 threads); dynamic LDS:
+// (n-k)*(b+1) + (n-k) + 3*b*b doubles
+__global__ __launch_bounds__(1024) void k_gj_panel(double* __restrict__ Mall, long long mstride,
+                                                   int n, int k, int b,
+                                                   double* __restrict__ Eall, long long estride,
+                                                   double* __restrict__ Ball, long long bstride,
+                                                   int* __restrict__ pivall,
+                                                   double* __restrict__ logdet,
+                                                   int* __restrict__ status) {
   extern __shared__ double smem[];
-  __shared__ ArgMax red[8];
+  __shared__ ArgMax red[16];
   __shared__ int lpiv[64];
   const int mat = blockIdx.x;
   double* __restrict__ M = Mall + (long long)mat * mstride;
@@ -64,10 +65,11 @@ __global__ __launch_bounds__(256) void k_gj_panel(double* __restrict__ Mall, lon
   int* __restrict__ piv = pivall + (long long)mat * n;
   const int m = n - k;
   const int pitch = b + 1;
-  double* P = smem;                       // m x pitch
-  double* Linv = P + (long long)m * pitch; // b x b
-  double* Uinv = Linv + b * b;            // b x b
-  double* Dinv = Uinv + b * b;            // b x b
+  double* P = smem;                        // m x pitch
+  double* lcol = P + (long long)m * pitch; // m: multipliers of the current column
+  double* Linv = lcol + m;                 // b x b
+  double* Uinv = Linv + b * b;             // b x b
+  double* Dinv = Uinv + b * b;             // b x b
   const int tid = threadIdx.x, nt = blockDim.x;
 
   for (int e = tid; e < m * b; e += nt) {
@@ -84,22 +86,30 @@ __global__ __launch_bounds__(256) void k_gj_panel(double* __restrict__ Mall, lon
     best = block_argmax(best, red);
     // a NaN column leaves the sentinel index: keep the diagonal (status set below)
     const int pr = (best.i >= j && best.i < m) ? best.i : j;
+    const double pv = P[pr * pitch + j];
     if (tid == 0) lpiv[j] = pr;
+    if (!(fabs(pv) > 0.0) || !isfinite(pv)) sing = true;
+    ld += log(fabs(pv));
+    const double inv = 1.0 / pv;
+    // multipliers of the rows below the pivot (reading the pre-swap rows) ...
+    for (int r = j + 1 + tid; r < m; r += nt) lcol[r] = (r == pr ? P[j * pitch + j] : P[r * pitch + j]) * inv;
+    __syncthreads();
+    // ... then the row swap (no thread reads column j of rows j / pr any more)
     if (pr != j)
       for (int c = tid; c < b; c += nt) {
-        double t0 = P[j * pitch + c];
+        const double t0 = P[j * pitch + c];
         P[j * pitch + c] = P[pr * pitch + c];
         P[pr * pitch + c] = t0;
       }
     __syncthreads();
-    const double pv = P[j * pitch + j];
-    if (!(fabs(pv) > 0.0) || !isfinite(pv)) sing = true;
-    ld += log(fabs(pv));
-    const double inv = 1.0 / pv;
-    for (int r = j + 1 + tid; r < m; r += nt) {
-      double l = P[r * pitch + j] * inv;
-      P[r * pitch + j] = l;
-      for (int c = j + 1; c < b; ++c) P[r * pitch + c] -= l * P[j * pitch + c];
+    // rank-1 update of the panel, one thread per element (r > j, c >= j)
+    const int w = b - j;
+    const int tot = (m - j - 1) * w;
+    for (int e = tid; e < tot; e += nt) {
+      const int r = j + 1 + e / w, c = j + e % w;
+      const double l = lcol[r];
+      if (c == j) P[r * pitch + j] = l;
+      else P[r * pitch + c] -= l * P[j * pitch + c];
     }
     __syncthreads();
   }
@@ -209,14 +219,17 @@ __global__ __launch_bounds__(256) void k_gj_unscramble(double* __restrict__ Mall
 }
 
 size_t gj_panel_lds_bytes(int n, int k, int b) {
-  return sizeof(double) * ((size_t)(n - k) * (b + 1) + 3 * (size_t)b * b);
+  return sizeof(double) * ((size_t)(n - k) * (b + 2) + 3 * (size_t)b * b);
 }
 
 hipError_t launch_gj_panel(double* M, long long mstride, int nmat, int n, int k, int b,
                            double* E, long long estride, double* Br, long long bstride,
                            int* piv, double* logdet, int* status, hipStream_t s) {
   size_t lds = gj_panel_lds_bytes(n, k, b);
-  hipLaunchKernelGGL(k_gj_panel, dim3(nmat), dim3(256), lds, s, M, mstride, n, k, b, E, estride,
+  int nt = ((n - k) * b / 4 + 63) / 64 * 64;  // about 4 update elements per thread
+  if (nt > 1024) nt = 1024;
+  if (nt < 256) nt = 256;
+  hipLaunchKernelGGL(k_gj_panel, dim3(nmat), dim3(nt), lds, s, M, mstride, n, k, b, E, estride,
                      Br, bstride, piv, logdet, status);
   return hipGetLastError();
 }

@@ -9,9 +9,9 @@
 // P = [[0, a], [-a, 0]], Pf = a Pf(D + (b1 b0^T - b0 b1^T) / a), b0 / b1 the
 // first two rows of B.  Before each step the largest entry of the current
 // first column is moved to position 1 by a symmetric swap (sign flip).
-// Blocked with delayed updates: inside a panel of nbh steps the current
+// Blocked with delayed updates: inside a panel of NBH steps the current
 // trailing matrix is A + U V^T - V U^T (U = b1, V = b0 / a per step); only the
-// two columns a step needs are formed, and after the panel the whole trailing
+// two columns a step needs are formed, and after the panel the trailing
 // matrix takes A += [U V] [V -U]^T as one complex GEMM.
 #include "sgs_internal.h"
 
@@ -27,6 +27,7 @@ __device__ __forceinline__ CArg cbetter(CArg a, CArg b) {
   return a;
 }
 
+// block-wide argmax (up to 16 waves); red: LDS scratch of 16 entries
 __device__ CArg cblock_argmax(CArg x, CArg* red) {
   for (int off = 32; off > 0; off >>= 1) {
     CArg o;
@@ -43,186 +44,244 @@ __device__ CArg cblock_argmax(CArg x, CArg* red) {
   return r;
 }
 
-// One panel of nbh elimination steps starting at pivot position p0, for every
-// matrix of the batch (one workgroup each).
-//   A   : matrices, planar (re plane, then im plane at +n*n), stride astride
-//   UV  : per matrix n x (2 nbh) planar (im plane at +uv_im): [U | V]
-//   RM  : per matrix n x (2 nbh) planar: [V | -U] (GEMM operand)
-//   acc : per matrix {ln|Pf|, cos arg, sin arg}
-// dynamic LDS: 2 n + 8 nbh doubles
-__global__ __launch_bounds__(256) void k_pf_panel(double* __restrict__ Aall, long long astride,
-                                                  int n, int p0, int nbh,
-                                                  double* __restrict__ UVall, double* __restrict__ RMall,
-                                                  long long uvstride, long long uv_im,
-                                                  double* __restrict__ acc,
-                                                  int* __restrict__ status) {
+// One panel of NBH elimination steps on the compact m x m trailing matrix A
+// (planar, leading dimension ld, imaginary plane at +plane), for every
+// matrix of the batch (one workgroup each).  Logical row l of the panel is
+// owned by thread l % nt (slot l / nt < RPT) and keeps its U and V entries in
+// registers.  Pivoting swaps two entries of a permutation in LDS (logical ->
+// stored index) and exchanges the two rows' registers; the stored matrix is
+// never written during the panel.  At the end the panel writes, for the
+// trailing logical rows l >= 2 NBH, the GEMM operands L = [U | V] and
+// Rm = [V | -U] (row l - 2 NBH, leading dimension 2 NBH) and perm[l]; the
+// trailing GEMM reads the old matrix through that permutation and writes the
+// next, compact trailing matrix into the other buffer.
+//   acc : per matrix {ln|Pf|, cos arg, sin arg}; first: start from Pf = 1
+// dynamic LDS: m ints + 3 (4 NBH + 2) doubles
+template <int NBH, int RPT>
+__global__ __launch_bounds__(512) void k_pf_panel(const double* __restrict__ Aall, long long astride,
+                                                   long long plane, int ld, int m,
+                                                   double* __restrict__ Lall, double* __restrict__ RMall,
+                                                   long long lstride, long long l_im,
+                                                   int* __restrict__ permall, int pstride,
+                                                   double* __restrict__ acc, int first,
+                                                   int* __restrict__ status) {
   extern __shared__ double smem[];
-  __shared__ CArg red[8];
-  const int mat = blockIdx.x;
-  const long long nn = (long long)n * n;
-  double* __restrict__ Ar = Aall + (long long)mat * astride;
-  double* __restrict__ Ai = Ar + nn;
-  double* __restrict__ Ur = UVall + (long long)mat * uvstride;  // U: cols [0, nbh), V: [nbh, 2nbh)
-  double* __restrict__ Ui = Ur + uv_im;
-  double* __restrict__ Rr = RMall + (long long)mat * uvstride;
-  double* __restrict__ Ri = Rr + uv_im;
-  const int ldu = 2 * nbh;
-  double* c0r = smem;
-  double* c0i = c0r + n;
-  double* rowr = c0i + n;   // 4 nbh: U_p re, U_p im, V_p re, V_p im
-  double* rowi = rowr + 4 * nbh;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ CArg red[16];
+  constexpr int BW = 4 * NBH + 2;  // record: U re, U im, V re, V im, c0 re, c0 im
+  int* perm = (int*)smem;
+  double* bc = smem + ((m + 1) / 2);
+  double* sw = bc + BW;  // two records
+  const int mat = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const double* __restrict__ Ar = Aall + (long long)mat * astride;
+  const double* __restrict__ Ai = Ar + plane;
 
-  double la = 0.0, pr = 1.0, pim = 0.0;
-  if (tid == 0 && p0 > 0) { la = acc[mat * 3]; pr = acc[mat * 3 + 1]; pim = acc[mat * 3 + 2]; }
+  double ur[RPT][NBH], ui[RPT][NBH], vr[RPT][NBH], vi[RPT][NBH], c0r[RPT], c0i[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    c0r[r] = 0.0;
+    c0i[r] = 0.0;
+#pragma unroll
+    for (int t = 0; t < NBH; ++t) { ur[r][t] = 0.0; ui[r][t] = 0.0; vr[r][t] = 0.0; vi[r][t] = 0.0; }
+  }
+  for (int l = tid; l < m; l += nt) perm[l] = l;
+  double la = 0.0, phr = 1.0, phi = 0.0;
+  if (tid == 0 && !first) { la = acc[mat * 3]; phr = acc[mat * 3 + 1]; phi = acc[mat * 3 + 2]; }
   bool sing = false;
+  const int ns = min(NBH, m / 2);
+  __syncthreads();
 
-  const int nsteps = min(nbh, (n - p0) / 2);
-  for (int s = 0; s < nsteps; ++s) {
-    const int p = p0 + 2 * s;
-    // row p of U and V
-    for (int t = tid; t < s; t += nt) {
-      rowr[t] = Ur[(long long)p * ldu + t];
-      rowr[nbh + t] = Ui[(long long)p * ldu + t];
-      rowr[2 * nbh + t] = Ur[(long long)p * ldu + nbh + t];
-      rowr[3 * nbh + t] = Ui[(long long)p * ldu + nbh + t];
+#pragma unroll
+  for (int s = 0; s < NBH; ++s) {
+    if (s < ns) {  // uniform: every thread takes the same branch
+    const int p = 2 * s;
+    // broadcast U, V of logical row p
+    if (tid == p % nt) {
+      const int rs = p / nt;
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if (r == rs) {
+#pragma unroll
+          for (int t = 0; t < s; ++t) {
+            bc[t] = ur[r][t]; bc[NBH + t] = ui[r][t]; bc[2 * NBH + t] = vr[r][t]; bc[3 * NBH + t] = vi[r][t];
+          }
+        }
     }
     __syncthreads();
-    // current column p: c0[i] = B[i][p] = -A[p][i] + sum_t (U_i V_p - V_i U_p)
+    // current column p: c0[l] = -A[p][l] + sum_t (U_l V_p - V_l U_p), l > p
+    const long long prow = (long long)perm[p] * ld;
     CArg best{-1.0, 0x7fffffff};
-    for (int i = p + 1 + tid; i < n; i += nt) {
-      double xr = -Ar[(long long)p * n + i], xi = -Ai[(long long)p * n + i];
-      const double* ur = Ur + (long long)i * ldu;
-      const double* ui = Ui + (long long)i * ldu;
-      for (int t = 0; t < s; ++t) {
-        double uir = ur[t], uii = ui[t], vir = ur[nbh + t], vii = ui[nbh + t];
-        double upr = rowr[t], upi = rowr[nbh + t], vpr = rowr[2 * nbh + t], vpi = rowr[3 * nbh + t];
-        xr += uir * vpr - uii * vpi - (vir * upr - vii * upi);
-        xi += uir * vpi + uii * vpr - (vir * upi + vii * upr);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int l = tid + r * nt;
+      if (l > p && l < m) {
+        const long long o = prow + perm[l];
+        double xr = -Ar[o], xi = -Ai[o];
+#pragma unroll
+        for (int t = 0; t < s; ++t) {
+          const double upr = bc[t], upi = bc[NBH + t], vpr = bc[2 * NBH + t], vpi = bc[3 * NBH + t];
+          xr += ur[r][t] * vpr - ui[r][t] * vpi - (vr[r][t] * upr - vi[r][t] * upi);
+          xi += ur[r][t] * vpi + ui[r][t] * vpr - (vr[r][t] * upi + vi[r][t] * upr);
+        }
+        c0r[r] = xr;
+        c0i[r] = xi;
+        best = cbetter(best, CArg{xr * xr + xi * xi, l});
       }
-      c0r[i] = xr;
-      c0i[i] = xi;
-      best = cbetter(best, CArg{xr * xr + xi * xi, i});
     }
     best = cblock_argmax(best, red);
-    // a NaN column leaves the sentinel index: no swap (status set below)
-    const int q = (best.i > p && best.i < n) ? best.i : p + 1;
-    if (q != p + 1) {
-      // symmetric swap of index p+1 and q in the trailing matrix (rows, then columns)
-      for (int j = p + tid; j < n; j += nt) {
-        long long a1 = (long long)(p + 1) * n + j, a2 = (long long)q * n + j;
-        double tr = Ar[a1], ti = Ai[a1];
-        Ar[a1] = Ar[a2]; Ai[a1] = Ai[a2];
-        Ar[a2] = tr; Ai[a2] = ti;
-      }
-      __syncthreads();
-      for (int i = p + tid; i < n; i += nt) {
-        long long a1 = (long long)i * n + p + 1, a2 = (long long)i * n + q;
-        double tr = Ar[a1], ti = Ai[a1];
-        Ar[a1] = Ar[a2]; Ai[a1] = Ai[a2];
-        Ar[a2] = tr; Ai[a2] = ti;
-      }
-      for (int t = tid; t < s; t += nt) {
-        for (int h = 0; h < 2; ++h) {
-          long long a1 = (long long)(p + 1) * ldu + h * nbh + t, a2 = (long long)q * ldu + h * nbh + t;
-          double tr = Ur[a1], ti = Ui[a1];
-          Ur[a1] = Ur[a2]; Ui[a1] = Ui[a2];
-          Ur[a2] = tr; Ui[a2] = ti;
+    const int q = (best.i > p && best.i < m) ? best.i : p + 1;  // NaN column: no swap
+    const bool flip = q != p + 1;
+    if (flip) {
+      // exchange the records of logical rows p+1 and q
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int l = tid + r * nt;
+        if (l == p + 1 || l == q) {
+          double* rec = sw + (l == q ? BW : 0);
+#pragma unroll
+          for (int t = 0; t < s; ++t) {
+            rec[t] = ur[r][t]; rec[NBH + t] = ui[r][t]; rec[2 * NBH + t] = vr[r][t]; rec[3 * NBH + t] = vi[r][t];
+          }
+          rec[4 * NBH] = c0r[r];
+          rec[4 * NBH + 1] = c0i[r];
         }
       }
       if (tid == 0) {
-        double tr = c0r[p + 1], ti = c0i[p + 1];
-        c0r[p + 1] = c0r[q]; c0i[p + 1] = c0i[q];
-        c0r[q] = tr; c0i[q] = ti;
+        const int x = perm[p + 1];
+        perm[p + 1] = perm[q];
+        perm[q] = x;
       }
       __syncthreads();
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int l = tid + r * nt;
+        if (l == p + 1 || l == q) {
+          const double* rec = sw + (l == q ? 0 : BW);
+#pragma unroll
+          for (int t = 0; t < s; ++t) {
+            ur[r][t] = rec[t]; ui[r][t] = rec[NBH + t]; vr[r][t] = rec[2 * NBH + t]; vi[r][t] = rec[3 * NBH + t];
+          }
+          c0r[r] = rec[4 * NBH];
+          c0i[r] = rec[4 * NBH + 1];
+        }
+      }
     }
+    // broadcast row p+1 (after the swap) and its c0
+    if (tid == (p + 1) % nt) {
+      const int rs = (p + 1) / nt;
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if (r == rs) {
+#pragma unroll
+          for (int t = 0; t < s; ++t) {
+            bc[t] = ur[r][t]; bc[NBH + t] = ui[r][t]; bc[2 * NBH + t] = vr[r][t]; bc[3 * NBH + t] = vi[r][t];
+          }
+          bc[4 * NBH] = c0r[r];
+          bc[4 * NBH + 1] = c0i[r];
+        }
+    }
+    __syncthreads();
     // pivot a = B[p][p+1] = -c0[p+1]
-    const double ar = -c0r[p + 1], ai = -c0i[p + 1];
+    const double ar = -bc[4 * NBH], ai = -bc[4 * NBH + 1];
     const double a2 = ar * ar + ai * ai;
     if (tid == 0) {
       if (!(a2 > 0.0) || !isfinite(a2)) sing = true;
-      const double mag = sqrt(a2);
-      la += log(mag);
-      double nr = pr * ar - pim * ai, ni = pr * ai + pim * ar;
-      if (q != p + 1) { nr = -nr; ni = -ni; }
+      la += 0.5 * log(a2);
+      double nr = phr * ar - phi * ai, ni = phr * ai + phi * ar;
+      if (flip) { nr = -nr; ni = -ni; }
       const double nm = 1.0 / sqrt(nr * nr + ni * ni);
-      pr = nr * nm;
-      pim = ni * nm;
+      phr = nr * nm;
+      phi = ni * nm;
     }
-    // row p+1 of U and V (after the swap)
-    for (int t = tid; t < s; t += nt) {
-      rowr[t] = Ur[(long long)(p + 1) * ldu + t];
-      rowr[nbh + t] = Ui[(long long)(p + 1) * ldu + t];
-      rowr[2 * nbh + t] = Ur[(long long)(p + 1) * ldu + nbh + t];
-      rowr[3 * nbh + t] = Ui[(long long)(p + 1) * ldu + nbh + t];
-    }
-    __syncthreads();
     const double inr = ar / a2, ini = -ai / a2;  // 1 / a
-    for (int i = p + 2 + tid; i < n; i += nt) {
-      double xr = -Ar[(long long)(p + 1) * n + i], xi = -Ai[(long long)(p + 1) * n + i];
-      const double* ur = Ur + (long long)i * ldu;
-      const double* ui = Ui + (long long)i * ldu;
-      for (int t = 0; t < s; ++t) {
-        double uir = ur[t], uii = ui[t], vir = ur[nbh + t], vii = ui[nbh + t];
-        double upr = rowr[t], upi = rowr[nbh + t], vpr = rowr[2 * nbh + t], vpi = rowr[3 * nbh + t];
-        xr += uir * vpr - uii * vpi - (vir * upr - vii * upi);
-        xi += uir * vpi + uii * vpr - (vir * upi + vii * upr);
+    const long long prow1 = (long long)perm[p + 1] * ld;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int l = tid + r * nt;
+      if (l > p + 1 && l < m) {
+        const long long o = prow1 + perm[l];
+        double xr = -Ar[o], xi = -Ai[o];
+#pragma unroll
+        for (int t = 0; t < s; ++t) {
+          const double upr = bc[t], upi = bc[NBH + t], vpr = bc[2 * NBH + t], vpi = bc[3 * NBH + t];
+          xr += ur[r][t] * vpr - ui[r][t] * vpi - (vr[r][t] * upr - vi[r][t] * upi);
+          xi += ur[r][t] * vpi + ui[r][t] * vpr - (vr[r][t] * upi + vi[r][t] * upr);
+        }
+        // U[l][s] = b1_l = -c1_l ; V[l][s] = b0_l / a = -c0_l / a
+        ur[r][s] = -xr;
+        ui[r][s] = -xi;
+        const double br = -c0r[r], bi = -c0i[r];
+        vr[r][s] = br * inr - bi * ini;
+        vi[r][s] = br * ini + bi * inr;
       }
-      // U[i][s] = b1_i = B[p+1][i] = -c1_i ; V[i][s] = b0_i / a = -c0_i / a
-      Ur[(long long)i * ldu + s] = -xr;
-      Ui[(long long)i * ldu + s] = -xi;
-      const double br = -c0r[i], bi = -c0i[i];
-      Ur[(long long)i * ldu + nbh + s] = br * inr - bi * ini;
-      Ui[(long long)i * ldu + nbh + s] = br * ini + bi * inr;
     }
     __syncthreads();
-  }
-  // GEMM operand [V | -U] for the trailing rows
-  const int pe = p0 + 2 * nsteps;
-  for (long long e = (long long)pe * ldu + tid; e < (long long)n * ldu; e += nt) {
-    const int t = (int)(e % ldu);
-    const long long i = e / ldu;
-    if (t < nbh) {
-      const bool ok = t < nsteps;
-      Rr[i * ldu + t] = ok ? Ur[i * ldu + nbh + t] : 0.0;
-      Ri[i * ldu + t] = ok ? Ui[i * ldu + nbh + t] : 0.0;
-    } else {
-      const bool ok = (t - nbh) < nsteps;
-      Rr[i * ldu + t] = ok ? -Ur[i * ldu + (t - nbh)] : 0.0;
-      Ri[i * ldu + t] = ok ? -Ui[i * ldu + (t - nbh)] : 0.0;
     }
   }
+  // GEMM operands for the trailing rows, and the permutation
+  const int pe = 2 * ns;
+  double* Lr = Lall + (long long)mat * lstride;
+  double* Li = Lr + l_im;
+  double* Rr = RMall + (long long)mat * lstride;
+  double* Ri = Rr + l_im;
+  int* gperm = permall + (long long)mat * pstride;
+  constexpr int K = 2 * NBH;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int l = tid + r * nt;
+    if (l >= pe && l < m) {
+      const long long o = (long long)(l - pe) * K;
+#pragma unroll
+      for (int t = 0; t < NBH; ++t) {
+        Lr[o + t] = ur[r][t]; Li[o + t] = ui[r][t];
+        Lr[o + NBH + t] = vr[r][t]; Li[o + NBH + t] = vi[r][t];
+        Rr[o + t] = vr[r][t]; Ri[o + t] = vi[r][t];
+        Rr[o + NBH + t] = -ur[r][t]; Ri[o + NBH + t] = -ui[r][t];
+      }
+    }
+  }
+  for (int l = pe + tid; l < m; l += nt) gperm[l - pe] = perm[l];
   if (tid == 0) {
     acc[mat * 3] = la;
-    acc[mat * 3 + 1] = pr;
-    acc[mat * 3 + 2] = pim;
+    acc[mat * 3 + 1] = phr;
+    acc[mat * 3 + 2] = phi;
     if (sing) atomicCAS(status, ST_OK, ST_SINGULAR);
   }
 }
 
-// Zero the unused U/V columns so the trailing GEMM (K = 2 nbh) may read them.
-__global__ void k_pf_zero(double* __restrict__ UVall, long long total) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x)
-    UVall[e] = 0.0;
+size_t pf_panel_lds_bytes(int m, int nbh) {
+  return sizeof(double) * ((size_t)(m + 1) / 2 + 3 * (size_t)(4 * nbh + 2)) + 64;
 }
 
-size_t pf_panel_lds_bytes(int n, int nbh) { return sizeof(double) * (2 * (size_t)n + 8 * (size_t)nbh); }
-
-hipError_t launch_pf_panel(double* A, long long astride, int nmat, int n, int p0, int nbh,
-                           double* UV, double* RM, long long uvstride, long long uv_im,
-                           double* acc, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_pf_panel, dim3(nmat), dim3(256), pf_panel_lds_bytes(n, nbh), s, A, astride, n,
-                     p0, nbh, UV, RM, uvstride, uv_im, acc, status);
-  return hipGetLastError();
+PfPanelShape pf_panel_shape(int m) {
+  PfPanelShape sh;
+  // at most 512 threads (256 VGPRs each): register rows x panel depth fixed
+  if (m <= 512) { sh.nbh = 16; sh.rpt = 1; }
+  else if (m <= 1024) { sh.nbh = 8; sh.rpt = 2; }
+  else if (m <= 2048) { sh.nbh = 4; sh.rpt = 4; }
+  else if (m <= 4096) { sh.nbh = 2; sh.rpt = 8; }
+  else { sh.nbh = 1; sh.rpt = 16; }
+  const int rows = (m + sh.rpt - 1) / sh.rpt;
+  sh.nt = ((rows + 63) / 64) * 64;
+  if (sh.nt > 512) sh.nt = 512;
+  if (sh.nt < 64) sh.nt = 64;
+  sh.ns = sh.nbh < m / 2 ? sh.nbh : m / 2;
+  return sh;
 }
 
-hipError_t launch_pf_zero(double* UV, long long total, hipStream_t s) {
-  int blocks = (int)((total + 255) / 256);
-  if (blocks > 4096) blocks = 4096;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_pf_zero, dim3(blocks), dim3(256), 0, s, UV, total);
+hipError_t launch_pf_panel(const double* A, long long astride, long long plane, int ld, int m, int nmat,
+                           double* L, double* RM, long long lstride, long long l_im, int* perm, int pstride,
+                           double* acc, int first, int* status, hipStream_t s) {
+  const PfPanelShape sh = pf_panel_shape(m);
+  const size_t lds = pf_panel_lds_bytes(m, sh.nbh);
+#define PF_LAUNCH(NB, RP)                                                                               \
+  hipLaunchKernelGGL((k_pf_panel<NB, RP>), dim3(nmat), dim3(sh.nt), lds, s, A, astride, plane, ld, m, L, \
+                     RM, lstride, l_im, perm, pstride, acc, first, status)
+  if (sh.nbh == 16) PF_LAUNCH(16, 1);
+  else if (sh.nbh == 8) PF_LAUNCH(8, 2);
+  else if (sh.nbh == 4) PF_LAUNCH(4, 4);
+  else if (sh.nbh == 2) PF_LAUNCH(2, 8);
+  else PF_LAUNCH(1, 16);
+#undef PF_LAUNCH
   return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ struct GemmJob {
   double alpha, beta, diag;
   int tiles_n;     // ceil(N / 64)
   int tile_begin;  // first global tile index of this job
+  const int* cperm;  // optional: C element (i, j) read at (cperm[i], cperm[j])
 };
 
 // float32 twin used by the precision path (same layout, float operands).
@@ -41,6 +42,7 @@ struct GemmJobF {
   float alpha, beta, diag;
   int tiles_n;
   int tile_begin;
+  const int* cperm;
 };
 
 constexpr int GEMM_TILE = 64;
@@ -130,11 +132,14 @@ hipError_t launch_gj_panel(double* M, long long mstride, int nmat, int n, int k,
 hipError_t launch_gj_unscramble(double* M, long long mstride, int nmat, int n, const int* piv,
                                 hipStream_t s);
 hipError_t set_gj_lds_limit(size_t bytes);
-size_t pf_panel_lds_bytes(int n, int nbh);
-hipError_t launch_pf_panel(double* A, long long astride, int nmat, int n, int p0, int nbh, double* UV,
-                           double* RM, long long uvstride, long long uv_im, double* acc, int* status,
-                           hipStream_t s);
-hipError_t launch_pf_zero(double* UV, long long total, hipStream_t s);
+struct PfPanelShape {
+  int nbh, rpt, nt, ns;
+};
+PfPanelShape pf_panel_shape(int m);
+size_t pf_panel_lds_bytes(int m, int nbh);
+hipError_t launch_pf_panel(const double* A, long long astride, long long plane, int ld, int m, int nmat,
+                           double* L, double* RM, long long lstride, long long l_im, int* perm, int pstride,
+                           double* acc, int first, int* status, hipStream_t s);
 hipError_t launch_pair_sum(const double* gam, int n, const int* pa, const int* pb, int P, double* S,
                            double* logdet, hipStream_t s);
 hipError_t launch_eps_fock(const HamDev& h, int P, int R, const double* W, const double* Di,

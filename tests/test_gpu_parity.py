@@ -156,3 +156,53 @@ def test_anderson_L7_trajectory_and_bounds():
         assert np.abs(x + x.T).max() == 0.0
         assert np.abs(x @ x + np.eye(x.shape[0])).max() < 1e-12
     ctx.close()
+
+
+# ---------------------------------------------------------------- full sizes
+
+def test_anderson_L99_R16_one_step():
+    """The benchmark workload (n = 400, R = 16), in the launch configuration
+    bench.py times, one step against the oracle."""
+    ham, gam, cfg = si.config_problem("anderson_L99_R16")
+    _say("[step] anderson_L99_R16 (n=400, R=16), unit weights")
+    ctx = _ctx(ham, gam, weight=1)
+    e = ctx.step(0.05, 1)
+    assert ctx.status() == 0
+    g_new = ctx.gammas(0).cpu().numpy()
+    ref = osgs.step(ham, gam, 0.05, mode="unit")
+    assert abs(e.cpu().item() - ref.E) < TOL_E * abs(ref.E)
+    assert np.abs(g_new - ref.gammas).max() < TOL_GAMMA
+    ctx.close()
+
+
+def _sampled_tables(name, pairs, phase_pairs):
+    from oracle import gaussian as ga
+    ham, gam, cfg = si.config_problem(name)
+    R = gam.shape[0]
+    _say(f"[pair_eval] {name} (n={ham.n}, R={R}), sampled pairs")
+    ctx = _ctx(ham, gam, weight=1)
+    la, ar, ep = _tables(ctx)
+    hp = ham.poly()
+    for a, b in pairs:
+        ref = ga.log_abs_overlap(gam[a], gam[b])
+        assert abs(la[a, b] - ref) < TOL_TAB * abs(ref)
+        assert la[b, a] == la[a, b]
+        d = ga.delta(gam[b], gam[a])  # Delta^{ba}: eps_ab
+        e_ref = ga.poly_value(d, hp)
+        assert abs(ep[a, b] - e_ref) < TOL_TAB * max(1.0, abs(e_ref))
+    g0 = gam[0]
+    for a, b in phase_pairs:
+        _, ph = ga.triple_product_schur(g0, gam[a], gam[b])
+        assert abs(np.exp(1j * ar[a, b]) - ph) < TOL_TAB
+        assert abs(ar[b, a] + ar[a, b]) < 1e-15
+    for a in range(R):
+        assert ar[0, a] == 0.0
+    ctx.close()
+
+
+def test_anderson_L199_R32_sampled_tables():
+    _sampled_tables("anderson_L199_R32_U1", [(0, 1), (3, 17), (30, 31)], [(1, 2), (5, 29), (30, 31)])
+
+
+def test_two_channel_kondo_L150_R24_sampled_tables():
+    _sampled_tables("tck_L150_R24_J0.3", [(0, 23), (7, 8)], [(1, 23), (11, 12)])
