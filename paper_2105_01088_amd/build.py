@@ -31,6 +31,7 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-mllvm", "-pragma-unroll-threshold=200000",
            "-I", os.path.join(os.path.dirname(HERE), "include"),
            "-o", tmp] + sources()
     if verbose:

@@ -35,6 +35,7 @@ struct JobTable {
   std::vector<GemmJob> host;
   int ntiles = 0;
   bool cplx = false;
+  XcdMap xm{};
 };
 
 struct Prob {
@@ -49,6 +50,7 @@ struct Prob {
   double *up_v, *colval, *q_val;
   int *piv, *pa, *pb, *qa, *qb, *pidx, *qidx, *up_k, *up_l, *colptr, *rowidx, *imp, *impos, *q_idx, *q_loc, *pfperm;
   unsigned long long* resid;
+  unsigned long long* dgnorm;
   int* nsctl;
   ForceTerm* terms;
   JobTable jdi, jt1, jxr, jnsq[2], jnsx[2], jval;
@@ -61,9 +63,38 @@ int gemm_tiles(int M, int N) { return ((M + 63) / 64) * ((N + 63) / 64); }
 
 void add_job(JobTable& t, GemmJob j) {
   j.tiles_n = (j.N + 63) / 64;
-  j.tile_begin = t.ntiles;
+  j.tile_begin = 0;
   t.ntiles += gemm_tiles(j.M, j.N);
   t.host.push_back(j);
+}
+
+// Assign every job to one XCD (largest first, to the least loaded XCD), order
+// the table by XCD and number each XCD's tiles from 0.
+void place_jobs(JobTable& t) {
+  std::vector<int> order(t.host.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return gemm_tiles(t.host[a].M, t.host[a].N) > gemm_tiles(t.host[b].M, t.host[b].N);
+  });
+  std::vector<std::vector<GemmJob>> per(8);
+  int load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i : order) {
+    int x = 0;
+    for (int y = 1; y < 8; ++y)
+      if (load[y] < load[x]) x = y;
+    GemmJob j = t.host[i];
+    j.tile_begin = load[x];
+    load[x] += gemm_tiles(j.M, j.N);
+    per[x].push_back(j);
+  }
+  t.host.clear();
+  t.xm.max_tiles = 0;
+  for (int x = 0; x < 8; ++x) {
+    t.xm.off[x] = (int)t.host.size();
+    for (auto& j : per[x]) t.host.push_back(j);
+    t.xm.max_tiles = std::max(t.xm.max_tiles, load[x]);
+  }
+  t.xm.off[8] = (int)t.host.size();
 }
 
 GemmJob job(const double* A, int lda, int ta, const double* B, int ldb, int tb, const double* C, int ldc,
@@ -202,7 +233,7 @@ static void carve(Prob& q, Arena& ar) {
   q.up_v = ar.take<double>(std::max(1, q.nnz_up));
   q.colval = ar.take<double>(std::max(1, q.nnz));
   q.q_val = ar.take<double>(std::max(1, q.nq));
-  q.piv = ar.take<int>(std::max(1LL, (long long)P * n));
+  q.piv = ar.take<int>(std::max(1LL, 2LL * P * n));  // pivots, then unscramble sources
   q.pa = ar.take<int>(std::max(1, P));
   q.pb = ar.take<int>(std::max(1, P));
   q.qa = ar.take<int>(std::max(1, Q));
@@ -219,6 +250,7 @@ static void carve(Prob& q, Arena& ar) {
   q.q_loc = ar.take<int>(std::max(1, 4 * q.nq));
   q.resid = ar.take<unsigned long long>(72);  // [0]: validation; [8 + it]: polar iterations
   q.nsctl = ar.take<int>(4);
+  q.dgnorm = ar.take<unsigned long long>(32);
   q.terms = ar.take<ForceTerm>((size_t)R * R);
 }
 
@@ -242,10 +274,8 @@ static void carve_jobs(Prob& q, Arena& ar) {
 }
 
 static int pick_gj_nb(int n, int lds_max) {
-  const int cands[4] = {32, 16, 8, 4};
-  for (int b : cands)
-    if (b <= n && gj_panel_lds_bytes(n, 0, b) <= (size_t)lds_max) return b;
-  return std::min(4, n);
+  (void)lds_max;
+  return std::min(gj_panel_shape(n).B, n);
 }
 
 static int device_lds_max() {
@@ -290,6 +320,7 @@ static hipError_t up(T* dev, const std::vector<T>& host) {
 }
 
 static hipError_t upload_jobs(JobTable& t) {
+  place_jobs(t);
   if (t.host.empty()) return hipSuccess;
   return hipMemcpy(t.dev, t.host.data(), t.host.size() * sizeof(GemmJob), hipMemcpyHostToDevice);
 }
@@ -441,7 +472,7 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
 // stages
 // ---------------------------------------------------------------------------
 static hipError_t run_gemm(const JobTable& t, hipStream_t s) {
-  return launch_gemm(t.dev, (int)t.host.size(), t.ntiles, t.cplx, s);
+  return launch_gemm(t.dev, t.xm, t.cplx, s);
 }
 
 #define HCHK(x)                               \
@@ -516,22 +547,20 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
   const long long nn = (long long)n * n;
   StageTimer& tm = c->timer;
   tm.begin(SGS_STAGE_FORCE, s);
-  HCHK(launch_force(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, q.dG, s));
+  HCHK(launch_force(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, q.dG, q.dgnorm, s));
   tm.end(s);
   (void)nn;
   tm.begin(SGS_STAGE_PURIFY, s);
   const int maxit = c->opt.purify_iters;
   unsigned long long* rs = q.resid + 8;
-  HCHK(launch_euler(q.gam, q.dG, dtau, n, R, q.nsX0, q.nsctl, rs, maxit, s));
+  HCHK(launch_euler(q.gam, q.dG, dtau, n, R, q.nsX0, q.nsctl, rs, maxit, q.dgnorm, s));
   const double thr = std::min(1e-8, std::sqrt(c->opt.purify_tol));
   for (int it = 0; it < maxit; ++it) {
     const int par = it & 1;
     // Q = X X with max|Q + 1| into rs[it]; then X' = X (3 + Q) / 2, which
     // marks this iteration as the last when rs[it] < thr
-    HCHK(launch_gemm(q.jnsq[par].dev, (int)q.jnsq[par].host.size(), q.jnsq[par].ntiles, false, s, q.nsctl, it,
-                     nullptr, 0.0, rs + it));
-    HCHK(launch_gemm(q.jnsx[par].dev, (int)q.jnsx[par].host.size(), q.jnsx[par].ntiles, false, s, q.nsctl, it,
-                     rs + it, thr, nullptr));
+    HCHK(launch_gemm(q.jnsq[par].dev, q.jnsq[par].xm, false, s, q.nsctl, it, nullptr, 0.0, rs + it));
+    HCHK(launch_gemm(q.jnsx[par].dev, q.jnsx[par].xm, false, s, q.nsctl, it, rs + it, thr, nullptr));
   }
   HCHK(launch_finalize(q.nsX0, q.nsX1, n, R, q.gam, q.nsctl, c->opt.purify_iters, c->status, s));
   tm.end(s);
@@ -602,7 +631,7 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
   }
   size_t lds_gj = 0, lds_solve = 0;
   for (auto& q : c->pr) {
-    lds_gj = std::max(lds_gj, gj_panel_lds_bytes(q.n, 0, q.gj_nb));
+    lds_gj = std::max(lds_gj, gj_panel_lds_bytes(q.n, 0, gj_panel_shape(q.n).B));
     lds_solve = std::max(lds_solve, solve_lds_bytes(q.R));
   }
   if (set_gj_lds_limit(lds_gj) != hipSuccess || set_solve_lds_limit(lds_solve) != hipSuccess) {

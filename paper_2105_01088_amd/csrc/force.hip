@@ -25,22 +25,33 @@ __device__ __forceinline__ dvec4 mfma64(double a, double b, dvec4 c) {
 constexpr int FTK = 16;
 constexpr int FLP = 64 + 1;
 
-// grid: (ntri, R); block 256.  terms: R*R descriptors (mu-major).
+// grid: 8 * ceil(R / 8) * ntri blocks of 256 threads.  Blocks are dispatched
+// round-robin over the 8 XCDs; block b serves state mu = b % 8 + 8 s on XCD
+// b % 8, so all tiles of a state share that XCD's L2 (every tile of state mu
+// streams the same Y and Delta panels).  terms: R*R descriptors (mu-major);
 // coef: c1 then c2 tables, complex interleaved, R*R each.
 __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceTerm* __restrict__ terms,
                                                const double* __restrict__ coef,
                                                const double* __restrict__ Adense,
                                                const int* __restrict__ impos, int M,
-                                               double* __restrict__ dG) {
-  __shared__ double As[2][FTK][FLP];
-  __shared__ double Bs[2][FTK][FLP];
-  __shared__ double Tt[64][FLP];
+                                               double* __restrict__ dG,
+                                               unsigned long long* __restrict__ nrm) {
+  // K-loop staging (As, Bs) and the epilogue's transposed block (Tt) share LDS
+  __shared__ double lds[2 * 2 * FTK * FLP];
+  typedef double Slab[FTK][FLP];
+  Slab* As = (Slab*)lds;                    // As[2]
+  Slab* Bs = (Slab*)(lds + 2 * FTK * FLP);  // Bs[2]
+  double (*Tt)[FLP] = (double (*)[FLP])lds; // 64 x FLP
 
+  const int ntri = T * (T + 1) / 2;
+  const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
+  const int mu = xcd + 8 * (loc / ntri);
+  if (mu >= R) return;
   // upper-triangular tile index -> (I, J), I <= J
-  int tri = blockIdx.x, I = 0;
+  if (loc % ntri == 0 && threadIdx.x == 0) nrm[mu] = 0ull;  // read by the Euler step after this kernel
+  int tri = loc % ntri, I = 0;
   while (tri >= T - I) { tri -= T - I; ++I; }
   const int J = I + tri;
-  const int mu = blockIdx.y;
   const int row0 = I * 64, col0 = J * 64;
   const long long nn = (long long)n * n;
 
@@ -203,10 +214,11 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
 }
 
 hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
-                        const int* impos, int M, double* dG, hipStream_t s) {
+                        const int* impos, int M, double* dG, unsigned long long* nrm, hipStream_t s) {
   const int T = (n + 63) / 64;
   const int ntri = T * (T + 1) / 2;
-  hipLaunchKernelGGL(k_force, dim3(ntri, R), dim3(256), 0, s, n, R, T, terms, coef, A, impos, M, dG);
+  const int per_xcd = (R + 7) / 8;
+  hipLaunchKernelGGL(k_force, dim3(8 * per_xcd * ntri), dim3(256), 0, s, n, R, T, terms, coef, A, impos, M, dG, nrm);
   return hipGetLastError();
 }
 

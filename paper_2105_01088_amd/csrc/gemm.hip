@@ -1,8 +1,10 @@
 // Grouped GEMM on the CDNA4 matrix cores.
 //
-// One launch runs a whole table of independent jobs of arbitrary (M, N, K):
-// workgroup b finds its job by binary search over the jobs' first-tile
-// indices, so uneven problem sizes share one grid.  Each workgroup computes
+// One launch runs a whole table of independent jobs of arbitrary (M, N, K).
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8), each with its own L2; the host assigns every job to one XCD, so all
+// tiles of a job share the panels of A and B in that XCD's L2.  Workgroup b
+// searches the jobs of XCD b % 8 for local tile b / 8.  Each workgroup computes
 // a 64 x 64 output tile with 4 waves of 32 x 32 (2 x 2 MFMA blocks of
 // 16 x 16); K advances in slabs of 16 staged through LDS, with the next slab
 // prefetched into registers while the current one is multiplied.
@@ -38,8 +40,7 @@ template <> struct VecOf<double> { typedef dvec4 type; };
 template <> struct VecOf<float> { typedef fvec4 type; };
 
 template <typename Job>
-__device__ __forceinline__ int find_job(const Job* __restrict__ jobs, int njobs, int tile) {
-  int lo = 0, hi = njobs - 1;
+__device__ __forceinline__ int find_job(const Job* __restrict__ jobs, int lo, int hi, int tile) {
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
     if (jobs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
@@ -56,7 +57,7 @@ constexpr int LDP = 64 + 1;  // LDS row pitch (elements), padded
 // iteration is the last one (ctl[0] = it).  rmax (optional) receives
 // max |D + 1| over the launch (D square), as an ordered bit pattern.
 template <typename T, typename Job, bool CPLX>
-__global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, int njobs,
+__global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, XcdMap xm,
                                               int* __restrict__ ctl, int it,
                                               const unsigned long long* __restrict__ rchk, double thr,
                                               unsigned long long* __restrict__ rmax) {
@@ -71,9 +72,12 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, int 
   __shared__ T As[NP][TK][LDP];
   __shared__ T Bs[NP][TK][LDP];
 
-  const int tile = blockIdx.x;
-  const int jid = find_job(jobs, njobs, tile);
+  const int x = blockIdx.x & 7;
+  const int tile = blockIdx.x >> 3;
+  if (xm.off[x] >= xm.off[x + 1]) return;
+  const int jid = find_job(jobs, xm.off[x], xm.off[x + 1] - 1, tile);
   const Job& J = jobs[jid];
+  if (tile - J.tile_begin >= J.tiles_n * ((J.M + 63) / 64)) return;
   const T* __restrict__ A = J.A;
   const T* __restrict__ B = J.B;
   const int M = J.M, N = J.N, K = J.K;
@@ -170,6 +174,8 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, int 
   const T* __restrict__ C = J.C;
   T* __restrict__ D = J.D;
   const int ldc = J.ldc, ldd = J.ldd;
+  const int* __restrict__ cperm = J.cperm;
+  const long long cim = J.c_im, dim = J.d_im;
   double rm = 0.0;
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -184,12 +190,11 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, int 
           for (int p = 0; p < NP; ++p) {
             T v = alpha * acc[p][bi][bj][r];
             if (beta != T(0)) {
-              const long long co = J.cperm ? (long long)J.cperm[row] * ldc + J.cperm[col]
-                                           : (long long)row * ldc + col;
-              v += beta * C[co + p * J.c_im];
+              const long long co = cperm ? (long long)cperm[row] * ldc + cperm[col] : (long long)row * ldc + col;
+              v += beta * C[co + p * cim];
             }
             if (p == 0 && row == col) v += diag;
-            D[(long long)row * ldd + col + p * J.d_im] = v;
+            D[(long long)row * ldd + col + p * dim] = v;
             if (rmax != nullptr) rm = fmax(rm, fabs((double)v + (row == col ? 1.0 : 0.0)));
           }
         }
@@ -206,22 +211,20 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, int 
   }
 }
 
-hipError_t launch_gemm(const GemmJob* jobs, int njobs, int ntiles, bool cplx, hipStream_t s,
-                       int* ctl, int it, const unsigned long long* rchk, double thr,
-                       unsigned long long* rmax) {
-  if (ntiles <= 0) return hipSuccess;
+hipError_t launch_gemm(const GemmJob* jobs, const XcdMap& xm, bool cplx, hipStream_t s, int* ctl, int it,
+                       const unsigned long long* rchk, double thr, unsigned long long* rmax) {
+  if (xm.max_tiles <= 0) return hipSuccess;
+  const dim3 grid(8 * xm.max_tiles);
   if (cplx)
-    hipLaunchKernelGGL((k_gemm<double, GemmJob, true>), dim3(ntiles), dim3(256), 0, s, jobs, njobs, ctl, it,
-                       rchk, thr, rmax);
+    hipLaunchKernelGGL((k_gemm<double, GemmJob, true>), grid, dim3(256), 0, s, jobs, xm, ctl, it, rchk, thr, rmax);
   else
-    hipLaunchKernelGGL((k_gemm<double, GemmJob, false>), dim3(ntiles), dim3(256), 0, s, jobs, njobs, ctl, it,
-                       rchk, thr, rmax);
+    hipLaunchKernelGGL((k_gemm<double, GemmJob, false>), grid, dim3(256), 0, s, jobs, xm, ctl, it, rchk, thr, rmax);
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_f32(const GemmJobF* jobs, int njobs, int ntiles, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gemm<float, GemmJobF, false>), dim3(ntiles), dim3(256), 0, s, jobs, njobs,
+hipError_t launch_gemm_f32(const GemmJobF* jobs, const XcdMap& xm, hipStream_t s) {
+  if (xm.max_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gemm<float, GemmJobF, false>), dim3(8 * xm.max_tiles), dim3(256), 0, s, jobs, xm,
                      (int*)nullptr, 0, (const unsigned long long*)nullptr, 0.0, (unsigned long long*)nullptr);
   return hipGetLastError();
 }

@@ -15,23 +15,25 @@
 
 namespace sgs {
 
-// grid: R blocks; X = alpha_mu (Gamma + ds dGamma); ctl[0] = "not converged";
-// resid[0..nresid) = 0
-__global__ __launch_bounds__(256) void k_euler(const double* __restrict__ gam, const double* __restrict__ dG,
-                                               double dtau, int n, double* __restrict__ X,
-                                               int* __restrict__ ctl, unsigned long long* __restrict__ resid,
-                                               int nresid) {
+static int grid_for(long long total) {
+  long long b = (total + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// max row sum of |dGamma_mu| (= max column sum: skew) into nrm[mu] as an
+// ordered bit pattern.  grid: (ceil(n / 16), R); one wave per row.  The force
+// kernel clears nrm[] before it writes dGamma.
+__global__ __launch_bounds__(256) void k_dg_norm(const double* __restrict__ dG, int n,
+                                                 unsigned long long* __restrict__ nrm) {
   __shared__ double red[4];
-  __shared__ double alpha_s;
-  const int mu = blockIdx.x;
+  const int mu = blockIdx.y;
   const long long nn = (long long)n * n;
-  const double* g = gam + mu * nn;
   const double* d = dG + mu * nn;
-  double* x = X + mu * nn;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  // max row sum of |dGamma| (= max column sum: skew); one wave per row
   double mx = 0.0;
-  for (int i = wv; i < n; i += 4) {
+  for (int i = blockIdx.x * 16 + wv; i < min(n, (int)blockIdx.x * 16 + 16); i += 4) {
     double s = 0.0;
     for (int j = lane; j < n; j += 64) s += fabs(d[(long long)i * n + j]);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
@@ -39,14 +41,26 @@ __global__ __launch_bounds__(256) void k_euler(const double* __restrict__ gam, c
   }
   if (lane == 0) red[wv] = mx;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const double nrm = dtau * fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    alpha_s = 1.0 / sqrt(1.0 + nrm * nrm);
+  if (threadIdx.x == 0)
+    atomicMax(nrm + mu, (unsigned long long)__double_as_longlong(fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))));
+}
+
+// X = alpha_mu (Gamma + ds dGamma), alpha_mu = 1/sqrt(1 + (ds |dGamma_mu|_1)^2);
+// also resets the polar iteration's control word and residual slots.
+__global__ __launch_bounds__(256) void k_euler(const double* __restrict__ gam, const double* __restrict__ dG,
+                                               double dtau, int n, int R, double* __restrict__ X,
+                                               const unsigned long long* __restrict__ nrm,
+                                               int* __restrict__ ctl, unsigned long long* __restrict__ resid,
+                                               int nresid) {
+  const long long nn = (long long)n * n, total = nn * R;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int mu = (int)(e / nn);
+    const double t = dtau * __longlong_as_double((long long)nrm[mu]);
+    const double alpha = 1.0 / sqrt(1.0 + t * t);
+    X[e] = alpha * (gam[e] + dtau * dG[e]);
   }
-  __syncthreads();
-  const double alpha = alpha_s;
-  for (long long e = threadIdx.x; e < nn; e += blockDim.x) x[e] = alpha * (g[e] + dtau * d[e]);
-  if (mu == 0) {
+  if (blockIdx.x == 0) {
     if (threadIdx.x == 0) ctl[0] = 0x7fffffff;
     for (int t = threadIdx.x; t < nresid; t += blockDim.x) resid[t] = 0ull;
   }
@@ -102,16 +116,11 @@ __global__ void k_finalize(const double* __restrict__ X0, const double* __restri
   if (blockIdx.x == 0 && threadIdx.x == 0 && c == 0x7fffffff) atomicCAS(status, ST_OK, ST_NOCONV);
 }
 
-static int grid_for(long long total) {
-  long long b = (total + 255) / 256;
-  if (b > 8192) b = 8192;
-  if (b < 1) b = 1;
-  return (int)b;
-}
-
 hipError_t launch_euler(const double* gam, const double* dG, double dtau, int n, int R, double* X, int* ctl,
-                        unsigned long long* resid, int nresid, hipStream_t s) {
-  hipLaunchKernelGGL(k_euler, dim3(R), dim3(256), 0, s, gam, dG, dtau, n, X, ctl, resid, nresid);
+                        unsigned long long* resid, int nresid, unsigned long long* nrm, hipStream_t s) {
+  hipLaunchKernelGGL(k_dg_norm, dim3((n + 15) / 16, R), dim3(256), 0, s, dG, n, nrm);
+  hipLaunchKernelGGL(k_euler, dim3(grid_for((long long)n * n * R)), dim3(256), 0, s, gam, dG, dtau, n, R, X,
+                     (const unsigned long long*)nrm, ctl, resid, nresid);
   return hipGetLastError();
 }
 

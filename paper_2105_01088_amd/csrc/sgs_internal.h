@@ -47,13 +47,19 @@ struct GemmJobF {
 
 constexpr int GEMM_TILE = 64;
 
-// Launch helpers (gemm.hip).  jobs: device table; ntiles: total tiles.
-hipError_t launch_gemm(const GemmJob* jobs, int njobs, int ntiles, bool cplx,
+// Jobs of XCD x occupy table entries [off[x], off[x+1]); their tile_begin
+// counts tiles within that XCD; max_tiles = largest per-XCD tile count.
+struct XcdMap {
+  int off[9];
+  int max_tiles;
+};
+
+// Launch helpers (gemm.hip).  jobs: device table ordered by XCD.
+hipError_t launch_gemm(const GemmJob* jobs, const XcdMap& xm, bool cplx,
                        hipStream_t s, int* ctl = nullptr, int it = 0,
                        const unsigned long long* rchk = nullptr, double thr = 0.0,
                        unsigned long long* rmax = nullptr);
-hipError_t launch_gemm_f32(const GemmJobF* jobs, int njobs, int ntiles,
-                           hipStream_t s);
+hipError_t launch_gemm_f32(const GemmJobF* jobs, const XcdMap& xm, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Status word (device int): first failure wins.
@@ -125,6 +131,10 @@ struct SolveArgs {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+struct GjPanelShape {
+  int B, rpt, nt;
+};
+GjPanelShape gj_panel_shape(int n);
 size_t gj_panel_lds_bytes(int n, int k, int b);
 hipError_t launch_gj_panel(double* M, long long mstride, int nmat, int n, int k, int b, double* E,
                            long long estride, double* Br, long long bstride, int* piv, double* logdet,
@@ -153,9 +163,10 @@ size_t solve_lds_bytes(int R);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 hipError_t set_solve_lds_limit(size_t bytes);
 hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
-                        const int* impos, int M, double* dG, hipStream_t s);
+                        const int* impos, int M, double* dG, unsigned long long* nrm, hipStream_t s);
 hipError_t launch_euler(const double* gam, const double* dG, double dtau, int n, int R, double* X,
-                        int* ctl, unsigned long long* resid, int nresid, hipStream_t s);
+                        int* ctl, unsigned long long* resid, int nresid, unsigned long long* nrm,
+                        hipStream_t s);
 hipError_t launch_ns_resid(const double* Q, int n, long long total, unsigned long long* out, hipStream_t s);
 hipError_t launch_ns_check(const double* Q, int n, int R, unsigned long long* resid, int* ctl, int it,
                            double thr, hipStream_t s);
