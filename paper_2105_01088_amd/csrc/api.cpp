@@ -59,12 +59,15 @@ struct Prob {
   long long uvstride = 0, uv_im = 0;
 };
 
-int gemm_tiles(int M, int N) { return ((M + 63) / 64) * ((N + 63) / 64); }
+int gemm_tiles(int M, int N, int mirror = 0) {
+  const int tm = (M + 63) / 64, tn = (N + 63) / 64;
+  return mirror ? tn * (tn + 1) / 2 : tm * tn;
+}
 
 void add_job(JobTable& t, GemmJob j) {
   j.tiles_n = (j.N + 63) / 64;
   j.tile_begin = 0;
-  t.ntiles += gemm_tiles(j.M, j.N);
+  t.ntiles += gemm_tiles(j.M, j.N, j.mirror);
   t.host.push_back(j);
 }
 
@@ -74,7 +77,7 @@ void place_jobs(JobTable& t) {
   std::vector<int> order(t.host.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return gemm_tiles(t.host[a].M, t.host[a].N) > gemm_tiles(t.host[b].M, t.host[b].N);
+    return gemm_tiles(t.host[a].M, t.host[a].N, t.host[a].mirror) > gemm_tiles(t.host[b].M, t.host[b].N, t.host[b].mirror);
   });
   std::vector<std::vector<GemmJob>> per(8);
   int load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -84,7 +87,7 @@ void place_jobs(JobTable& t) {
       if (load[y] < load[x]) x = y;
     GemmJob j = t.host[i];
     j.tile_begin = load[x];
-    load[x] += gemm_tiles(j.M, j.N);
+    load[x] += gemm_tiles(j.M, j.N, j.mirror);
     per[x].push_back(j);
   }
   t.host.clear();
@@ -385,8 +388,12 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
   // Im Delta^{ba} = 2 Gamma_b W - 1
   q.jdi.host.clear(); q.jdi.ntiles = 0;
   for (int pp = 0; pp < P; ++pp)
-    add_job(q.jdi, job(q.gam + (long long)pb[pp] * nn, n, 0, q.W + pp * nn, n, 0, nullptr, n, q.Di + pp * nn, n,
-                       n, n, n, 2.0, 0.0, -1.0));
+  {
+    GemmJob j = job(q.gam + (long long)pb[pp] * nn, n, 0, q.W + pp * nn, n, 0, nullptr, n, q.Di + pp * nn, n,
+                    n, n, n, 2.0, 0.0, -1.0);
+    j.mirror = -1;  // Im Delta is skew
+    add_job(q.jdi, j);
+  }
   HIPCHK(upload_jobs(q.jdi));
   // phase matrices: T_a = Gamma_0 W_0a ; Re X_a = T_a Gamma_0 + W_0a
   q.jt1.host.clear(); q.jt1.ntiles = 0; q.jxr.host.clear(); q.jxr.ntiles = 0;
@@ -417,6 +424,7 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
                           cout + qq * 2 * nn, n, mp, mp, K, 1.0, 1.0);
           j.a_im = q.uv_im; j.b_im = q.uv_im; j.c_im = nn; j.d_im = nn;
           j.cperm = q.pfperm + (long long)qq * n;
+          j.mirror = -1;  // the trailing matrix stays skew
           add_job(jt, j);
         }
       HIPCHK(upload_jobs(jt));
@@ -430,9 +438,13 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
     q.jnsq[par].host.clear(); q.jnsq[par].ntiles = 0;
     q.jnsx[par].host.clear(); q.jnsx[par].ntiles = 0;
     for (int mu = 0; mu < R; ++mu) {
-      add_job(q.jnsq[par], job(Xin + mu * nn, n, 0, Xin + mu * nn, n, 0, nullptr, n, q.nsQ + mu * nn, n, n, n, n, 1.0, 0.0));
-      add_job(q.jnsx[par], job(Xin + mu * nn, n, 0, q.nsQ + mu * nn, n, 0, Xin + mu * nn, n, Xout + mu * nn, n, n, n, n,
-                               0.5, 1.5));
+      GemmJob jq = job(Xin + mu * nn, n, 0, Xin + mu * nn, n, 0, nullptr, n, q.nsQ + mu * nn, n, n, n, n, 1.0, 0.0);
+      jq.mirror = 1;  // X^2 is symmetric for skew X
+      add_job(q.jnsq[par], jq);
+      GemmJob jx = job(Xin + mu * nn, n, 0, q.nsQ + mu * nn, n, 0, Xin + mu * nn, n, Xout + mu * nn, n, n, n, n,
+                       0.5, 1.5);
+      jx.mirror = -1;  // X (3 + X^2) / 2 is skew
+      add_job(q.jnsx[par], jx);
     }
     HIPCHK(upload_jobs(q.jnsq[par])); HIPCHK(upload_jobs(q.jnsx[par]));
   }

@@ -69,15 +69,18 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, XcdM
   }
   typedef typename VecOf<T>::type V4;
   constexpr int NP = CPLX ? 2 : 1;
-  __shared__ T As[NP][TK][LDP];
-  __shared__ T Bs[NP][TK][LDP];
+  __shared__ T smem_ab[2 * NP * TK * LDP];  // As, Bs; reused by the mirrored write
+  T(*As)[TK][LDP] = (T(*)[TK][LDP])smem_ab;
+  T(*Bs)[TK][LDP] = (T(*)[TK][LDP])(smem_ab + NP * TK * LDP);
 
   const int x = blockIdx.x & 7;
   const int tile = blockIdx.x >> 3;
   if (xm.off[x] >= xm.off[x + 1]) return;
   const int jid = find_job(jobs, xm.off[x], xm.off[x + 1] - 1, tile);
-  const Job& J = jobs[jid];
-  if (tile - J.tile_begin >= J.tiles_n * ((J.M + 63) / 64)) return;
+  const Job J = jobs[jid];  // by value: the fields live in scalar registers
+  const int mirror = J.mirror;
+  const int ntile_job = mirror ? J.tiles_n * (J.tiles_n + 1) / 2 : J.tiles_n * ((J.M + 63) / 64);
+  if (tile - J.tile_begin >= ntile_job) return;
   const T* __restrict__ A = J.A;
   const T* __restrict__ B = J.B;
   const int M = J.M, N = J.N, K = J.K;
@@ -85,13 +88,46 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, XcdM
   const int ta = J.ta, tb = J.tb;
   const long long aim = J.a_im, bim = J.b_im;
   const int t = tile - J.tile_begin;
-  const int row0 = (t / J.tiles_n) * 64;
-  const int col0 = (t % J.tiles_n) * 64;
+  int ti, tj;
+  if (mirror) {  // upper-triangular tile index -> (ti, tj), ti <= tj
+    int tri = t;
+    ti = 0;
+    while (tri >= J.tiles_n - ti) { tri -= J.tiles_n - ti; ++ti; }
+    tj = ti + tri;
+  } else {
+    ti = t / J.tiles_n;
+    tj = t % J.tiles_n;
+  }
+  const int row0 = ti * 64;
+  const int col0 = tj * 64;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
+
+  // C values of this lane's outputs, loaded before the K loop: their latency
+  // hides behind it, and no load of C can wait on a store of D (they may
+  // alias: the in-place updates pass C == D)
+  const T beta = J.beta;
+  const T* __restrict__ C = J.C;
+  const int ldc = J.ldc;
+  const int* __restrict__ cperm = J.cperm;
+  const long long cim = J.c_im;
+  T cval[NP][2][2][4];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wm * 32 + bi * 16 + AccRow<T>::row(lane, r);
+        const int col = col0 + wn * 32 + bj * 16 + (lane & 15);
+        const bool ok = beta != T(0) && row < M && col < N;
+        const long long co = !ok ? 0 : (cperm ? (long long)cperm[row] * ldc + cperm[col] : (long long)row * ldc + col);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) cval[p][bi][bj][r] = ok ? C[co + p * cim] : T(0);
+      }
 
   V4 acc[NP][2][2];
 #pragma unroll
@@ -170,12 +206,10 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, XcdM
     }
   }
 
-  const T alpha = J.alpha, beta = J.beta, diag = J.diag;
-  const T* __restrict__ C = J.C;
-  T* __restrict__ D = J.D;
-  const int ldc = J.ldc, ldd = J.ldd;
-  const int* __restrict__ cperm = J.cperm;
-  const long long cim = J.c_im, dim = J.d_im;
+  const T alpha = J.alpha, diag = J.diag;
+  T* D = J.D;
+  const int ldd = J.ldd;
+  const long long dim = J.d_im;
   double rm = 0.0;
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -188,17 +222,45 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, XcdM
         if (row < M && col < N) {
 #pragma unroll
           for (int p = 0; p < NP; ++p) {
-            T v = alpha * acc[p][bi][bj][r];
-            if (beta != T(0)) {
-              const long long co = cperm ? (long long)cperm[row] * ldc + cperm[col] : (long long)row * ldc + col;
-              v += beta * C[co + p * cim];
-            }
+            T v = alpha * acc[p][bi][bj][r] + beta * cval[p][bi][bj][r];
             if (p == 0 && row == col) v += diag;
             D[(long long)row * ldd + col + p * dim] = v;
             if (rmax != nullptr) rm = fmax(rm, fabs((double)v + (row == col ? 1.0 : 0.0)));
           }
         }
       }
+  if (mirror && ti != tj) {
+    // mirrored block D[col][row] = mirror * D[row][col], transposed through
+    // LDS in two halves of 32 output rows (32 x LDP fits in As + Bs)
+    T(*Tt)[LDP] = (T(*)[LDP])smem_ab;
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        __syncthreads();
+        if (wn == h) {
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int li = wm * 32 + bi * 16 + AccRow<T>::row(lane, r);
+                const int lj = bj * 16 + (lane & 15);  // within the half
+                const int row = row0 + li, col = col0 + h * 32 + lj;
+                T v = T(0);
+                if (row < M && col < N) v = alpha * acc[p][bi][bj][r] + beta * cval[p][bi][bj][r];
+                Tt[lj][li] = v;
+              }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+          const int r = e >> 6, c = e & 63;  // D row col0 + 32 h + r, column row0 + c
+          const int row = col0 + h * 32 + r, col = row0 + c;
+          if (row < N && col < M) D[(long long)row * ldd + col + p * dim] = T(mirror) * Tt[r][c];
+        }
+      }
+  }
   if (rmax != nullptr) {
     __shared__ double red[256];
     red[threadIdx.x] = rm;

@@ -27,6 +27,8 @@ struct GemmJob {
   int tiles_n;     // ceil(N / 64)
   int tile_begin;  // first global tile index of this job
   const int* cperm;  // optional: C element (i, j) read at (cperm[i], cperm[j])
+  int mirror;        // 0, or +1 / -1: D (square) is symmetric / skew; only
+                     // tiles I <= J run and write the mirrored block too
 };
 
 // float32 twin used by the precision path (same layout, float operands).
@@ -43,6 +45,7 @@ struct GemmJobF {
   int tiles_n;
   int tile_begin;
   const int* cperm;
+  int mirror;
 };
 
 constexpr int GEMM_TILE = 64;
