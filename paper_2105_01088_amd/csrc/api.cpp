@@ -54,7 +54,7 @@ struct Prob {
   int* nsctl;
   ForceTerm* terms;
   JobTable jdi, jt1, jxr, jnsq[2], jnsx[2], jval;
-  std::vector<JobTable> jgj, jpf;
+  std::vector<JobTable> jgj0, jgj1, jpf;  // GJ updates: pairs (0, a), then the rest
   std::vector<int> gj_k, gj_b, pf_m;
   long long uvstride = 0, uv_im = 0;
 };
@@ -114,6 +114,8 @@ GemmJob job(const double* A, int lda, int ta, const double* B, int ldb, int tb, 
 
 }  // namespace
 
+constexpr int NSTAGES = 8;  // SGS_STAGE_INVERSE .. SGS_STAGE_PURIFY
+
 struct StageTimer {
   bool on = false;
   std::vector<hipEvent_t> pool;
@@ -123,8 +125,7 @@ struct StageTimer {
     hipEvent_t a, b;
   };
   std::vector<Rec> rec;
-  int cur_stage = -1;
-  hipEvent_t cur = nullptr;
+  hipEvent_t cur[NSTAGES] = {};
   hipEvent_t get() {
     if (used == pool.size()) {
       hipEvent_t e = nullptr;
@@ -133,19 +134,19 @@ struct StageTimer {
     }
     return pool[used++];
   }
+  // stages may overlap (two streams): each stage has its own open event
   void begin(int stage, hipStream_t s) {
     if (!on) return;
-    cur = get();
-    cur_stage = stage;
-    if (cur) (void)hipEventRecord(cur, s);
+    cur[stage] = get();
+    if (cur[stage]) (void)hipEventRecord(cur[stage], s);
   }
-  void end(hipStream_t s) {
-    if (!on || !cur) return;
+  void end(int stage, hipStream_t s) {
+    if (!on || !cur[stage]) return;
     hipEvent_t e = get();
     if (!e) return;
     (void)hipEventRecord(e, s);
-    rec.push_back({cur_stage, cur, e});
-    cur = nullptr;
+    rec.push_back({stage, cur[stage], e});
+    cur[stage] = nullptr;
   }
   ~StageTimer() {
     for (auto e : pool) (void)hipEventDestroy(e);
@@ -155,11 +156,18 @@ struct StageTimer {
 struct sgs_ctx {
   std::vector<Prob> pr;
   hipStream_t s = nullptr;
+  hipStream_t s2 = nullptr;            // the phase chain runs here, forked from s
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   sgs_options opt;
   int* status = nullptr;
   int lds_max = 65536;
   bool evaluated = false;
   StageTimer timer;
+  ~sgs_ctx() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (s2) (void)hipStreamDestroy(s2);
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -260,8 +268,10 @@ static void carve(Prob& q, Arena& ar) {
 static void carve_jobs(Prob& q, Arena& ar) {
   const int n = q.n;
   const int ngj = (n + q.gj_nb - 1) / q.gj_nb;
-  q.jgj.assign(ngj, JobTable());
-  for (auto& t : q.jgj) t.dev = ar.take<GemmJob>(std::max(1, q.P));
+  q.jgj0.assign(ngj, JobTable());
+  q.jgj1.assign(ngj, JobTable());
+  for (auto& t : q.jgj0) t.dev = ar.take<GemmJob>(std::max(1, q.R - 1));
+  for (auto& t : q.jgj1) t.dev = ar.take<GemmJob>(std::max(1, q.P - (q.R - 1)));
   int npf = 0;
   for (int m = n; m > 0; m -= 2 * pf_panel_shape(m).ns) ++npf;
   q.jpf.assign(npf, JobTable());
@@ -378,12 +388,16 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
   for (int k = 0, t = 0; k < n; k += q.gj_nb, ++t) {
     const int b = std::min(q.gj_nb, n - k);
     q.gj_k.push_back(k); q.gj_b.push_back(b);
-    JobTable& jt = q.jgj[t];
-    jt.host.clear(); jt.ntiles = 0;
-    for (int pp = 0; pp < P; ++pp)
-      add_job(jt, job(q.gjE + (long long)pp * n * GJ_NB_MAX, b, 0, q.gjB + (long long)pp * n * GJ_NB_MAX, n, 0,
-                      q.W + pp * nn, n, q.W + pp * nn, n, n, n, b, -1.0, 1.0));
-    HIPCHK(upload_jobs(jt));
+    // pairs are ordered (0,1) .. (0,R-1), (1,2), ...: the first R - 1 feed the phases
+    for (int half = 0; half < 2; ++half) {
+      JobTable& jt = half == 0 ? q.jgj0[t] : q.jgj1[t];
+      jt.host.clear(); jt.ntiles = 0;
+      const int p0 = half == 0 ? 0 : std::min(P, R - 1), p1 = half == 0 ? std::min(P, R - 1) : P;
+      for (int pp = p0; pp < p1; ++pp)
+        add_job(jt, job(q.gjE + (long long)pp * n * GJ_NB_MAX, b, 0, q.gjB + (long long)pp * n * GJ_NB_MAX, n, 0,
+                        q.Di + pp * nn, n, q.Di + pp * nn, n, n, n, b, -1.0, 1.0));
+      HIPCHK(upload_jobs(jt));
+    }
   }
   // Im Delta^{ba} = 2 Gamma_b W - 1
   q.jdi.host.clear(); q.jdi.ntiles = 0;
@@ -498,21 +512,53 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
   const int n = q.n, P = q.P, R = q.R;
   const long long nn = (long long)n * n;
   StageTimer& tm = c->timer;
+  const int P0 = std::min(P, R - 1);  // pairs (0, a): their inverses feed the phases
+  const bool fork = q.Q > 0;
   if (P > 0) {
-    // overlap magnitudes and W = (Gamma_a + Gamma_b)^{-1}
+    // overlap magnitudes and W = (Gamma_a + Gamma_b)^{-1}; the elimination
+    // runs in the Di buffer (overwritten by the transition matrices next)
     tm.begin(SGS_STAGE_INVERSE, s);
-    HCHK(launch_pair_sum(q.gam, n, q.pa, q.pb, P, q.W, q.logdet, s));
-    for (size_t t = 0; t < q.gj_k.size(); ++t) {
-      HCHK(launch_gj_panel(q.W, nn, P, n, q.gj_k[t], q.gj_b[t], q.gjE, (long long)n * GJ_NB_MAX, q.gjB,
-                           (long long)n * GJ_NB_MAX, q.piv, q.logdet, c->status, s));
-      HCHK(run_gemm(q.jgj[t], s));
+    HCHK(launch_pair_sum(q.gam, n, q.pa, q.pb, P, q.Di, q.logdet, s));
+    for (int half = 0; half < 2; ++half) {
+      const int off = half == 0 ? 0 : P0, cnt = half == 0 ? P0 : P - P0;
+      if (cnt > 0) {
+        for (size_t t = 0; t < q.gj_k.size(); ++t) {
+          HCHK(launch_gj_panel(q.Di + off * nn, nn, cnt, n, q.gj_k[t], q.gj_b[t],
+                               q.gjE + (long long)off * n * GJ_NB_MAX, (long long)n * GJ_NB_MAX,
+                               q.gjB + (long long)off * n * GJ_NB_MAX, (long long)n * GJ_NB_MAX,
+                               q.piv + (long long)off * n, q.piv + (long long)(P + off) * n, q.logdet + off,
+                               c->status, s));
+          HCHK(run_gemm(half == 0 ? q.jgj0[t] : q.jgj1[t], s));
+        }
+        HCHK(launch_gj_unscramble(q.Di + off * nn, q.W + off * nn, nn, cnt, n, q.piv + (long long)off * n,
+                                  q.piv + (long long)(P + off) * n, s));
+      }
+      if (half == 0 && fork) {
+        // phases on the second stream, concurrent with the other inverses
+        HCHK(hipEventRecord(c->ev_fork, s));
+        HCHK(hipStreamWaitEvent(c->s2, c->ev_fork, 0));
+        hipStream_t s2 = c->s2;
+        tm.begin(SGS_STAGE_PHASE, s2);
+        HCHK(run_gemm(q.jt1, s2));
+        HCHK(run_gemm(q.jxr, s2));
+        HCHK(launch_build_c(n, q.gam, q.T1, q.Xr, q.qa, q.qb, q.Q, q.Cm, s2));
+        tm.end(SGS_STAGE_PHASE, s2);
+        tm.begin(SGS_STAGE_PFAFFIAN, s2);
+        for (size_t t = 0; t < q.pf_m.size(); ++t) {
+          const double* cin = (t & 1) ? q.Cm2 : q.Cm;
+          HCHK(launch_pf_panel(cin, 2 * nn, nn, n, q.pf_m[t], q.Q, q.UV, q.RM, q.uvstride, q.uv_im, q.pfperm, n,
+                               q.pfacc, t == 0, c->status, s2));
+          HCHK(run_gemm(q.jpf[t], s2));
+        }
+        tm.end(SGS_STAGE_PFAFFIAN, s2);
+        HCHK(hipEventRecord(c->ev_join, s2));
+      }
     }
-    HCHK(launch_gj_unscramble(q.W, nn, P, n, q.piv, s));
-    tm.end(s);
+    tm.end(SGS_STAGE_INVERSE, s);
     // transition matrices
     tm.begin(SGS_STAGE_DELTA, s);
     HCHK(run_gemm(q.jdi, s));
-    tm.end(s);
+    tm.end(SGS_STAGE_DELTA, s);
   }
   // Hamiltonian elements, Fock corrections, Y = Delta F
   tm.begin(SGS_STAGE_WICK, s);
@@ -520,23 +566,8 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
   HCHK(launch_eps_fock(h, P, R, q.W, q.Di, q.gam, q.pa, q.pb, q.eps, q.Fc, s));
   SparseA sa{q.colptr, q.rowidx, q.colval, q.imp, q.impos, q.M};
   HCHK(launch_apply_fock(sa, n, P, R, q.W, q.Di, q.gam, q.Fc, q.Y, q.Yd, s));
-  tm.end(s);
-  // phases
-  if (q.Q > 0) {
-    tm.begin(SGS_STAGE_PHASE, s);
-    HCHK(run_gemm(q.jt1, s));
-    HCHK(run_gemm(q.jxr, s));
-    HCHK(launch_build_c(n, q.gam, q.T1, q.Xr, q.qa, q.qb, q.Q, q.Cm, s));
-    tm.end(s);
-    tm.begin(SGS_STAGE_PFAFFIAN, s);
-    for (size_t t = 0; t < q.pf_m.size(); ++t) {
-      const double* cin = (t & 1) ? q.Cm2 : q.Cm;
-      HCHK(launch_pf_panel(cin, 2 * nn, nn, n, q.pf_m[t], q.Q, q.UV, q.RM, q.uvstride, q.uv_im, q.pfperm, n,
-                           q.pfacc, t == 0, c->status, s));
-      HCHK(run_gemm(q.jpf[t], s));
-    }
-    tm.end(s);
-  }
+  tm.end(SGS_STAGE_WICK, s);
+  if (P > 0 && fork) HCHK(hipStreamWaitEvent(s, c->ev_join, 0));
   SolveArgs a;
   a.N = q.N; a.R = R; a.P = P;
   a.pidx = q.pidx; a.qidx = q.qidx; a.logdet = q.logdet; a.pfacc = q.pfacc; a.eps = q.eps;
@@ -549,7 +580,7 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
   a.weight = c->opt.weight;
   tm.begin(SGS_STAGE_SOLVE, s);
   HCHK(launch_solve(a, s));
-  tm.end(s);
+  tm.end(SGS_STAGE_SOLVE, s);
   return hipSuccess;
 }
 
@@ -560,7 +591,7 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
   StageTimer& tm = c->timer;
   tm.begin(SGS_STAGE_FORCE, s);
   HCHK(launch_force(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, q.dG, q.dgnorm, s));
-  tm.end(s);
+  tm.end(SGS_STAGE_FORCE, s);
   (void)nn;
   tm.begin(SGS_STAGE_PURIFY, s);
   const int maxit = c->opt.purify_iters;
@@ -575,7 +606,7 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
     HCHK(launch_gemm(q.jnsx[par].dev, q.jnsx[par].xm, false, s, q.nsctl, it, rs + it, thr, nullptr));
   }
   HCHK(launch_finalize(q.nsX0, q.nsX1, n, R, q.gam, q.nsctl, c->opt.purify_iters, c->status, s));
-  tm.end(s);
+  tm.end(SGS_STAGE_PURIFY, s);
   return hipSuccess;
 }
 
@@ -652,6 +683,10 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
   }
   for (int p = 0; p < nprob; ++p)
     if ((rc = build_tables(c->pr[p], probs[p]))) { delete c; return rc; }
+  // second stream (default priority) and the fork / join events
+  if (hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) { delete c; return SGS_EHIP; }
   if (hipMemsetAsync(c->status, 0, sizeof(int), c->s) != hipSuccess) { delete c; return SGS_EHIP; }
   // validate the covariance matrices: skew, Gamma^2 = -1
   for (auto& q : c->pr) {

@@ -14,6 +14,8 @@
 // conjugate (sgn = -1 on every imaginary part).
 #include "sgs_internal.h"
 
+#include <type_traits>
+
 namespace sgs {
 
 typedef double dvec4 __attribute__((ext_vector_type(4)));
@@ -71,27 +73,32 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
   // B slab: k kc..kc+15, cols col0..+63 (thread: k tid>>4, 4 consecutive cols)
   const int b_k = tid >> 4, b_j = (tid & 15) * 4;
 
-  for (int b = 0; b < R; ++b) {
-    const ForceTerm tm = terms[mu * R + b];
-    const double x1 = c1t[2 * tm.coef], y1 = c1t[2 * tm.coef + 1];
-    const bool has_im = tm.Yi != nullptr;
+  // one term's GEMM; IM: the term has imaginary planes (uniform per term, so
+  // the matrix-core loop carries no branch)
+  auto run_term = [&](const ForceTerm& tm, double x1, double y1, auto im_tag) {
+    constexpr bool IM = decltype(im_tag)::value;
     const double sg = tm.sgn, ds = tm.dr_scale;
-    double ra[2][4], rb[2][4];
+    const SGS_GLOBAL double* __restrict__ Yr = as_global(tm.Yr);
+    const SGS_GLOBAL double* __restrict__ Yi = as_global(IM ? tm.Yi : tm.Yr);
+    const SGS_GLOBAL double* __restrict__ Dr = as_global(tm.Dr);
+    const SGS_GLOBAL double* __restrict__ Di = as_global(IM ? tm.Di : tm.Dr);
+    // raw prefetch registers: the B operand Re(c1 D) / -Im(c1 D) is formed
+    // when the slab is written to LDS, so the loads of the next slab stay in
+    // flight across the current slab's matrix-core work
+    double ra[2][4], rd[2][4];
     auto load = [&](int kc) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gi = row0 + a_i, gk = kc + a_k + r;
         const bool ok = gi < n && gk < n;
         const long long o = (long long)gi * n + gk;
-        ra[0][r] = ok ? tm.Yr[o] : 0.0;
-        ra[1][r] = (ok && has_im) ? sg * tm.Yi[o] : 0.0;
+        ra[0][r] = ok ? Yr[o] : 0.0;
+        ra[1][r] = (IM && ok) ? Yi[o] : 0.0;
         const int gk2 = kc + b_k, gj = col0 + b_j + r;
         const bool okb = gk2 < n && gj < n;
         const long long ob = (long long)gk2 * n + gj;
-        const double dr = okb ? ds * tm.Dr[ob] : 0.0;
-        const double di = (okb && has_im) ? sg * tm.Di[ob] : 0.0;
-        rb[0][r] = x1 * dr - y1 * di;       // Re(c1 D)
-        rb[1][r] = -(x1 * di + y1 * dr);    // -Im(c1 D)
+        rd[0][r] = okb ? Dr[ob] : 0.0;
+        rd[1][r] = (IM && okb) ? Di[ob] : 0.0;
       }
     };
     load(0);
@@ -99,10 +106,11 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
+        const double dr = ds * rd[0][r], di = sg * rd[1][r];
         As[0][a_k + r][a_i] = ra[0][r];
-        As[1][a_k + r][a_i] = ra[1][r];
-        Bs[0][b_k][b_j + r] = rb[0][r];
-        Bs[1][b_k][b_j + r] = rb[1][r];
+        if (IM) As[1][a_k + r][a_i] = sg * ra[1][r];
+        Bs[0][b_k][b_j + r] = x1 * dr - y1 * di;     // Re(c1 D)
+        if (IM) Bs[1][b_k][b_j + r] = -(x1 * di + y1 * dr);  // -Im(c1 D)
       }
       __syncthreads();
       if (kc + FTK < n) load(kc + FTK);
@@ -113,19 +121,30 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           a0[q] = As[0][kr][wm * 32 + q * 16 + (lane & 15)];
-          a1[q] = As[1][kr][wm * 32 + q * 16 + (lane & 15)];
           b0[q] = Bs[0][kr][wn * 32 + q * 16 + (lane & 15)];
-          b1[q] = Bs[1][kr][wn * 32 + q * 16 + (lane & 15)];
+          if (IM) {
+            a1[q] = As[1][kr][wm * 32 + q * 16 + (lane & 15)];
+            b1[q] = Bs[1][kr][wn * 32 + q * 16 + (lane & 15)];
+          }
         }
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-          for (int bj = 0; bj < 2; ++bj) {
-            acc[bi][bj] = mfma64(a0[bi], b0[bj], acc[bi][bj]);
-            if (has_im) acc[bi][bj] = mfma64(a1[bi], b1[bj], acc[bi][bj]);
-          }
+          for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma64(a0[bi], b0[bj], acc[bi][bj]);
+        if (IM) {
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma64(a1[bi], b1[bj], acc[bi][bj]);
+        }
       }
     }
+  };
+  for (int b = 0; b < R; ++b) {
+    const ForceTerm tm = terms[mu * R + b];
+    const double x1 = c1t[2 * tm.coef], y1 = c1t[2 * tm.coef + 1];
+    if (tm.Yi != nullptr) run_term(tm, x1, y1, std::true_type{});
+    else run_term(tm, x1, y1, std::false_type{});
   }
 
   // ---- remaining terms, per output element (i, j) of this lane ----
@@ -142,20 +161,22 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
     const double x1 = c1t[2 * tm.coef], y1 = c1t[2 * tm.coef + 1];
     const double x2 = c2t[2 * tm.coef], y2 = c2t[2 * tm.coef + 1];
     const bool has_im = tm.Yi != nullptr;
+    const double im = has_im ? 1.0 : 0.0;  // terms without imaginary planes read Yr / Dr in their place
     const double sg = tm.sgn, ds = tm.dr_scale;
+    const SGS_GLOBAL double* __restrict__ Yr = as_global(tm.Yr);
+    const SGS_GLOBAL double* __restrict__ Yi = as_global(has_im ? tm.Yi : tm.Yr);
+    const SGS_GLOBAL double* __restrict__ Dr = as_global(tm.Dr);
+    const SGS_GLOBAL double* __restrict__ Di = as_global(has_im ? tm.Di : tm.Dr);
     sx1 += x1;
     // transposed block: Tt[c][r] = (x1 sg Yi + y1 Yr)(col0 + r, row0 + c)
     __syncthreads();
     for (int e = tid; e < 64 * 64; e += 256) {
       const int r = e >> 6, c = e & 63;
       const int gr = col0 + r, gc = row0 + c;
-      double v = 0.0;
-      if (gr < n && gc < n) {
-        const long long o = (long long)gr * n + gc;
-        v = y1 * tm.Yr[o];
-        if (has_im) v += x1 * sg * tm.Yi[o];
-      }
-      Tt[c][r] = v;
+      const bool ok = gr < n && gc < n;
+      const long long o = ok ? (long long)gr * n + gc : 0;
+      const double v = y1 * Yr[o] + im * x1 * sg * Yi[o];
+      Tt[c][r] = ok ? v : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -167,19 +188,17 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
           const int li = wm * 32 + bi * 16 + 4 * r + (lane >> 4);  // f64 MFMA accumulator row
           const int lj = wn * 32 + bj * 16 + (lane & 15);
           const int gi = row0 + li, gj = col0 + lj;
-          if (gi < n && gj < n) {
-            const long long o = (long long)gi * n + gj;
-            double v = Tt[li][lj] - y1 * tm.Yr[o] + x2 * ds * tm.Dr[o];
-            if (has_im) v += -x1 * sg * tm.Yi[o] - y2 * sg * tm.Di[o];
-            if (M > 0) {
-              const int pi = impos[gi], pj = impos[gj];
-              if (pi >= 0 && pj >= 0) {
-                v += x1 * tm.Fcr[pi * M + pj];
-                if (tm.Fci) v -= y1 * sg * tm.Fci[pi * M + pj];
-              }
+          const bool ok = gi < n && gj < n;
+          const long long o = ok ? (long long)gi * n + gj : 0;
+          double v = Tt[li][lj] - y1 * Yr[o] + x2 * ds * Dr[o] + im * (-x1 * sg * Yi[o] - y2 * sg * Di[o]);
+          if (M > 0 && ok) {
+            const int pi = impos[gi], pj = impos[gj];
+            if (pi >= 0 && pj >= 0) {
+              v += x1 * as_global(tm.Fcr)[pi * M + pj];
+              if (tm.Fci) v -= y1 * sg * as_global(tm.Fci)[pi * M + pj];
             }
-            lin[bi][bj][r] += v;
           }
+          if (ok) lin[bi][bj][r] += v;
         }
   }
 

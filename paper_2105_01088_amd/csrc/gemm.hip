@@ -81,8 +81,8 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, XcdM
   const int mirror = J.mirror;
   const int ntile_job = mirror ? J.tiles_n * (J.tiles_n + 1) / 2 : J.tiles_n * ((J.M + 63) / 64);
   if (tile - J.tile_begin >= ntile_job) return;
-  const T* __restrict__ A = J.A;
-  const T* __restrict__ B = J.B;
+  const SGS_GLOBAL T* __restrict__ A = as_global(J.A);
+  const SGS_GLOBAL T* __restrict__ B = as_global(J.B);
   const int M = J.M, N = J.N, K = J.K;
   const int lda = J.lda, ldb = J.ldb;
   const int ta = J.ta, tb = J.tb;
@@ -110,9 +110,9 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, XcdM
   // hides behind it, and no load of C can wait on a store of D (they may
   // alias: the in-place updates pass C == D)
   const T beta = J.beta;
-  const T* __restrict__ C = J.C;
+  const SGS_GLOBAL T* __restrict__ C = as_global(J.C);
   const int ldc = J.ldc;
-  const int* __restrict__ cperm = J.cperm;
+  const SGS_GLOBAL int* __restrict__ cperm = as_global(J.cperm);
   const long long cim = J.c_im;
   T cval[NP][2][2][4];
 #pragma unroll
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, XcdM
   }
 
   const T alpha = J.alpha, diag = J.diag;
-  T* D = J.D;
+  SGS_GLOBAL T* D = as_global(J.D);
   const int ldd = J.ldd;
   const long long dim = J.d_im;
   double rm = 0.0;

@@ -1,274 +1,347 @@
-// Batched in-place Gauss-Jordan inversion with partial (row) pivoting, for the
-// pair matrices S_ab = Gamma_a + Gamma_b.  W_ab = S_ab^{-1} enters the
-// transition matrix of Eq. (def-delta-matrix), and
-// ln|det S_ab| = sum ln|pivot| gives the overlap magnitude
-// |<a|b>|^2 = 2^{-N} |det S_ab|^{1/2} (Sec. II.B).
+// Batched Gauss-Jordan inversion with partial pivoting, for the pair
+// matrices S_ab = Gamma_a + Gamma_b.  W_ab = S_ab^{-1} enters the transition
+// matrix of Eq. (def-delta-matrix), and ln|det S_ab| = sum ln|pivot| gives the
+// overlap magnitude |<a|b>|^2 = 2^{-N} |det S_ab|^{1/2} (Sec. II.B).
 //
-// Blocked form.  For each column panel J = [k, k+b):
-//   1. k_gj_panel (one workgroup per matrix): LU with partial pivoting of the
-//      (n-k) x b panel held in LDS; the row swaps are applied to the other
-//      columns; with D = (pivot block)^{-1} it writes the multipliers
-//      E (n x b: rows above k: M[i,J] D; pivot rows: 1 - D; rows below:
-//      L21 L11^{-1}), the pivot rows Brow (b x n, zero on J) and the final
-//      panel columns (-E, and D on the pivot rows).
-//   2. grouped GEMM: M <- M - E Brow  (every row, every column outside J).
-// After the last panel, k_gj_unscramble undoes the row pivoting by permuting
-// columns (the swaps taken in reverse order).
+// Pivoting is virtual: rows never move.  Logical row r of the elimination is
+// physical row piv[r], the row chosen as pivot for column r.  For each column
+// panel J = [k, k+b):
+//   1. k_gj_panel (one workgroup per matrix) sweeps the n x b panel with
+//      partial pivoting over the free rows; with D = (pivot block)^-1 it
+//      writes the multipliers E = M[:, J] D for every row (E_i = e_l - D_l on
+//      the pivot row of position l), the final panel columns (-E_i; D_l on
+//      the pivot rows) and Brow = the pivot rows, zero on J.
+//   2. grouped GEMM: M <- M - E Brow over every row and column.
+// Afterwards M[piv[r]][c] = W[r][pi(c)] with pi = piv, and k_gj_unscramble
+// writes W[r][c] = M[piv[r]][piv^-1[c]] into a separate buffer.
 #include "sgs_internal.h"
 
 namespace sgs {
 
-constexpr int GJ_STAGE_DOUBLES = 6144;  // 48 KB of LDS for the row gather
+constexpr int GJ_MAX_WAVES = 8;
 
-struct ArgMax {
-  double v;  // |value|
-  int i;
-};
-
-__device__ __forceinline__ ArgMax better(ArgMax a, ArgMax b) {
-  // larger value wins; ties go to the smaller index (deterministic)
-  if (b.v > a.v || (b.v == a.v && b.i < a.i)) return b;
-  return a;
+// Pivot search key: |v| as an ordered bit pattern with its low 16 bits
+// replaced by 0xffff - row, so one unsigned 64-bit maximum yields the largest
+// entry (to 36 mantissa bits, far inside what partial pivoting needs) and, on
+// ties, the smallest row.  0 means "no candidate".
+__device__ __forceinline__ unsigned long long pivot_key(double v, int row) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(v));
+  return (bits & ~0xffffull) | (unsigned long long)(0xffff - row);
 }
 
-// block-wide argmax (up to 16 waves); red: LDS scratch of 16 entries
-__device__ ArgMax block_argmax(ArgMax x, ArgMax* red) {
-  for (int off = 32; off > 0; off >>= 1) {
-    ArgMax o;
-    o.v = __shfl_xor(x.v, off);
-    o.i = __shfl_xor(x.i, off);
-    x = better(x, o);
-  }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) red[w] = x;
-  __syncthreads();
-  ArgMax r = red[0];
-  for (int k = 1; k < (int)(blockDim.x >> 6); ++k) r = better(r, red[k]);
-  __syncthreads();
-  return r;
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, 0xf, 0xf, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
 }
 
-// Row-owning panel kernel.  Thread t owns the rows i = t + r nt (r < RPT) of
-// the whole matrix and keeps their b panel entries M[i, J] in registers
-// (J = [k, k + b), b <= B).  For the rows i >= k (logical rows l = i - k of
-// the panel) it runs LU with partial pivoting column by column: argmax over
-// the owned entries, the pivot row and the displaced row exchange registers
-// through LDS, and every row below updates itself from the broadcast pivot
-// row (three barriers per column).  Then, with L11 / U11 in LDS, every row
-// solves for its multipliers in registers:
-//   rows above the panel:  E_i = M[i, J] U^-1 L^-1       (M[i, J] <- -E_i)
-//   pivot rows (l < b):    D_l = e_l U^-1 L^-1, E_i = e_l - D_l (M[i, J] <- D_l)
-//   rows below:            E_i = L21_l L^-1              (M[i, J] <- -E_i)
-// The row swaps reach the other columns as one gather of the moved rows, the
-// pivot rows go to Brow (zero on J), and the composed row permutation
-// pi (new row r = old row pi[r]) is kept per matrix; after the last panel
-// src = pi^-1 drives the column unscramble.
-// dynamic LDS: see gj_panel_lds_bytes
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int lane) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
+  return a > b ? a : b;
+}
+
+// Maximum over the 64 lanes of a wave (every lane active), returned uniform.
+// DPP within rows of 16 lanes (swap neighbours, swap pairs, half-row mirror,
+// row mirror), then the four row results are read as scalars.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+  v = umax64(v, dpp_u64<0xb1>(v));   // quad_perm [1,0,3,2]
+  v = umax64(v, dpp_u64<0x4e>(v));   // quad_perm [2,3,0,1]
+  v = umax64(v, dpp_u64<0x141>(v));  // row_half_mirror
+  v = umax64(v, dpp_u64<0x140>(v));  // row_mirror
+  return umax64(umax64(readlane_u64(v, 0), readlane_u64(v, 16)),
+                umax64(readlane_u64(v, 32), readlane_u64(v, 48)));
+}
+
+// Panel kernel.  Thread t owns the physical rows i = t + r nt (r < RPT) and
+// keeps their b panel entries in registers.  The panel is swept column by
+// column with the exchange (Gauss-Jordan pivot) operation: for the pivot row
+// p of column j (pivot a = x[p][j]) every other row takes f = x[i][j] / a,
+// x[i][c] -= f x[p][c] (c != j), x[i][j] = f, and the pivot row becomes
+// x[p][c] = -x[p][c] / a, x[p][j] = 1 / a.  After the b columns the pivot row
+// of position l holds row l of D = (pivot block)^-1 and every other row holds
+// E_i = M[i, J] D, so the panel's outputs are read off the registers.
+//
+// Pivot search, column j: every free row (no pivot yet) offers a key, a wave
+// maximum picks each wave's candidate, whose lane posts the key and its row
+// to LDS; after the one barrier of the column every thread takes the best of
+// the waves' posts.  Posts alternate between two LDS slots.  The next
+// column's key is formed as soon as that column is updated, so its wave
+// maximum overlaps the rest of the row update.
+// The panel moves between HBM and registers through a per-wave LDS tile, so
+// that global loads and stores are row segments rather than one row per lane.
 template <int B, int RPT>
-__global__ __launch_bounds__(512) void k_gj_panel(double* __restrict__ Mall, long long mstride,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gj_panel(double* __restrict__ Mall, long long mstride,
                                                   int n, int k, int b,
                                                   double* __restrict__ Eall, long long estride,
                                                   double* __restrict__ Ball, long long bstride,
-                                                  int* __restrict__ pivall,
+                                                  int* __restrict__ pivall, int* __restrict__ srcall,
                                                   double* __restrict__ logdet,
                                                   int* __restrict__ status) {
-  extern __shared__ double smem[];
-  __shared__ ArgMax red[16];
-  __shared__ double pivrow[B], swrow[B];
-  __shared__ int cnt;
+  constexpr int CB = B < 16 ? B : 16;  // columns per LDS staging pass
+  constexpr int RPI = 64 / CB;          // rows per coalesced load / store
+  constexpr bool PRE = RPT == 1;        // pivot row copied into registers
+  constexpr bool STG = RPT == 1;        // staged loads / stores (register budget)
+  // dynamic LDS: tag (n ints: 1 if the row is a pivot of an earlier panel),
+  // then per wave a 64 x (CB + 1) staging tile, then per wave 64 ints
+  extern __shared__ int tag[];
+  __shared__ unsigned long long skey[2][GJ_MAX_WAVES];
+  __shared__ __attribute__((aligned(16))) double srow[2][GJ_MAX_WAVES][B];
+  __shared__ int pivl[B];
   const int mat = blockIdx.x;
   double* __restrict__ M = Mall + (long long)mat * mstride;
   double* __restrict__ E = Eall + (long long)mat * estride;
   double* __restrict__ Br = Ball + (long long)mat * bstride;
-  int* __restrict__ pi = pivall + (long long)mat * n;
-  int* __restrict__ src = pivall + (long long)gridDim.x * n + (long long)mat * n;
-  const int m = n - k;
+  int* __restrict__ piv = pivall + (long long)mat * n;
+  int* __restrict__ src = srcall + (long long)mat * n;
   const int tid = threadIdx.x, nt = blockDim.x;
-  double* LU = smem;                    // B x (B + 1)
-  int* permr = (int*)(LU + B * (B + 1)); // m: logical row l now holds old logical row permr[l]
-  int* trow = permr + m;                 // moved logical rows (<= 2B)
-  int* pis = trow + 2 * B;               // m: staging of pi
-  double* stage = (double*)(pis + ((m + 1) & ~1));  // gather staging
-  const int stage_cap = GJ_STAGE_DOUBLES;
+  const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
 
+  for (int i = tid; i < n; i += nt) tag[i] = 0;
+  // the panel into registers, through the wave's LDS tile: coalesced loads
+  // of RPI rows x CB columns, then every lane takes its row
+  double* __restrict__ stg = (double*)(tag + ((n + 3) & ~3)) + w * 64 * (CB + 1);
+  int* __restrict__ spos = (int*)((double*)(tag + ((n + 3) & ~3)) + nw * 64 * (CB + 1)) + w * 64;
   double x[RPT][B];
+  if (STG) {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int rbase = r * nt + w * 64;
+#pragma unroll
+      for (int h = 0; h < B / CB; ++h) {
+#pragma unroll
+        for (int s = 0; s < CB; ++s) {
+          const int rr = s * RPI + lane / CB, cc = lane % CB;
+          const int i = rbase + rr, c = h * CB + cc;
+          stg[rr * (CB + 1) + cc] = (i < n && c < b) ? M[(long long)i * n + k + c] : 0.0;
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int cc = 0; cc < CB; ++cc) x[r][h * CB + cc] = stg[lane * (CB + 1) + cc];
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = tid + r * nt;
+#pragma unroll
+      for (int c = 0; c < B; ++c) x[r][c] = (i < n && c < b) ? M[(long long)i * n + k + c] : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int l = tid; l < k; l += nt) tag[piv[l]] = 1;
+  __syncthreads();
+  bool act[RPT];  // free: not a pivot row yet
+  int pos[RPT];   // panel position of a pivot row of this panel, else -1
+  unsigned long long mine[RPT];
+  unsigned long long key = 0;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const int i = tid + r * nt;
-#pragma unroll
-    for (int c = 0; c < B; ++c) x[r][c] = (i < n && c < b) ? M[(long long)i * n + k + c] : 0.0;
+    act[r] = i < n && tag[i] == 0;
+    pos[r] = -1;
+    mine[r] = act[r] ? pivot_key(x[r][0], i) : 0ull;
+    key = umax64(key, mine[r]);
   }
-  for (int l = tid; l < m; l += nt) permr[l] = l;
-  double ld = 0.0;
+  key = wave_max_u64(key);
+  // running |product of pivots| = pm 2^pe; singularity flag (all uniform)
+  double pm = 1.0;
+  int pe = 0;
   bool sing = false;
-  __syncthreads();
 
 #pragma unroll
   for (int j = 0; j < B; ++j) {
     if (j < b) {  // uniform
-      ArgMax best{-1.0, 0x7fffffff};
+      const int par = j & 1;
+      if (lane == 0) skey[par][w] = key;
+      int sel = -1;  // which owned row posts (selected by value, not by address)
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int l = tid + r * nt - k;
-        if (l >= j && l < m) best = better(best, ArgMax{fabs(x[r][j]), l});
-      }
-      best = block_argmax(best, red);
-      const int pr = (best.i >= j && best.i < m) ? best.i : j;  // NaN column: keep the diagonal
+      for (int r = 0; r < RPT; ++r)
+        if (key != 0ull && mine[r] == key) sel = r;
+      if (sel >= 0) {
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int l = tid + r * nt - k;
-        if (l == pr) {
+        for (int c = 0; c < B; ++c) {
+          double v = x[0][c];
 #pragma unroll
-          for (int c = 0; c < B; ++c) pivrow[c] = x[r][c];
-        }
-        if (l == j && pr != j) {
-#pragma unroll
-          for (int c = 0; c < B; ++c) swrow[c] = x[r][c];
+          for (int r = 1; r < RPT; ++r) v = (sel == r) ? x[r][c] : v;
+          srow[par][w][c] = v;
         }
       }
-      if (tid == 0 && pr != j) { const int t0 = permr[j]; permr[j] = permr[pr]; permr[pr] = t0; }
       __syncthreads();
-      const double pv = pivrow[j];
-      if (tid == 0) {
-        if (!(fabs(pv) > 0.0) || !isfinite(pv)) sing = true;
-        ld += log(fabs(pv));
+      unsigned long long kq[GJ_MAX_WAVES];
+#pragma unroll
+      for (int q = 0; q < GJ_MAX_WAVES; ++q) kq[q] = q < nw ? skey[par][q] : 0ull;
+      unsigned long long best = kq[0];
+      int ww = 0;
+#pragma unroll
+      for (int q = 1; q < GJ_MAX_WAVES; ++q)
+        if (kq[q] > best) { best = kq[q]; ww = q; }
+      int p = 0xffff - (int)(best & 0xffffull);
+      const bool bad = best == 0ull || p >= n;
+      if (bad) p = 0;  // cannot happen for b <= n - k; keeps every index in range
+      // the whole pivot row into registers at once (one LDS latency) when
+      // the registers allow, else read in place
+      double prow[PRE ? B : 1];
+      const double* __restrict__ ps = srow[par][ww];
+#pragma unroll
+      for (int c = 0; c < (PRE ? B : 1); ++c) prow[c] = ps[c];
+#define PROW(c) (PRE ? prow[(c) % (PRE ? B : 1)] : ps[c])
+      const double a = bad ? 0.0 : PROW(j);
+      if (bad || !(fabs(a) > 0.0) || !isfinite(a)) sing = true;
+      {
+        int e;
+        pm *= frexp(fabs(a), &e);
+        pe += e;
       }
-      const double inv = 1.0 / pv;
+      // 1 / a: hardware reciprocal and two Newton steps
+      double ra = __builtin_amdgcn_rcp(a);
+      ra = fma(ra, fma(-a, ra, 1.0), ra);
+      ra = fma(ra, fma(-a, ra, 1.0), ra);
+      if (tid == 0) pivl[j] = p;
+      double f[RPT];
+      bool isp[RPT];
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
-        const int l = tid + r * nt - k;
-        if (l == j) {
-#pragma unroll
-          for (int c = 0; c < B; ++c) x[r][c] = pivrow[c];
-        } else if (l == pr) {
-#pragma unroll
-          for (int c = 0; c < B; ++c) x[r][c] = swrow[c];
-        }
-        if (l > j && l < m) {
-          const double f = x[r][j] * inv;
-          x[r][j] = f;
-#pragma unroll
-          for (int c = j + 1; c < B; ++c) x[r][c] -= f * pivrow[c];
+        isp[r] = tid + r * nt == p;
+        f[r] = x[r][j] * ra;
+        if (isp[r]) {
+          act[r] = false;
+          pos[r] = j;
+        } else if (j + 1 < B) {
+          x[r][j + 1] -= f[r] * PROW(j + 1);
         }
       }
+      if (j + 1 < b) {
+        key = 0;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+          const double v = isp[r] ? 0.0 : x[r][(j + 1) % B];
+          mine[r] = act[r] ? pivot_key(v, tid + r * nt) : 0ull;
+          key = umax64(key, mine[r]);
+        }
+        key = wave_max_u64(key);
+      }
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        if (isp[r]) {
+#pragma unroll
+          for (int c = 0; c < B; ++c) x[r][c] = (c == j) ? ra : -x[r][c] * ra;
+        } else {
+#pragma unroll
+          for (int c = 0; c < B; ++c)
+            if (c != j && c != j + 1) x[r][c] -= f[r] * PROW(c);
+          x[r][j] = f[r];
+        }
+      }
+#undef PROW
     }
   }
   if (tid == 0) {
-    logdet[mat] += ld;
+    logdet[mat] += log(pm) + (double)pe * 0.69314718055994530942;
     if (sing) atomicCAS(status, ST_OK, ST_SINGULAR);
   }
-  // L11 / U11 of the pivot block
+  __syncthreads();  // pivl complete
+  // Brow: the pivot rows outside J (zero on J); 16 rows in flight per thread
+  for (int l0 = 0; l0 < b; l0 += 16) {
+    for (int c = tid; c < n; c += nt) {
+      const bool inj = c >= k && c < k + b;
+      double v[16];
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int l = tid + r * nt - k;
-    if (l >= 0 && l < b) {
+      for (int u = 0; u < 16; ++u)
+        v[u] = (l0 + u < b && !inj) ? M[(long long)pivl[l0 + u] * n + c] : 0.0;
 #pragma unroll
-      for (int c = 0; c < B; ++c) LU[l * (B + 1) + c] = x[r][c];
+      for (int u = 0; u < 16; ++u)
+        if (l0 + u < b) Br[(long long)(l0 + u) * n + c] = v[u];
     }
   }
-  __syncthreads();
-  // multipliers, by triangular solves in registers (in place on the row)
+  // panel outputs (pivot rows M[i, J] = D_l, E_i = e_l - D_l; others
+  // M[i, J] = -E_i), through the wave's LDS tile as coalesced row segments
+  if (STG) {
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int i = tid + r * nt;
-    const int l = i - k;
-    if (i < n) {
-      if (l >= 0 && l < b) {
+    for (int r = 0; r < RPT; ++r) {
+      const int rbase = r * nt + w * 64;
+      spos[lane] = pos[r];
 #pragma unroll
-        for (int c = 0; c < B; ++c) x[r][c] = (c == l) ? 1.0 : 0.0;  // pivot row: e_l
+      for (int h = 0; h < B / CB; ++h) {
+#pragma unroll
+        for (int cc = 0; cc < CB; ++cc) stg[lane * (CB + 1) + cc] = x[r][h * CB + cc];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int s = 0; s < CB; ++s) {
+          const int rr = s * RPI + lane / CB, cc = lane % CB;
+          const int i = rbase + rr, c = h * CB + cc;
+          if (i < n && c < b) {
+            const double v = stg[rr * (CB + 1) + cc];
+            const int l = spos[rr];
+            M[(long long)i * n + k + c] = l >= 0 ? v : -v;
+            E[(long long)i * b + c] = l >= 0 ? (c == l ? 1.0 : 0.0) - v : v;
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
       }
-      if (l < b) {
-        // x <- x U^-1 (rows above the panel and pivot rows)
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = tid + r * nt;
+      if (i < n) {
 #pragma unroll
         for (int c = 0; c < B; ++c) {
-          double s = x[r][c];
-#pragma unroll
-          for (int q = 0; q < c; ++q) s -= x[r][q] * LU[q * (B + 1) + c];
-          x[r][c] = (c < b) ? s / LU[c * (B + 1) + c] : 0.0;
+          if (c < b) {
+            const double v = x[r][c];
+            M[(long long)i * n + k + c] = pos[r] >= 0 ? v : -v;
+            E[(long long)i * b + c] = pos[r] >= 0 ? (c == pos[r] ? 1.0 : 0.0) - v : v;
+          }
         }
       }
-      // x <- x L^-1 (L unit lower); below the panel x already holds L21
-#pragma unroll
-      for (int c = B - 1; c >= 0; --c) {
-        double s = x[r][c];
-#pragma unroll
-        for (int q = c + 1; q < B; ++q) s -= x[r][q] * LU[q * (B + 1) + c];
-        x[r][c] = (c < b) ? s : 0.0;
-      }
-      double* ei = E + (long long)i * b;
-      double* mi = M + (long long)i * n + k;
-      if (l >= 0 && l < b) {
-#pragma unroll
-        for (int c = 0; c < B; ++c)
-          if (c < b) { ei[c] = (c == l ? 1.0 : 0.0) - x[r][c]; mi[c] = x[r][c]; }
-      } else {
-#pragma unroll
-        for (int c = 0; c < B; ++c)
-          if (c < b) { ei[c] = x[r][c]; mi[c] = -x[r][c]; }
-      }
     }
   }
-  // rows that moved (and the pivot rows, for Brow); composed permutation
-  if (tid == 0) cnt = 0;
-  if (k == 0)
-    for (int l = tid; l < m; l += nt) pis[l] = permr[l];
-  else
-    for (int l = tid; l < m; l += nt) pis[l] = pi[k + permr[l]];
-  __syncthreads();
-  for (int l = tid; l < m; l += nt) {
-    pi[k + l] = pis[l];
-    if (l < b || permr[l] != l) trow[atomicAdd(&cnt, 1)] = l;
-  }
-  __syncthreads();
-  const int nto = cnt;
-  const int chunk = max(1, min(n, stage_cap / max(1, nto)));
-  for (int c0 = 0; c0 < n; c0 += chunk) {
-    const int cw = min(chunk, n - c0);
-    for (int e = tid; e < nto * cw; e += nt) {
-      const int t = e / cw, c = c0 + e % cw;
-      stage[e] = (c >= k && c < k + b) ? 0.0 : M[(long long)(k + permr[trow[t]]) * n + c];
-    }
-    __syncthreads();
-    for (int e = tid; e < nto * cw; e += nt) {
-      const int t = e / cw, c = c0 + e % cw;
-      const int l = trow[t];
-      if (c < k || c >= k + b) M[(long long)(k + l) * n + c] = stage[e];
-      if (l < b) Br[(long long)l * n + c] = stage[e];
-    }
-    __syncthreads();
-  }
-  // after the last panel: src = pi^-1 for the column unscramble
+  if (tid < b) piv[k + tid] = pivl[tid];
+  // after the last panel: src = piv^-1 for the unscramble
   if (k + b == n) {
-    __syncthreads();
-    for (int c = tid; c < n; c += nt) src[pi[c]] = c;
+    for (int c = tid; c < n; c += nt) src[c < k ? piv[c] : pivl[c - k]] = c;
   }
 }
 
-// grid (matrices, row chunks of 16); out[i][c] = M[i][src[c]] in place
-__global__ __launch_bounds__(256) void k_gj_unscramble(double* __restrict__ Mall, long long mstride,
-                                                       int n, const int* __restrict__ pivall, int rpb) {
-  extern __shared__ double smem[];
-  double* rowbuf = smem;  // rpb rows
+// grid (matrices, row chunks of rpb): W[r][c] = M[piv[r]][src[c]]
+__global__ __launch_bounds__(256) void k_gj_unscramble(const double* __restrict__ Mall, double* __restrict__ Wall,
+                                                       long long mstride, int n, const int* __restrict__ pivall,
+                                                       const int* __restrict__ srcall, int rpb) {
+  extern __shared__ double rowbuf[];  // rpb rows
   const int mat = blockIdx.x;
-  double* M = Mall + (long long)mat * mstride;
-  const int* src = pivall + (long long)gridDim.x * n + (long long)mat * n;
-  const int r0 = blockIdx.y * rpb, r1 = min(n, r0 + rpb);
-  for (long long e = threadIdx.x; e < (long long)(r1 - r0) * n; e += blockDim.x)
-    rowbuf[e] = M[(long long)r0 * n + e];
-  __syncthreads();
-  for (long long e = threadIdx.x; e < (long long)(r1 - r0) * n; e += blockDim.x) {
-    const long long r = e / n, c = e - r * n;
-    M[(long long)(r0 + r) * n + c] = rowbuf[r * n + src[c]];
+  const double* M = Mall + (long long)mat * mstride;
+  double* W = Wall + (long long)mat * mstride;
+  const int* piv = pivall + (long long)mat * n;
+  const int* src = srcall + (long long)mat * n;
+  const int r0 = blockIdx.y * rpb, nr = min(rpb, n - r0);
+  // (indices clamped: a singular matrix, flagged in the status word, may leave
+  // the pivot list short of a permutation)
+  for (int r = 0; r < nr; ++r) {
+    const double* mrow = M + (long long)min(max(piv[r0 + r], 0), n - 1) * n;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) rowbuf[r * n + c] = mrow[c];
   }
+  __syncthreads();
+  for (int r = 0; r < nr; ++r)
+    for (int c = threadIdx.x; c < n; c += blockDim.x)
+      W[(long long)(r0 + r) * n + c] = rowbuf[r * n + min(max(src[c], 0), n - 1)];
 }
 
+// Register budget: the panel (n x B doubles) lives in the registers of one
+// workgroup of at most 512 threads, RPT x B doubles per thread.
 GjPanelShape gj_panel_shape(int n) {
   GjPanelShape sh;
   if (n <= 512) { sh.B = 32; sh.rpt = 1; }
-  else if (n <= 1024) { sh.B = 16; sh.rpt = 2; }
-  else if (n <= 2048) { sh.B = 8; sh.rpt = 4; }
-  else if (n <= 4096) { sh.B = 4; sh.rpt = 8; }
-  else { sh.B = 2; sh.rpt = 16; }
+  else if (n <= 1024) { sh.B = 32; sh.rpt = 2; }
+  else if (n <= 1536) { sh.B = 32; sh.rpt = 3; }
+  else if (n <= 2048) { sh.B = 16; sh.rpt = 4; }
+  else if (n <= 4096) { sh.B = 8; sh.rpt = 8; }
+  else { sh.B = 4; sh.rpt = 16; }
   const int rows = (n + sh.rpt - 1) / sh.rpt;
   sh.nt = ((rows + 63) / 64) * 64;
   if (sh.nt > 512) sh.nt = 512;
@@ -278,45 +351,51 @@ GjPanelShape gj_panel_shape(int n) {
 
 size_t gj_panel_lds_bytes(int n, int k, int b) {
   (void)k;
-  const int m = n;  // largest panel
-  return sizeof(double) * ((size_t)b * (b + 1) + GJ_STAGE_DOUBLES) + sizeof(int) * (2 * (size_t)m + 2 * b + 2) + 64;
+  (void)b;
+  const GjPanelShape sh = gj_panel_shape(n);
+  const int cb = sh.B < 16 ? sh.B : 16;
+  const size_t nw = (size_t)sh.nt / 64;
+  return sizeof(int) * (size_t)((n + 3) & ~3) + nw * 64 * (cb + 1) * sizeof(double) + nw * 64 * sizeof(int) + 64;
 }
 
 hipError_t launch_gj_panel(double* M, long long mstride, int nmat, int n, int k, int b,
                            double* E, long long estride, double* Br, long long bstride,
-                           int* piv, double* logdet, int* status, hipStream_t s) {
+                           int* piv, int* src, double* logdet, int* status, hipStream_t s) {
   const GjPanelShape sh = gj_panel_shape(n);
+  if (b < 1 || b > sh.B || k < 0 || k + b > n || (long long)sh.nt * sh.rpt < n) return hipErrorInvalidValue;
   const size_t lds = gj_panel_lds_bytes(n, k, sh.B);
 #define GJ_LAUNCH(BB, RP)                                                                                    \
   hipLaunchKernelGGL((k_gj_panel<BB, RP>), dim3(nmat), dim3(sh.nt), lds, s, M, mstride, n, k, b, E, estride, \
-                     Br, bstride, piv, logdet, status)
-  if (sh.B == 32) GJ_LAUNCH(32, 1);
-  else if (sh.B == 16) GJ_LAUNCH(16, 2);
-  else if (sh.B == 8) GJ_LAUNCH(8, 4);
-  else if (sh.B == 4) GJ_LAUNCH(4, 8);
-  else GJ_LAUNCH(2, 16);
+                     Br, bstride, piv, src, logdet, status)
+  if (sh.rpt == 1) GJ_LAUNCH(32, 1);
+  else if (sh.rpt == 2) GJ_LAUNCH(32, 2);
+  else if (sh.rpt == 3) GJ_LAUNCH(32, 3);
+  else if (sh.rpt == 4) GJ_LAUNCH(16, 4);
+  else if (sh.rpt == 8) GJ_LAUNCH(8, 8);
+  else GJ_LAUNCH(4, 16);
 #undef GJ_LAUNCH
   return hipGetLastError();
 }
 
-hipError_t launch_gj_unscramble(double* M, long long mstride, int nmat, int n, const int* piv,
-                                hipStream_t s) {
+hipError_t launch_gj_unscramble(const double* M, double* W, long long mstride, int nmat, int n, const int* piv,
+                                const int* src, hipStream_t s) {
   int rpb = (int)(((size_t)48 * 1024 / sizeof(double)) / (size_t)n);  // rows per block, <= 48 KB of LDS
   if (rpb > 16) rpb = 16;
   if (rpb < 1) rpb = 1;
   size_t lds = sizeof(double) * (size_t)rpb * n;
-  hipLaunchKernelGGL(k_gj_unscramble, dim3(nmat, (n + rpb - 1) / rpb), dim3(256), lds, s, M, mstride, n,
-                     piv, rpb);
+  hipLaunchKernelGGL(k_gj_unscramble, dim3(nmat, (n + rpb - 1) / rpb), dim3(256), lds, s, M, W, mstride, n,
+                     piv, src, rpb);
   return hipGetLastError();
 }
 
 hipError_t set_gj_lds_limit(size_t bytes) {
   hipError_t e;
   if ((e = hipFuncSetAttribute((const void*)k_gj_panel<32, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_gj_panel<16, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_gj_panel<8, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_gj_panel<4, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_gj_panel<2, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if ((e = hipFuncSetAttribute((const void*)k_gj_panel<32, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_gj_panel<32, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_gj_panel<16, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_gj_panel<8, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_gj_panel<4, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 }  // namespace sgs

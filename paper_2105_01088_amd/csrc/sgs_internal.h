@@ -50,6 +50,20 @@ struct GemmJobF {
 
 constexpr int GEMM_TILE = 64;
 
+// Pointers read from device-side tables are generic (flat) to the compiler;
+// flat loads also count against the LDS wait counter, which serializes them
+// with the LDS traffic of a K loop.  Kernels cast such pointers to the global
+// address space.
+#define SGS_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const SGS_GLOBAL T* as_global(const T* p) {
+  return (const SGS_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ SGS_GLOBAL T* as_global(T* p) {
+  return (SGS_GLOBAL T*)p;
+}
+
 // Jobs of XCD x occupy table entries [off[x], off[x+1]); their tile_begin
 // counts tiles within that XCD; max_tiles = largest per-XCD tile count.
 struct XcdMap {
@@ -140,10 +154,10 @@ struct GjPanelShape {
 GjPanelShape gj_panel_shape(int n);
 size_t gj_panel_lds_bytes(int n, int k, int b);
 hipError_t launch_gj_panel(double* M, long long mstride, int nmat, int n, int k, int b, double* E,
-                           long long estride, double* Br, long long bstride, int* piv, double* logdet,
+                           long long estride, double* Br, long long bstride, int* piv, int* src, double* logdet,
                            int* status, hipStream_t s);
-hipError_t launch_gj_unscramble(double* M, long long mstride, int nmat, int n, const int* piv,
-                                hipStream_t s);
+hipError_t launch_gj_unscramble(const double* M, double* W, long long mstride, int nmat, int n, const int* piv,
+                                const int* src, hipStream_t s);
 hipError_t set_gj_lds_limit(size_t bytes);
 struct PfPanelShape {
   int nbh, rpt, nt, ns;
