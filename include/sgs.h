@@ -147,7 +147,9 @@ int sgs_step(sgs_ctx* ctx, double dtau, int32_t nsteps, double* energies);
  * Errors: SGS_EINVAL. */
 int sgs_energy(sgs_ctx* ctx, double* E, double* lambda);
 
-/* Observables of the current SGS state of one problem.
+/* Observables of the current SGS state of one problem (the states in gamma
+ * now; tables are re-evaluated when the states changed since the last
+ * evaluation).  iargs and dargs are host arrays, read before return.
  *   SGS_OBS_POLY  : expectation values <psi|O_t|psi> of npoly Majorana
  *                   polynomials (Sec. IV.B, Eq. Cr, uses this for S(0).S(r)).
  *                   iargs = {problem, npoly, nterm, then nterm rows of
@@ -155,10 +157,13 @@ int sgs_energy(sgs_ctx* ctx, double* E, double* lambda);
  *                   distinct increasing Majorana indices (unused = -1);
  *                   dargs = 2*nterm doubles, complex coefficients;
  *                   out (device) = 2*npoly doubles, complex results.
+ *                   Limits: npoly <= 4096, nterm <= 16384.  Waits for the
+ *                   stream before returning.
  *   SGS_OBS_RENYI2: iargs = {problem, nA} with nA even, the subsystem being
- *                   Majoranas 0..nA-1 (nA <= 64); dargs unused;
- *                   out (device) = 1 double, S_2 (Eq. S2_SGS, App. B).
- * Errors: SGS_EINVAL. */
+ *                   Majoranas 0..nA-1 (2 <= nA <= 32); dargs unused;
+ *                   out (device) = 1 double, S_2 = -ln Tr rho_A^2
+ *                   (Eq. S2_SGS, App. B; R^4 Pfaffians of order 2 nA).
+ * Errors: SGS_EINVAL (kind, sizes, indices), SGS_EHIP. */
 int sgs_observables(sgs_ctx* ctx, int32_t kind, const int32_t* iargs,
                     int32_t niargs, const double* dargs, int32_t ndargs,
                     double* out);

@@ -195,6 +195,33 @@ class SGS:
                "sgs_observables")
         return out
 
+    def expectations(self, polys, problem: int = 0) -> np.ndarray:
+        """<psi|O|psi> of the current state for Majorana polynomials O, each a
+        mapping {sorted distinct word (tuple of Majorana indices): complex
+        coefficient}.  Words of odd length have zero expectation in an
+        even-parity state and are skipped; words longer than 4 are rejected."""
+        iargs = [int(problem), len(polys), 0]
+        dargs = []
+        nterm = 0
+        for k, poly in enumerate(polys):
+            for word, coef in poly.items():
+                m = len(word)
+                if m % 2:
+                    continue
+                if m > 4:
+                    raise ValueError(f"word {word}: at most 4 Majoranas per term")
+                iargs += [k, m] + [int(x) for x in word] + [-1] * (4 - m)
+                c = complex(coef)
+                dargs += [c.real, c.imag]
+                nterm += 1
+        iargs[2] = nterm
+        out = self.observables(SGS_OBS_POLY, iargs, dargs, 2 * len(polys)).cpu().numpy()
+        return out[0::2] + 1j * out[1::2]
+
+    def renyi2(self, nA: int, problem: int = 0) -> float:
+        """S_2 = -ln Tr rho_A^2 of the current state, A = Majoranas 0..nA-1."""
+        return float(self.observables(SGS_OBS_RENYI2, [int(problem), int(nA)], [], 1).cpu().item())
+
     def set_timing(self, on: bool = True):
         _check(self.lib.sgs_set_timing(self.ctx, 1 if on else 0), "sgs_set_timing")
 

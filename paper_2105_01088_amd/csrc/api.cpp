@@ -153,6 +153,14 @@ struct StageTimer {
   }
 };
 
+// device staging of the observables (polynomial terms, partial sums)
+struct ObsBuf {
+  int* rows = nullptr;
+  double* coef = nullptr;
+  int* off = nullptr;
+  double* part = nullptr;
+};
+
 struct sgs_ctx {
   std::vector<Prob> pr;
   hipStream_t s = nullptr;
@@ -163,6 +171,7 @@ struct sgs_ctx {
   int lds_max = 65536;
   bool evaluated = false;
   StageTimer timer;
+  ObsBuf obs;
   ~sgs_ctx() {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
@@ -298,9 +307,18 @@ static int device_lds_max() {
   return v;
 }
 
-static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, char* base, int lds_max) {
+static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, char* base, int lds_max,
+                   ObsBuf* ob = nullptr) {
   Arena ar{base, 0};
   ar.take<int>(64);  // status word and spare
+  {
+    ObsBuf o;
+    o.rows = ar.take<int>(6 * (size_t)OBS_MAX_TERMS);
+    o.coef = ar.take<double>(2 * (size_t)OBS_MAX_TERMS);
+    o.off = ar.take<int>((size_t)OBS_MAX_POLY + 1);
+    o.part = ar.take<double>(2 * 32 * 32);
+    if (ob) *ob = o;
+  }
   pr.assign(nprob, Prob());
   for (int p = 0; p < nprob; ++p) {
     Prob& q = pr[p];
@@ -664,7 +682,7 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
   c->opt = o;
   c->s = (hipStream_t)stream;
   c->lds_max = device_lds_max();
-  const size_t need = plan(c->pr, probs, nprob, (char*)workspace, c->lds_max);
+  const size_t need = plan(c->pr, probs, nprob, (char*)workspace, c->lds_max, &c->obs);
   if (ws_bytes < need) { delete c; return SGS_EWORKSPACE; }
   c->status = (int*)workspace;
   double* g = gamma;
@@ -677,7 +695,8 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
     lds_gj = std::max(lds_gj, gj_panel_lds_bytes(q.n, 0, gj_panel_shape(q.n).B));
     lds_solve = std::max(lds_solve, solve_lds_bytes(q.R));
   }
-  if (set_gj_lds_limit(lds_gj) != hipSuccess || set_solve_lds_limit(lds_solve) != hipSuccess) {
+  if (set_gj_lds_limit(lds_gj) != hipSuccess || set_solve_lds_limit(lds_solve) != hipSuccess ||
+      set_renyi2_lds_limit() != hipSuccess) {
     delete c;
     return SGS_EHIP;
   }
@@ -758,9 +777,70 @@ int sgs_energy(sgs_ctx* c, double* E, double* lambda) {
 
 int sgs_observables(sgs_ctx* c, int32_t kind, const int32_t* iargs, int32_t niargs, const double* dargs,
                     int32_t ndargs, double* out) {
-  (void)iargs; (void)niargs; (void)dargs; (void)ndargs; (void)out;
-  if (!c) return SGS_EINVAL;
-  (void)kind;
+  if (!c || !iargs || niargs < 1 || !out) return SGS_EINVAL;
+  const int p = iargs[0];
+  if (p < 0 || p >= (int)c->pr.size()) return SGS_EINVAL;
+  Prob& q = c->pr[p];
+  const int n = q.n;
+  if (kind == SGS_OBS_POLY) {
+    if (niargs < 3) return SGS_EINVAL;
+    const int npoly = iargs[1], nterm = iargs[2];
+    if (npoly < 1 || npoly > OBS_MAX_POLY || nterm < 0 || nterm > OBS_MAX_TERMS) return SGS_EINVAL;
+    if (niargs != 3 + 6 * nterm || ndargs != 2 * nterm || (nterm > 0 && !dargs)) return SGS_EINVAL;
+    // validate and sort the terms by polynomial (counting sort, stable)
+    std::vector<int> cnt(npoly + 1, 0);
+    for (int t = 0; t < nterm; ++t) {
+      const int* w = iargs + 3 + 6 * t;
+      const int pi = w[0], m = w[1];
+      if (pi < 0 || pi >= npoly || (m != 0 && m != 2 && m != 4)) return SGS_EINVAL;
+      for (int u = 0; u < 4; ++u) {
+        if (u < m) {
+          if (w[2 + u] < 0 || w[2 + u] >= n || (u > 0 && w[2 + u] <= w[1 + u])) return SGS_EINVAL;
+        } else if (w[2 + u] != -1) {
+          return SGS_EINVAL;
+        }
+      }
+      ++cnt[pi + 1];
+    }
+    for (int i = 0; i < npoly; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int> rows(6 * (size_t)std::max(1, nterm)), pos(cnt.begin(), cnt.end() - 1);
+    std::vector<double> coef(2 * (size_t)std::max(1, nterm));
+    for (int t = 0; t < nterm; ++t) {
+      const int* w = iargs + 3 + 6 * t;
+      const int d = pos[w[0]]++;
+      for (int u = 0; u < 6; ++u) rows[6 * (size_t)d + u] = w[u];
+      coef[2 * (size_t)d] = dargs[2 * t];
+      coef[2 * (size_t)d + 1] = dargs[2 * t + 1];
+    }
+    if (!c->evaluated) {
+      for (auto& qq : c->pr)
+        if (pair_stage(c, qq, nullptr, nullptr, nullptr, nullptr) != hipSuccess) return SGS_EHIP;
+      c->evaluated = true;
+    }
+    // pageable sources: the copies complete (into staging) before return
+    if (hipMemcpyAsync(c->obs.rows, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice, c->s) != hipSuccess ||
+        hipMemcpyAsync(c->obs.coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, c->s) != hipSuccess ||
+        hipMemcpyAsync(c->obs.off, cnt.data(), cnt.size() * sizeof(int), hipMemcpyHostToDevice, c->s) != hipSuccess)
+      return SGS_EHIP;
+    ObsState s{n, q.R, q.gam, q.W, q.Di, q.lam, q.Gt, q.pidx};
+    if (launch_obs_poly(s, c->obs.rows, c->obs.coef, c->obs.off, npoly, out, c->s) != hipSuccess) return SGS_EHIP;
+    // the host vectors must outlive the copies
+    if (hipStreamSynchronize(c->s) != hipSuccess) return SGS_EHIP;
+    return SGS_OK;
+  }
+  if (kind == SGS_OBS_RENYI2) {
+    if (niargs != 2) return SGS_EINVAL;
+    const int nA = iargs[1];
+    if (nA < 2 || nA > OBS_MAX_NA || (nA & 1) || nA > n) return SGS_EINVAL;
+    if (!c->evaluated) {
+      for (auto& qq : c->pr)
+        if (pair_stage(c, qq, nullptr, nullptr, nullptr, nullptr) != hipSuccess) return SGS_EHIP;
+      c->evaluated = true;
+    }
+    ObsState s{n, q.R, q.gam, q.W, q.Di, q.lam, q.Gt, q.pidx};
+    if (launch_renyi2(s, nA, c->obs.part, out, c->s) != hipSuccess) return SGS_EHIP;
+    return SGS_OK;
+  }
   return SGS_EINVAL;
 }
 

@@ -179,6 +179,25 @@ hipError_t launch_build_c(int n, const double* gam, const double* T, const doubl
 size_t solve_lds_bytes(int R);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 hipError_t set_solve_lds_limit(size_t bytes);
+// Observables (obs.hip): the current tables of one problem.
+struct ObsState {
+  int n, R;
+  const double* gam;  // R covariance matrices
+  const double* W;    // per pair: (Gamma_a + Gamma_b)^{-1}
+  const double* Di;   // per pair: Im Delta^{ba}
+  const double* lam;  // R complex amplitudes
+  const double* Gt;   // R x R complex overlaps
+  const int* pidx;    // R x R pair index
+};
+constexpr int OBS_MAX_NA = 32;      // Renyi-2 subsystem: at most 32 Majoranas
+constexpr int OBS_MAX_TERMS = 16384;
+constexpr int OBS_MAX_POLY = 4096;
+hipError_t launch_obs_poly(const ObsState& s, const int* rows, const double* coef, const int* off, int npoly,
+                           double* out, hipStream_t st);
+size_t renyi2_lds_bytes(int nA);
+hipError_t set_renyi2_lds_limit();
+hipError_t launch_renyi2(const ObsState& s, int nA, double* part, double* out, hipStream_t st);
+
 hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
                         const int* impos, int M, double* dG, unsigned long long* nrm, hipStream_t s);
 hipError_t launch_euler(const double* gam, const double* dG, double dtau, int n, int R, double* X,

@@ -1,0 +1,128 @@
+"""Observables on the GPU (through the C ABI) against the CPU oracle: Majorana
+polynomial expectations (spin correlations of Sec. IV.B) and the Renyi-2
+entropy of Eq. (S2_SGS), both at the current states and after a few steps.
+
+Tolerance: the tables enter through lambda and G (pinned at 1e-9 relative by
+the pair-table tests), so expectations and S_2 are compared at 1e-9
+(absolute, relative to max(1, |value|))."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import sgs_inputs as si
+from oracle import observables as ob
+from oracle import sgs as osgs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _ctx(ham, gam, **kw):
+    from paper_2105_01088_amd import SGS, default_options
+    return SGS([ham], [gam], options=default_options(**kw))
+
+
+def _polys(L):
+    # S(0).S(r) for r = 0..L (modes 2r, 2r+1), the impurity occupation, and a hopping term
+    polys = [si.spin_dot_poly((0, 1), (2 * r, 2 * r + 1)) for r in range(0, L + 1)]
+    n0 = {(): 0.5, (0, 1): 0.5j}                       # a_0^dag a_0 = (1 + i c_0 c_1) / 2
+    hop = {(0, 5): 0.25 + 0.1j, (1, 4): -0.25, (2, 3, 6, 7): 0.3}
+    return polys + [n0, hop]
+
+
+@pytest.mark.parametrize("L,R,seed", [(3, 4, 1), (5, 3, 2), (2, 1, 4)])
+def test_expectations_match_oracle(L, R, seed):
+    ham = si.anderson(L, 1.3, 0.6)
+    gam = si.random_states(ham.N, R, seed)
+    _say(f"[obs poly] anderson L={L} R={R}")
+    ctx = _ctx(ham, gam)
+    polys = _polys(L)
+    got = ctx.expectations(polys)
+    E, lam, tab = osgs.energy(ham, gam)
+    ref = np.array([ob.expectation(gam, lam, tab.G, p) for p in polys])
+    assert np.abs(got - ref).max() < TOL * max(1.0, np.abs(ref).max())
+    ctx.close()
+
+
+def test_expectations_after_steps():
+    ham = si.anderson(3, 1.0, 0.5)
+    gam = si.random_states(ham.N, 4, 7)
+    _say("[obs poly] after 3 steps")
+    ctx = _ctx(ham, gam, weight=1)
+    ctx.step(0.05, 3)
+    polys = _polys(3)
+    got = ctx.expectations(polys)
+    g = ctx.gammas(0).cpu().numpy()
+    E, lam, tab = osgs.energy(ham, g)
+    ref = np.array([ob.expectation(g, lam, tab.G, p) for p in polys])
+    assert np.abs(got - ref).max() < TOL * max(1.0, np.abs(ref).max())
+    ctx.close()
+
+
+@pytest.mark.parametrize("nA", [2, 4, 8, 16])
+def test_renyi2_matches_oracle(nA):
+    ham = si.anderson(3, 1.3, 0.6)
+    gam = si.random_states(ham.N, 4, 3)
+    _say(f"[obs renyi2] anderson L=3 R=4 nA={nA}")
+    ctx = _ctx(ham, gam)
+    got = ctx.renyi2(nA)
+    E, lam, tab = osgs.energy(ham, gam)
+    ref = ob.renyi2(gam, lam, tab.G, nA)
+    assert abs(got - ref) < TOL * max(1.0, abs(ref))
+    ctx.close()
+
+
+def test_renyi2_full_system_is_zero():
+    # the SGS state is pure: Tr rho^2 = 1 when A is the whole system
+    ham = si.anderson(3, 1.3, 0.6)
+    gam = si.random_states(ham.N, 3, 5)
+    _say("[obs renyi2] whole system")
+    ctx = _ctx(ham, gam)
+    assert abs(ctx.renyi2(ham.n)) < 1e-10
+    ctx.close()
+
+
+def test_observables_anderson_L99_R16():
+    """The benchmark workload (n = 400, R = 16): two spin correlations and S_2
+    of the impurity plus one site (8 Majoranas)."""
+    ham, gam, cfg = si.config_problem("anderson_L99_R16")
+    _say("[obs] anderson_L99_R16")
+    ctx = _ctx(ham, gam, weight=1)
+    polys = [si.spin_dot_poly((0, 1), (2 * r, 2 * r + 1)) for r in (1, 7)]
+    got = ctx.expectations(polys)
+    s2 = ctx.renyi2(8)
+    E, lam, tab = osgs.energy(ham, gam)
+    ref = np.array([ob.expectation(gam, lam, tab.G, p) for p in polys])
+    assert np.abs(got - ref).max() < TOL * max(1.0, np.abs(ref).max())
+    ref2 = ob.renyi2(gam, lam, tab.G, 8)
+    assert abs(s2 - ref2) < TOL * max(1.0, abs(ref2))
+    ctx.close()
+
+
+def test_observables_reject_bad_arguments():
+    from paper_2105_01088_amd import SGSError
+    from paper_2105_01088_amd._lib import SGS_OBS_POLY, SGS_OBS_RENYI2
+    ham = si.anderson(2, 1.0, 0.5)
+    gam = si.random_states(ham.N, 2, 1)
+    _say("[obs] argument checks")
+    ctx = _ctx(ham, gam)
+    with pytest.raises(SGSError):
+        ctx.observables(SGS_OBS_RENYI2, [0, 3], [], 1)       # odd nA
+    with pytest.raises(SGSError):
+        ctx.observables(SGS_OBS_RENYI2, [0, 34], [], 1)      # beyond the limit
+    with pytest.raises(SGSError):
+        ctx.observables(SGS_OBS_POLY, [0, 1, 1, 0, 2, 3, 1, -1, -1], [1.0, 0.0], 2)  # unsorted word
+    with pytest.raises(SGSError):
+        ctx.observables(SGS_OBS_POLY, [1, 1, 0], [], 2)      # no such problem
+    with pytest.raises(SGSError):
+        ctx.observables(7, [0], [], 1)                       # unknown kind
+    ctx.close()
