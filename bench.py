@@ -57,6 +57,9 @@ def main(argv=None):
     import sgs_inputs as si
     from paper_2105_01088_amd import SGS, default_options
 
+    if args.config.startswith("batched"):
+        return bench_batched(args)
+
     ham, gam, cfg = si.config_problem(args.config)
     n, R = ham.n, gam.shape[0]
     P = R * (R - 1) // 2
@@ -158,6 +161,69 @@ def main(argv=None):
 
     print(json.dumps(out), flush=True)
     ctx.close()
+    return 0
+
+
+def bench_batched(args):
+    """The batched workload: 64 independent Anderson problems of uneven size
+    (n = 84..1204, R in {4, 8, 16}) in one context, all stepped together.
+    Timed twice: problems one after another on one stream, then concurrently
+    on the library's worker streams."""
+    import torch
+
+    import sgs_inputs as si
+    from paper_2105_01088_amd import SGS, default_options
+
+    count = int(args.config[len("batched"):] or 64)
+    probs = si.batched_problems(0, count=count)
+    hams = [h for h, _, _ in probs]
+    gams = [g for _, g, _ in probs]
+    pairs = sum(g.shape[0] * (g.shape[0] - 1) // 2 for g in gams)
+    dtau = float(args.dtau if args.dtau is not None else 0.05)
+    weight = 1 if args.weight == "unit" else 0
+    rates = {}
+    ms = {}
+    for streams in (1, 4):
+        ctx = SGS(hams, gams, options=default_options(weight=weight, streams=streams))
+        ctx.step(dtau, max(1, args.warmup))
+        torch.cuda.synchronize()
+        if ctx.status() != 0:
+            raise SystemExit(f"device status {ctx.status()} during warmup")
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(ctx.stream)
+        ctx.step(dtau, args.steps)
+        t1.record(ctx.stream)
+        torch.cuda.synchronize()
+        if ctx.status() != 0:
+            raise SystemExit(f"device status {ctx.status()} in the timed region")
+        total = t0.elapsed_time(t1)
+        ms[streams] = total / args.steps
+        rates[streams] = pairs * args.steps / (total / 1e3)
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    out = {
+        "metric": "Gaussian-pair evals/s",
+        "value": rates[4],
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms[4],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched{count}", "problems": count, "pairs_per_step": pairs,
+                   "n_range": [min(h.n for h in hams), max(h.n for h in hams)], "dtau": dtau, "seed": 0,
+                   "weights": args.weight, "precision": args.precision},
+        "sequential": {"value": rates[1], "ms_per_step": ms[1], "streams": 1},
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
     return 0
 
 

@@ -96,6 +96,9 @@ typedef struct {
   int32_t purify_iters;    /* max Newton-Schulz polar iterations (default 24); */
                            /* not converging sets SGS_ENOCONV                  */
   int32_t refine_iters;    /* float64 refinement sweeps on the FP32 path (2)  */
+  int32_t streams;         /* independent problems run concurrently on up to  */
+                           /* this many HIP streams, each with its own scratch*/
+                           /* (1..4, default 4)                               */
 } sgs_options;
 
 /* Fill *opt with the defaults listed above. */

@@ -41,6 +41,7 @@ struct JobTable {
 struct Prob {
   int N = 0, n = 0, R = 0, P = 0, Q = 0, M = 0, nq = 0, nnz_up = 0, nnz = 0;
   int gj_nb = 16;
+  int worker = 0;  // stream (and scratch region) this problem runs on
   double e0 = 0.0;
   double* gam = nullptr;
   // dense work
@@ -161,21 +162,53 @@ struct ObsBuf {
   double* part = nullptr;
 };
 
+// One stream of independent problems.  Worker 0 runs on the context's
+// stream; every worker forks its phase chain onto its own second stream.
+struct Worker {
+  hipStream_t s = nullptr;
+  bool own_s = false;
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_done = nullptr;
+  int owner = -1;  // problem whose scratch tables are current
+};
+
 struct sgs_ctx {
   std::vector<Prob> pr;
   hipStream_t s = nullptr;
-  hipStream_t s2 = nullptr;            // the phase chain runs here, forked from s
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  std::vector<Worker> wk;
+  hipEvent_t ev_start = nullptr;
   sgs_options opt;
   int* status = nullptr;
   int lds_max = 65536;
   bool evaluated = false;
   StageTimer timer;
+  StageTimer mute;  // never switched on
   ObsBuf obs;
   ~sgs_ctx() {
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (ev_join) (void)hipEventDestroy(ev_join);
-    if (s2) (void)hipStreamDestroy(s2);
+    for (auto& w : wk) {
+      if (w.ev_fork) (void)hipEventDestroy(w.ev_fork);
+      if (w.ev_join) (void)hipEventDestroy(w.ev_join);
+      if (w.ev_done) (void)hipEventDestroy(w.ev_done);
+      if (w.s2) (void)hipStreamDestroy(w.s2);
+      if (w.own_s && w.s) (void)hipStreamDestroy(w.s);
+    }
+    if (ev_start) (void)hipEventDestroy(ev_start);
+  }
+  // fork: every worker stream waits for the work enqueued so far on s
+  hipError_t fork() {
+    if (wk.size() < 2) return hipSuccess;
+    hipError_t e = hipEventRecord(ev_start, s);
+    for (size_t w = 1; w < wk.size() && e == hipSuccess; ++w) e = hipStreamWaitEvent(wk[w].s, ev_start, 0);
+    return e;
+  }
+  // join: s waits for every worker stream
+  hipError_t join() {
+    hipError_t e = hipSuccess;
+    for (size_t w = 1; w < wk.size() && e == hipSuccess; ++w) {
+      e = hipEventRecord(wk[w].ev_done, wk[w].s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, wk[w].ev_done, 0);
+    }
+    return e;
   }
 };
 
@@ -214,9 +247,11 @@ static int nnz_count(const sgs_problem& p, int* up) {
   return nz;
 }
 
-static void carve(Prob& q, Arena& ar) {
+// Scratch of one evaluation: per-pair and per-state dense matrices.  Problems
+// that run one after another on the same worker stream share one region.
+static void carve_scratch(Prob& q, Arena& ar) {
   const long long nn = (long long)q.n * q.n;
-  const int R = q.R, P = q.P, Q = q.Q, n = q.n, M = q.M;
+  const int R = q.R, P = q.P, Q = q.Q, n = q.n;
   q.W = ar.take<double>(std::max(1LL, P * nn));
   q.Di = ar.take<double>(std::max(1LL, P * nn));
   q.Y = ar.take<double>(std::max(1LL, 2 * P * nn));
@@ -236,6 +271,14 @@ static void carve(Prob& q, Arena& ar) {
   q.nsX0 = ar.take<double>(R * nn);
   q.nsX1 = ar.take<double>(R * nn);
   q.nsQ = ar.take<double>(R * nn);
+  q.piv = ar.take<int>(std::max(1LL, 2LL * P * n));  // pivots, then unscramble sources
+}
+
+// Per-problem state that persists between calls (tables, amplitudes, the
+// Hamiltonian in device form).
+static void carve(Prob& q, Arena& ar) {
+  const long long nn = (long long)q.n * q.n;
+  const int R = q.R, P = q.P, Q = q.Q, M = q.M, n = q.n;
   q.Adense = ar.take<double>(nn);
   q.pfacc = ar.take<double>(std::max(1, 3 * Q));
   q.logdet = ar.take<double>(std::max(1, P));
@@ -253,7 +296,6 @@ static void carve(Prob& q, Arena& ar) {
   q.up_v = ar.take<double>(std::max(1, q.nnz_up));
   q.colval = ar.take<double>(std::max(1, q.nnz));
   q.q_val = ar.take<double>(std::max(1, q.nq));
-  q.piv = ar.take<int>(std::max(1LL, 2LL * P * n));  // pivots, then unscramble sources
   q.pa = ar.take<int>(std::max(1, P));
   q.pb = ar.take<int>(std::max(1, P));
   q.qa = ar.take<int>(std::max(1, Q));
@@ -307,8 +349,10 @@ static int device_lds_max() {
   return v;
 }
 
+constexpr int MAX_WORKERS = 4;  // concurrent streams for independent problems
+
 static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, char* base, int lds_max,
-                   ObsBuf* ob = nullptr) {
+                   int max_workers, ObsBuf* ob = nullptr, int* nworkers = nullptr) {
   Arena ar{base, 0};
   ar.take<int>(64);  // status word and spare
   {
@@ -333,6 +377,39 @@ static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, c
     carve(q, ar);
     carve_jobs(q, ar);
   }
+  // workers: problems go, largest first, to the least loaded stream (work
+  // ~ R^2 n^3); each stream's scratch region fits its largest problem
+  const int K = std::max(1, std::min(nprob, max_workers));
+  std::vector<size_t> need(nprob);
+  std::vector<int> order(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    Arena probe{nullptr, 0};
+    carve_scratch(pr[p], probe);
+    need[p] = probe.off;
+    order[p] = p;
+  }
+  auto work = [&](int p) { return (double)pr[p].R * pr[p].R * pr[p].n * (double)pr[p].n * pr[p].n; };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+  std::vector<double> load(K, 0.0);
+  std::vector<size_t> region(K, 0);
+  for (int p : order) {
+    int w = 0;
+    for (int v = 1; v < K; ++v)
+      if (load[v] < load[w]) w = v;
+    pr[p].worker = w;
+    load[w] += work(p);
+    region[w] = std::max(region[w], need[p]);
+  }
+  for (int w = 0; w < K; ++w) {
+    const size_t start = (ar.off + 255) & ~(size_t)255;
+    for (int p = 0; p < nprob; ++p)
+      if (pr[p].worker == w) {
+        Arena sub{base ? base + start : nullptr, 0};
+        carve_scratch(pr[p], sub);
+      }
+    ar.off = start + region[w];
+  }
+  if (nworkers) *nworkers = K;
   return ar.off + 256;
 }
 
@@ -526,10 +603,12 @@ static hipError_t run_gemm(const JobTable& t, hipStream_t s) {
   } while (0)
 
 static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o_la, double* o_arg, double* o_eps) {
-  hipStream_t s = c->s;
+  Worker& wk = c->wk[q.worker];
+  hipStream_t s = wk.s;
   const int n = q.n, P = q.P, R = q.R;
   const long long nn = (long long)n * n;
-  StageTimer& tm = c->timer;
+  // stage times are recorded for the problems of worker 0
+  StageTimer& tm = q.worker == 0 ? c->timer : c->mute;
   const int P0 = std::min(P, R - 1);  // pairs (0, a): their inverses feed the phases
   const bool fork = q.Q > 0;
   if (P > 0) {
@@ -553,9 +632,9 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
       }
       if (half == 0 && fork) {
         // phases on the second stream, concurrent with the other inverses
-        HCHK(hipEventRecord(c->ev_fork, s));
-        HCHK(hipStreamWaitEvent(c->s2, c->ev_fork, 0));
-        hipStream_t s2 = c->s2;
+        HCHK(hipEventRecord(wk.ev_fork, s));
+        HCHK(hipStreamWaitEvent(wk.s2, wk.ev_fork, 0));
+        hipStream_t s2 = wk.s2;
         tm.begin(SGS_STAGE_PHASE, s2);
         HCHK(run_gemm(q.jt1, s2));
         HCHK(run_gemm(q.jxr, s2));
@@ -569,7 +648,7 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
           HCHK(run_gemm(q.jpf[t], s2));
         }
         tm.end(SGS_STAGE_PFAFFIAN, s2);
-        HCHK(hipEventRecord(c->ev_join, s2));
+        HCHK(hipEventRecord(wk.ev_join, s2));
       }
     }
     tm.end(SGS_STAGE_INVERSE, s);
@@ -585,7 +664,7 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
   SparseA sa{q.colptr, q.rowidx, q.colval, q.imp, q.impos, q.M};
   HCHK(launch_apply_fock(sa, n, P, R, q.W, q.Di, q.gam, q.Fc, q.Y, q.Yd, s));
   tm.end(SGS_STAGE_WICK, s);
-  if (P > 0 && fork) HCHK(hipStreamWaitEvent(s, c->ev_join, 0));
+  if (P > 0 && fork) HCHK(hipStreamWaitEvent(s, wk.ev_join, 0));
   SolveArgs a;
   a.N = q.N; a.R = R; a.P = P;
   a.pidx = q.pidx; a.qidx = q.qidx; a.logdet = q.logdet; a.pfacc = q.pfacc; a.eps = q.eps;
@@ -599,14 +678,15 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
   tm.begin(SGS_STAGE_SOLVE, s);
   HCHK(launch_solve(a, s));
   tm.end(SGS_STAGE_SOLVE, s);
+  wk.owner = (int)(&q - c->pr.data());
   return hipSuccess;
 }
 
 static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
-  hipStream_t s = c->s;
+  hipStream_t s = c->wk[q.worker].s;
   const int n = q.n, R = q.R;
   const long long nn = (long long)n * n;
-  StageTimer& tm = c->timer;
+  StageTimer& tm = q.worker == 0 ? c->timer : c->mute;
   tm.begin(SGS_STAGE_FORCE, s);
   HCHK(launch_force(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, q.dG, q.dgnorm, s));
   tm.end(SGS_STAGE_FORCE, s);
@@ -641,6 +721,7 @@ void sgs_default_options(sgs_options* o) {
   o->purify_tol = 1e-12;
   o->purify_iters = 24;
   o->refine_iters = 2;
+  o->streams = MAX_WORKERS;
 }
 
 static int check_options(const sgs_options& o) {
@@ -649,6 +730,7 @@ static int check_options(const sgs_options& o) {
   if (!(o.g_rel_threshold > 0.0 && o.g_rel_threshold < 1.0)) return SGS_EINVAL;
   if (!(o.purify_tol > 0.0) || o.purify_iters < 1 || o.purify_iters > 64) return SGS_EINVAL;
   if (o.refine_iters < 0 || o.refine_iters > 16) return SGS_EINVAL;
+  if (o.streams < 1 || o.streams > MAX_WORKERS) return SGS_EINVAL;
   return SGS_OK;
 }
 
@@ -662,7 +744,7 @@ int sgs_workspace_bytes(const sgs_problem* probs, int32_t nprob, const sgs_optio
   for (int p = 0; p < nprob; ++p)
     if ((rc = check_problem(probs[p]))) return rc;
   std::vector<Prob> pr;
-  *bytes = plan(pr, probs, nprob, nullptr, device_lds_max());
+  *bytes = plan(pr, probs, nprob, nullptr, device_lds_max(), o.streams);
   return SGS_OK;
 }
 
@@ -682,7 +764,8 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
   c->opt = o;
   c->s = (hipStream_t)stream;
   c->lds_max = device_lds_max();
-  const size_t need = plan(c->pr, probs, nprob, (char*)workspace, c->lds_max, &c->obs);
+  int nworkers = 1;
+  const size_t need = plan(c->pr, probs, nprob, (char*)workspace, c->lds_max, c->opt.streams, &c->obs, &nworkers);
   if (ws_bytes < need) { delete c; return SGS_EWORKSPACE; }
   c->status = (int*)workspace;
   double* g = gamma;
@@ -702,10 +785,23 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
   }
   for (int p = 0; p < nprob; ++p)
     if ((rc = build_tables(c->pr[p], probs[p]))) { delete c; return rc; }
-  // second stream (default priority) and the fork / join events
-  if (hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) { delete c; return SGS_EHIP; }
+  // worker streams (default priority; worker 0 is the context's stream), each
+  // with a second stream for its phase chain, and the fork / join events
+  c->wk.assign(nworkers, Worker());
+  if (hipEventCreateWithFlags(&c->ev_start, hipEventDisableTiming) != hipSuccess) { delete c; return SGS_EHIP; }
+  for (int w = 0; w < nworkers; ++w) {
+    Worker& k = c->wk[w];
+    if (w == 0) {
+      k.s = c->s;
+    } else {
+      if (hipStreamCreateWithFlags(&k.s, hipStreamNonBlocking) != hipSuccess) { delete c; return SGS_EHIP; }
+      k.own_s = true;
+    }
+    if (hipStreamCreateWithFlags(&k.s2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&k.ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&k.ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&k.ev_done, hipEventDisableTiming) != hipSuccess) { delete c; return SGS_EHIP; }
+  }
   if (hipMemsetAsync(c->status, 0, sizeof(int), c->s) != hipSuccess) { delete c; return SGS_EHIP; }
   // validate the covariance matrices: skew, Gamma^2 = -1
   for (auto& q : c->pr) {
@@ -730,6 +826,7 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
 int sgs_pair_eval(sgs_ctx* c, double* log_abs_G, double* arg_G, double* eps) {
   if (!c) return SGS_EINVAL;
   long long off = 0;
+  if (c->fork() != hipSuccess) return SGS_EHIP;
   for (auto& q : c->pr) {
     const int RR = q.R * q.R;
     if (pair_stage(c, q, nullptr, log_abs_G ? log_abs_G + off : nullptr, arg_G ? arg_G + off : nullptr,
@@ -737,6 +834,7 @@ int sgs_pair_eval(sgs_ctx* c, double* log_abs_G, double* arg_G, double* eps) {
       return SGS_EHIP;
     off += RR;
   }
+  if (c->join() != hipSuccess) return SGS_EHIP;
   c->evaluated = true;
   return SGS_OK;
 }
@@ -744,6 +842,8 @@ int sgs_pair_eval(sgs_ctx* c, double* log_abs_G, double* arg_G, double* eps) {
 int sgs_step(sgs_ctx* c, double dtau, int32_t nsteps, double* energies) {
   if (!c || nsteps < 0 || !std::isfinite(dtau) || dtau <= 0.0) return SGS_EINVAL;
   const int np = (int)c->pr.size();
+  // independent problems run concurrently, one stream per worker
+  if (c->fork() != hipSuccess) return SGS_EHIP;
   for (int k = 0; k < nsteps; ++k)
     for (int p = 0; p < np; ++p) {
       Prob& q = c->pr[p];
@@ -752,15 +852,21 @@ int sgs_step(sgs_ctx* c, double dtau, int32_t nsteps, double* energies) {
         return SGS_EHIP;
       if (update_stage(c, q, dtau) != hipSuccess) return SGS_EHIP;
     }
-  if (nsteps > 0) c->evaluated = false;
+  if (c->join() != hipSuccess) return SGS_EHIP;
+  if (nsteps > 0) {
+    c->evaluated = false;
+    for (auto& w : c->wk) w.owner = -1;
+  }
   return SGS_OK;
 }
 
 int sgs_energy(sgs_ctx* c, double* E, double* lambda) {
   if (!c || !E) return SGS_EINVAL;
   if (!c->evaluated) {
+    if (c->fork() != hipSuccess) return SGS_EHIP;
     for (auto& q : c->pr)
       if (pair_stage(c, q, nullptr, nullptr, nullptr, nullptr) != hipSuccess) return SGS_EHIP;
+    if (c->join() != hipSuccess) return SGS_EHIP;
     c->evaluated = true;
   }
   long long off = 0;
@@ -773,6 +879,17 @@ int sgs_energy(sgs_ctx* c, double* E, double* lambda) {
     off += q.R;
   }
   return SGS_OK;
+}
+
+// The scratch tables (W, Im Delta) of problem p for its current states; other
+// problems of the same worker may have overwritten them since.
+static hipError_t ensure_tables(sgs_ctx* c, int p) {
+  Prob& q = c->pr[p];
+  if (c->evaluated && c->wk[q.worker].owner == p) return hipSuccess;
+  hipError_t e = c->fork();
+  if (e == hipSuccess) e = pair_stage(c, q, nullptr, nullptr, nullptr, nullptr);
+  if (e == hipSuccess) e = c->join();
+  return e;
 }
 
 int sgs_observables(sgs_ctx* c, int32_t kind, const int32_t* iargs, int32_t niargs, const double* dargs,
@@ -812,11 +929,7 @@ int sgs_observables(sgs_ctx* c, int32_t kind, const int32_t* iargs, int32_t niar
       coef[2 * (size_t)d] = dargs[2 * t];
       coef[2 * (size_t)d + 1] = dargs[2 * t + 1];
     }
-    if (!c->evaluated) {
-      for (auto& qq : c->pr)
-        if (pair_stage(c, qq, nullptr, nullptr, nullptr, nullptr) != hipSuccess) return SGS_EHIP;
-      c->evaluated = true;
-    }
+    if (ensure_tables(c, p) != hipSuccess) return SGS_EHIP;
     // pageable sources: the copies complete (into staging) before return
     if (hipMemcpyAsync(c->obs.rows, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice, c->s) != hipSuccess ||
         hipMemcpyAsync(c->obs.coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, c->s) != hipSuccess ||
@@ -832,11 +945,7 @@ int sgs_observables(sgs_ctx* c, int32_t kind, const int32_t* iargs, int32_t niar
     if (niargs != 2) return SGS_EINVAL;
     const int nA = iargs[1];
     if (nA < 2 || nA > OBS_MAX_NA || (nA & 1) || nA > n) return SGS_EINVAL;
-    if (!c->evaluated) {
-      for (auto& qq : c->pr)
-        if (pair_stage(c, qq, nullptr, nullptr, nullptr, nullptr) != hipSuccess) return SGS_EHIP;
-      c->evaluated = true;
-    }
+    if (ensure_tables(c, p) != hipSuccess) return SGS_EHIP;
     ObsState s{n, q.R, q.gam, q.W, q.Di, q.lam, q.Gt, q.pidx};
     if (launch_renyi2(s, nA, c->obs.part, out, c->s) != hipSuccess) return SGS_EHIP;
     return SGS_OK;
