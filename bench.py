@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
+FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 
 
 def force_flops(n: int, R: int) -> float:
@@ -40,7 +41,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="anderson_L99_R16")
     ap.add_argument("--weight", choices=["unit", "printed"], default="unit")
-    ap.add_argument("--precision", choices=["fp64"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="fp32: the force's dense product on the FP32 matrix cores")
     ap.add_argument("--dtau", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args(argv)
@@ -66,7 +68,8 @@ def main(argv=None):
     dtau = float(args.dtau if args.dtau is not None else cfg["dtau"])
     weight = 1 if args.weight == "unit" else 0
 
-    ctx = SGS([ham], [gam], options=default_options(weight=weight))
+    prec = 1 if args.precision == "fp32" else 0
+    ctx = SGS([ham], [gam], options=default_options(weight=weight, precision=prec))
     stream = ctx.stream
     # warmup
     e_first = ctx.step(dtau, 1)
@@ -101,6 +104,7 @@ def main(argv=None):
     f_ms, f_n = stages["force"]
     f_avg_ms = f_ms / max(1, f_n)
     achieved = force_flops(n, R) / (f_avg_ms / 1e3) / 1e12
+    peak = FP32_PEAK_TFLOPS if prec == 1 else FP64_PEAK_TFLOPS
 
     out = {
         "metric": "Gaussian-pair evals/s",
@@ -113,7 +117,7 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == 0 else "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": args.config,
@@ -125,9 +129,9 @@ def main(argv=None):
             "bound": "mfma",
             "kernel": "k_force",
             "achieved": achieved,
-            "peak": FP64_PEAK_TFLOPS,
+            "peak": peak,
             "unit": "TFLOP/s",
-            "frac": achieved / FP64_PEAK_TFLOPS,
+            "frac": achieved / peak,
             "traffic": None,
             "force_avg_ms": f_avg_ms,
             "force_flops_per_launch": force_flops(n, R),
@@ -136,6 +140,17 @@ def main(argv=None):
         "wall_s": wall,
         "E_last": float(energies[-1].item()),
     }
+
+    if prec == 1:
+        # per-step energy error of the FP32 path against a float64 run of the
+        # same steps from the same states (outside the timed region)
+        ctxa = SGS([ham], [gam], options=default_options(weight=weight, precision=prec))
+        ctxb = SGS([ham], [gam], options=default_options(weight=weight))
+        ea = ctxa.step(dtau, args.steps).cpu().numpy()
+        eb = ctxb.step(dtau, args.steps).cpu().numpy()
+        out["E_rel_err_vs_fp64_per_step"] = [float(x) for x in (np.abs(ea - eb) / np.abs(eb))]
+        ctxa.close()
+        ctxb.close()
 
     if not args.no_cpu_baseline:
         from oracle import sgs as osgs

@@ -60,10 +60,12 @@ extern "C" {
 
 /* sgs_options.precision */
 #define SGS_FP64 0          /* every stage in float64                          */
-#define SGS_FP32_REFINE 1   /* pair inverses and force GEMMs on float32 MFMA,  */
-                            /* won back by float64 iterative refinement;      */
-                            /* overlaps, eigen-solve and purification stay    */
-                            /* float64                                        */
+#define SGS_FP32_REFINE 1   /* the force's dense product (Eq. EOM-Gamma3) on   */
+                            /* the float32 matrix cores (about 1e-7 relative, */
+                            /* far below the O(dtau) error of the Euler step);*/
+                            /* inverses, overlaps, Wick elements, eigen-solve */
+                            /* stay float64, and the float64 purification     */
+                            /* returns every step to the pure states          */
 /* sgs_options.weight: the scalar c_mu of Eq. (Bmu) (Sec. III.A) */
 #define SGS_W_PRINTED 0     /* c_mu = 1 / (lambda_mu lambda~_mu^*)             */
 #define SGS_W_UNIT 1        /* c_mu = lambda~_mu lambda_mu^* / |lambda~_mu lambda_mu| */
@@ -95,7 +97,6 @@ typedef struct {
                            /* < min(1e-8, sqrt(purify_tol)) (default 1e-12)    */
   int32_t purify_iters;    /* max Newton-Schulz polar iterations (default 24); */
                            /* not converging sets SGS_ENOCONV                  */
-  int32_t refine_iters;    /* float64 refinement sweeps on the FP32 path (2)  */
   int32_t streams;         /* independent problems run concurrently on up to  */
                            /* this many HIP streams, each with its own scratch*/
                            /* (1..4, default 4)                               */

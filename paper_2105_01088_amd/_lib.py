@@ -38,7 +38,7 @@ class sgs_problem(ctypes.Structure):
 
 class sgs_options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("weight", c_int32), ("g_rel_threshold", c_double),
-                ("purify_tol", c_double), ("purify_iters", c_int32), ("refine_iters", c_int32),
+                ("purify_tol", c_double), ("purify_iters", c_int32),
                 ("streams", c_int32)]
 
 

@@ -688,7 +688,8 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
   const long long nn = (long long)n * n;
   StageTimer& tm = q.worker == 0 ? c->timer : c->mute;
   tm.begin(SGS_STAGE_FORCE, s);
-  HCHK(launch_force(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, q.dG, q.dgnorm, s));
+  const int fmode = c->opt.precision == SGS_FP64 ? FORCE_FP64 : FORCE_FP32;
+  HCHK(launch_force(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, q.dG, q.dgnorm, fmode, s));
   tm.end(SGS_STAGE_FORCE, s);
   (void)nn;
   tm.begin(SGS_STAGE_PURIFY, s);
@@ -720,7 +721,6 @@ void sgs_default_options(sgs_options* o) {
   o->g_rel_threshold = 1e-12;
   o->purify_tol = 1e-12;
   o->purify_iters = 24;
-  o->refine_iters = 2;
   o->streams = MAX_WORKERS;
 }
 
@@ -729,7 +729,6 @@ static int check_options(const sgs_options& o) {
   if (o.weight != SGS_W_PRINTED && o.weight != SGS_W_UNIT) return SGS_EINVAL;
   if (!(o.g_rel_threshold > 0.0 && o.g_rel_threshold < 1.0)) return SGS_EINVAL;
   if (!(o.purify_tol > 0.0) || o.purify_iters < 1 || o.purify_iters > 64) return SGS_EINVAL;
-  if (o.refine_iters < 0 || o.refine_iters > 16) return SGS_EINVAL;
   if (o.streams < 1 || o.streams > MAX_WORKERS) return SGS_EINVAL;
   return SGS_OK;
 }

@@ -12,6 +12,11 @@
 // the tile and its skew mirror (the force is skew: only tiles I <= J run).
 // The pair (a < b) stores Delta^{ba}; the term for mu = b uses its complex
 // conjugate (sgn = -1 on every imaginary part).
+//
+// Precision: TT = double runs the product on the FP64 matrix cores.  TT =
+// float (the FP32 path) rounds both operands to float when they are staged
+// and accumulates in float on the FP32 matrix cores (about 1e-7 relative);
+// every other term is added in float64.
 #include "sgs_internal.h"
 
 #include <type_traits>
@@ -19,31 +24,53 @@
 namespace sgs {
 
 typedef double dvec4 __attribute__((ext_vector_type(4)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ dvec4 mfma64(double a, double b, dvec4 c) {
+__device__ __forceinline__ dvec4 mfma_t(double a, double b, dvec4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ fvec4 mfma_t(float a, float b, fvec4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// accumulator register r of lane l holds row acc_row(l, r), column l % 16
+// (f64: 4 r + l / 16; f32: 4 (l / 16) + r; both measured on gfx950)
+template <typename T> __device__ __forceinline__ int acc_row(int lane, int r);
+template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { return 4 * r + (lane >> 4); }
+template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
+
+template <typename T> struct Vec4;
+template <> struct Vec4<double> { typedef dvec4 type; };
+template <> struct Vec4<float> { typedef fvec4 type; };
 
 constexpr int FTK = 16;
 constexpr int FLP = 64 + 1;
+
+constexpr size_t force_lds_bytes(size_t elem) {
+  return (2 * 2 * FTK * FLP * elem) > (64 * FLP * sizeof(double)) ? (2 * 2 * FTK * FLP * elem)
+                                                                  : (64 * FLP * sizeof(double));
+}
 
 // grid: 8 * ceil(R / 8) * ntri blocks of 256 threads.  Blocks are dispatched
 // round-robin over the 8 XCDs; block b serves state mu = b % 8 + 8 s on XCD
 // b % 8, so all tiles of a state share that XCD's L2 (every tile of state mu
 // streams the same Y and Delta panels).  terms: R*R descriptors (mu-major);
 // coef: c1 then c2 tables, complex interleaved, R*R each.
+template <typename TT>
 __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceTerm* __restrict__ terms,
                                                const double* __restrict__ coef,
                                                const double* __restrict__ Adense,
                                                const int* __restrict__ impos, int M,
                                                double* __restrict__ dG,
                                                unsigned long long* __restrict__ nrm) {
-  // K-loop staging (As, Bs) and the epilogue's transposed block (Tt) share LDS
-  __shared__ double lds[2 * 2 * FTK * FLP];
-  typedef double Slab[FTK][FLP];
-  Slab* As = (Slab*)lds;                    // As[2]
-  Slab* Bs = (Slab*)(lds + 2 * FTK * FLP);  // Bs[2]
-  double (*Tt)[FLP] = (double (*)[FLP])lds; // 64 x FLP
+  typedef typename Vec4<TT>::type V4;
+  // K-loop staging As[re/im], Bs[re/im] and the epilogue's transposed block
+  // (Tt, float64) share LDS
+  __shared__ __attribute__((aligned(16))) char lds_raw[force_lds_bytes(sizeof(TT))];
+  typedef TT Slab[FTK][FLP];
+  Slab* As = (Slab*)lds_raw;      // As[part]
+  Slab* Bs = (Slab*)lds_raw + 2;  // Bs[part]
+  double (*Tt)[FLP] = (double (*)[FLP])lds_raw;  // 64 x FLP
 
   const int ntri = T * (T + 1) / 2;
   const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
@@ -59,11 +86,11 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
-  dvec4 acc[2][2];
+  V4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = dvec4{0, 0, 0, 0};
+    for (int j = 0; j < 2; ++j) acc[i][j] = V4{0, 0, 0, 0};
 
   const double* c1t = coef;
   const double* c2t = coef + 2 * R * R;
@@ -107,35 +134,37 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const double dr = ds * rd[0][r], di = sg * rd[1][r];
-        As[0][a_k + r][a_i] = ra[0][r];
-        if (IM) As[1][a_k + r][a_i] = sg * ra[1][r];
-        Bs[0][b_k][b_j + r] = x1 * dr - y1 * di;     // Re(c1 D)
-        if (IM) Bs[1][b_k][b_j + r] = -(x1 * di + y1 * dr);  // -Im(c1 D)
+        const double v[4] = {ra[0][r], sg * ra[1][r], x1 * dr - y1 * di, -(x1 * di + y1 * dr)};
+        // A: Y_r, sg Y_i; B: Re(c1 D), -Im(c1 D)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (!IM && (u & 1)) continue;
+          TT* dst = u < 2 ? &As[u][a_k + r][a_i] : &Bs[u - 2][b_k][b_j + r];
+          *dst = (TT)v[u];
+        }
       }
       __syncthreads();
       if (kc + FTK < n) load(kc + FTK);
 #pragma unroll
       for (int kk = 0; kk < FTK / 4; ++kk) {
         const int kr = kk * 4 + (lane >> 4);
-        double a0[2], a1[2], b0[2], b1[2];
+        TT ah[2][2], bh[2][2];  // [re/im][q]
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          a0[q] = As[0][kr][wm * 32 + q * 16 + (lane & 15)];
-          b0[q] = Bs[0][kr][wn * 32 + q * 16 + (lane & 15)];
-          if (IM) {
-            a1[q] = As[1][kr][wm * 32 + q * 16 + (lane & 15)];
-            b1[q] = Bs[1][kr][wn * 32 + q * 16 + (lane & 15)];
+        for (int u = 0; u < 2; ++u) {
+          if (!IM && u) continue;
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            ah[u][q] = As[u][kr][wm * 32 + q * 16 + (lane & 15)];
+            bh[u][q] = Bs[u][kr][wn * 32 + q * 16 + (lane & 15)];
           }
         }
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma64(a0[bi], b0[bj], acc[bi][bj]);
-        if (IM) {
+        for (int u = 0; u < 2; ++u) {
+          if (!IM && u) continue;
 #pragma unroll
           for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma64(a1[bi], b1[bj], acc[bi][bj]);
+            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma_t(ah[u][bi], bh[u][bj], acc[bi][bj]);
         }
       }
     }
@@ -185,7 +214,7 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
       for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int li = wm * 32 + bi * 16 + 4 * r + (lane >> 4);  // f64 MFMA accumulator row
+          const int li = wm * 32 + bi * 16 + acc_row<TT>(lane, r);
           const int lj = wn * 32 + bj * 16 + (lane & 15);
           const int gi = row0 + li, gj = col0 + lj;
           const bool ok = gi < n && gj < n;
@@ -211,11 +240,11 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int li = wm * 32 + bi * 16 + 4 * r + (lane >> 4);  // f64 MFMA accumulator row
+        const int li = wm * 32 + bi * 16 + acc_row<TT>(lane, r);
         const int lj = wn * 32 + bj * 16 + (lane & 15);
         const int gi = row0 + li, gj = col0 + lj;
         double v = 0.0;
-        if (gi < n && gj < n) v = acc[bi][bj][r] + lin[bi][bj][r] + sx1 * Adense[(long long)gi * n + gj];
+        if (gi < n && gj < n) v = (double)acc[bi][bj][r] + lin[bi][bj][r] + sx1 * Adense[(long long)gi * n + gj];
         if (I == J) Tt[li][lj] = v;
         else if (gi < n && gj < n) {
           out[(long long)gi * n + gj] = v;
@@ -233,11 +262,15 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
 }
 
 hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
-                        const int* impos, int M, double* dG, unsigned long long* nrm, hipStream_t s) {
+                        const int* impos, int M, double* dG, unsigned long long* nrm, int mode, hipStream_t s) {
   const int T = (n + 63) / 64;
   const int ntri = T * (T + 1) / 2;
   const int per_xcd = (R + 7) / 8;
-  hipLaunchKernelGGL(k_force, dim3(8 * per_xcd * ntri), dim3(256), 0, s, n, R, T, terms, coef, A, impos, M, dG, nrm);
+  const dim3 grid(8 * per_xcd * ntri), block(256);
+  if (mode == FORCE_FP64)
+    hipLaunchKernelGGL((k_force<double>), grid, block, 0, s, n, R, T, terms, coef, A, impos, M, dG, nrm);
+  else
+    hipLaunchKernelGGL((k_force<float>), grid, block, 0, s, n, R, T, terms, coef, A, impos, M, dG, nrm);
   return hipGetLastError();
 }
 

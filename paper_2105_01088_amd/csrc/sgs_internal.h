@@ -198,8 +198,9 @@ size_t renyi2_lds_bytes(int nA);
 hipError_t set_renyi2_lds_limit();
 hipError_t launch_renyi2(const ObsState& s, int nA, double* part, double* out, hipStream_t st);
 
+enum : int { FORCE_FP64 = 0, FORCE_FP32 = 1 };
 hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
-                        const int* impos, int M, double* dG, unsigned long long* nrm, hipStream_t s);
+                        const int* impos, int M, double* dG, unsigned long long* nrm, int mode, hipStream_t s);
 hipError_t launch_euler(const double* gam, const double* dG, double dtau, int n, int R, double* X,
                         int* ctl, unsigned long long* resid, int nresid, unsigned long long* nrm,
                         hipStream_t s);

@@ -206,3 +206,43 @@ def test_anderson_L199_R32_sampled_tables():
 
 def test_two_channel_kondo_L150_R24_sampled_tables():
     _sampled_tables("tck_L150_R24_J0.3", [(0, 23), (7, 8)], [(1, 23), (11, 12)])
+
+
+# ------------------------------------------------------------- FP32 path
+
+def _run(ham, gam, steps, **kw):
+    ctx = _ctx(ham, gam, **kw)
+    e = ctx.step(0.05, steps).cpu().numpy()
+    assert ctx.status() == 0
+    g = ctx.gammas(0).cpu().numpy()
+    ctx.close()
+    return e, g
+
+
+def test_fp32_one_step_against_oracle():
+    """FP32 path: the energy entering the step is the float64 one; the new
+    covariance matrices differ from the oracle's by the float32 rounding of
+    the force product: at most 1e-5 dtau max|dGamma| here (float32 epsilon
+    6e-8 times K = 2 n R = 360 products, allowing for cancellation)."""
+    ham = si.anderson(8, 1.3, 0.6)
+    gam = si.random_states(ham.N, 5, 9)
+    _say("[fp32] anderson L=8 R=5")
+    e, g = _run(ham, gam, 1, weight=1, precision=1)
+    ref = osgs.step(ham, gam, 0.05, mode="unit")
+    assert abs(e[0] - ref.E) < TOL_E * abs(ref.E)
+    err = np.abs(g - ref.gammas).max()
+    assert err < 1e-5 * 0.05 * np.abs(ref.dgamma).max()
+    assert err > 0.0  # the float product is really used
+
+
+def test_fp32_plain_error_bound():
+    """FP32 path at the benchmark size: after 5 steps the states and energies
+    follow the float64 run closely, and the energy still decreases."""
+    ham, gam, cfg = si.config_problem("anderson_L99_R16")
+    _say("[fp32] anderson_L99_R16, 5 steps against float64")
+    e64, g64 = _run(ham, gam, 5, weight=1)
+    e32, g32 = _run(ham, gam, 5, weight=1, precision=1)
+    assert e32[0] == e64[0]  # the first energy does not see the force
+    assert np.abs(g32 - g64).max() < 1e-5
+    assert np.abs(e32 - e64).max() < 1e-8 * np.abs(e64).max()
+    assert np.all(np.diff(e32) <= 1e-10 * abs(e32[0]))
