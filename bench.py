@@ -25,6 +25,12 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 
+# HBM bytes per k_force launch, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# counters on this workload (FETCH_SIZE scaled by 2.0, WRITE_SIZE by 1.0: the
+# factors a 1 GiB device copy reads back).  Only valid for the kernel and
+# workload it was taken on; any other combination reports null.
+FORCE_TRAFFIC_BYTES = {("anderson_L99_R16", "fp64"): 2.974e9}
+
 
 def force_flops(n: int, R: int) -> float:
     """Algorithmic flops of one force launch: for every ordered pair mu != b the
@@ -45,7 +51,19 @@ def main(argv=None):
                     help="fp32: the force's dense product on the FP32 matrix cores")
     ap.add_argument("--dtau", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES between two device buffers (counter calibration) and exit")
     args = ap.parse_args(argv)
+
+    if args.copy_probe > 0:
+        import torch
+        x = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel() * 8}), flush=True)
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -132,7 +150,7 @@ def main(argv=None):
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": FORCE_TRAFFIC_BYTES.get((args.config, args.precision)),
             "force_avg_ms": f_avg_ms,
             "force_flops_per_launch": force_flops(n, R),
         },
