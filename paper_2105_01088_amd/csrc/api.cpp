@@ -529,7 +529,8 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
       double* cout = (t & 1) ? q.Cm : q.Cm2;
       if (mp > 0)
         for (int qq = 0; qq < q.Q; ++qq) {
-          GemmJob j = job(q.UV + qq * q.uvstride, K, 0, q.RM + qq * q.uvstride, K, 1, cin + qq * 2 * nn, n,
+          // the panel stores [U V] and [V -U] transposed (K x mp)
+          GemmJob j = job(q.UV + qq * q.uvstride, mp, 1, q.RM + qq * q.uvstride, mp, 0, cin + qq * 2 * nn, n,
                           cout + qq * 2 * nn, n, mp, mp, K, 1.0, 1.0);
           j.a_im = q.uv_im; j.b_im = q.uv_im; j.c_im = nn; j.d_im = nn;
           j.cperm = q.pfperm + (long long)qq * n;

@@ -15,48 +15,11 @@
 // Afterwards M[piv[r]][c] = W[r][pi(c)] with pi = piv, and k_gj_unscramble
 // writes W[r][c] = M[piv[r]][piv^-1[c]] into a separate buffer.
 #include "sgs_internal.h"
+#include "wave_ops.h"
 
 namespace sgs {
 
 constexpr int GJ_MAX_WAVES = 8;
-
-// Pivot search key: |v| as an ordered bit pattern with its low 16 bits
-// replaced by 0xffff - row, so one unsigned 64-bit maximum yields the largest
-// entry (to 36 mantissa bits, far inside what partial pivoting needs) and, on
-// ties, the smallest row.  0 means "no candidate".
-__device__ __forceinline__ unsigned long long pivot_key(double v, int row) {
-  const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(v));
-  return (bits & ~0xffffull) | (unsigned long long)(0xffff - row);
-}
-
-template <int CTRL>
-__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, 0xf, 0xf, false);
-  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
-}
-
-__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int lane) {
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
-  return ((unsigned long long)hi << 32) | lo;
-}
-
-__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
-  return a > b ? a : b;
-}
-
-// Maximum over the 64 lanes of a wave (every lane active), returned uniform.
-// DPP within rows of 16 lanes (swap neighbours, swap pairs, half-row mirror,
-// row mirror), then the four row results are read as scalars.
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-  v = umax64(v, dpp_u64<0xb1>(v));   // quad_perm [1,0,3,2]
-  v = umax64(v, dpp_u64<0x4e>(v));   // quad_perm [2,3,0,1]
-  v = umax64(v, dpp_u64<0x141>(v));  // row_half_mirror
-  v = umax64(v, dpp_u64<0x140>(v));  // row_mirror
-  return umax64(umax64(readlane_u64(v, 0), readlane_u64(v, 16)),
-                umax64(readlane_u64(v, 32), readlane_u64(v, 48)));
-}
 
 // Panel kernel.  Thread t owns the physical rows i = t + r nt (r < RPT) and
 // keeps their b panel entries in registers.  The panel is swept column by
@@ -72,7 +35,8 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 // to LDS; after the one barrier of the column every thread takes the best of
 // the waves' posts.  Posts alternate between two LDS slots.  The next
 // column's key is formed as soon as that column is updated, so its wave
-// maximum overlaps the rest of the row update.
+// maximum overlaps the rest of the row update.  The column loop is rolled,
+// with the row registers rotated one column per step.
 // The panel moves between HBM and registers through a per-wave LDS tile, so
 // that global loads and stores are row segments rather than one row per lane.
 template <int B, int RPT>
@@ -85,7 +49,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                                                   int* __restrict__ status) {
   constexpr int CB = B < 16 ? B : 16;  // columns per LDS staging pass
   constexpr int RPI = 64 / CB;          // rows per coalesced load / store
-  constexpr bool PRE = RPT == 1;        // pivot row copied into registers
   constexpr bool STG = RPT == 1;        // staged loads / stores (register budget)
   // dynamic LDS: tag (n ints: 1 if the row is a pivot of an earlier panel),
   // then per wave a 64 x (CB + 1) staging tile, then per wave 64 ints
@@ -155,91 +118,115 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   int pe = 0;
   bool sing = false;
 
+  // The column loop stays rolled (its unrolled form is tens of KB of code,
+  // fetched once per panel: instruction-cache bound).  Instead the registers
+  // rotate by one column per step, so the current column is always x[r][0]
+  // and the next x[r][1]; posted rows carry the same rotation.
+#pragma unroll 1
+  for (int j = 0; j < b; ++j) {
+    const int par = j & 1;
+    if (lane == 0) skey[par][w] = key;
+    int sel = -1;  // which owned row posts (selected by value, not by address)
 #pragma unroll
-  for (int j = 0; j < B; ++j) {
-    if (j < b) {  // uniform
-      const int par = j & 1;
-      if (lane == 0) skey[par][w] = key;
-      int sel = -1;  // which owned row posts (selected by value, not by address)
+    for (int r = 0; r < RPT; ++r)
+      if (key != 0ull && mine[r] == key) sel = r;
+    if (sel >= 0) {
 #pragma unroll
-      for (int r = 0; r < RPT; ++r)
-        if (key != 0ull && mine[r] == key) sel = r;
-      if (sel >= 0) {
+      for (int c = 0; c < B; ++c) {
+        double v = x[0][c];
 #pragma unroll
-        for (int c = 0; c < B; ++c) {
-          double v = x[0][c];
-#pragma unroll
-          for (int r = 1; r < RPT; ++r) v = (sel == r) ? x[r][c] : v;
-          srow[par][w][c] = v;
-        }
+        for (int r = 1; r < RPT; ++r) v = (sel == r) ? x[r][c] : v;
+        srow[par][w][c] = v;
       }
-      __syncthreads();
-      unsigned long long kq[GJ_MAX_WAVES];
+    }
+    __syncthreads();
+    unsigned long long kq[GJ_MAX_WAVES];
 #pragma unroll
-      for (int q = 0; q < GJ_MAX_WAVES; ++q) kq[q] = q < nw ? skey[par][q] : 0ull;
-      unsigned long long best = kq[0];
-      int ww = 0;
+    for (int q = 0; q < GJ_MAX_WAVES; ++q) kq[q] = q < nw ? skey[par][q] : 0ull;
+    unsigned long long best = kq[0];
+    int ww = 0;
 #pragma unroll
-      for (int q = 1; q < GJ_MAX_WAVES; ++q)
-        if (kq[q] > best) { best = kq[q]; ww = q; }
-      int p = 0xffff - (int)(best & 0xffffull);
-      const bool bad = best == 0ull || p >= n;
-      if (bad) p = 0;  // cannot happen for b <= n - k; keeps every index in range
-      // the whole pivot row into registers at once (one LDS latency) when
-      // the registers allow, else read in place
-      double prow[PRE ? B : 1];
-      const double* __restrict__ ps = srow[par][ww];
+    for (int q = 1; q < GJ_MAX_WAVES; ++q)
+      if (kq[q] > best) { best = kq[q]; ww = q; }
+    int p = 0xffff - (int)(best & 0xffffull);
+    const bool bad = best == 0ull || p >= n;
+    if (bad) p = 0;  // cannot happen for b <= n - k; keeps every index in range
+    // the pivot row: one element per lane, broadcast from lane c
+    const double* __restrict__ ps = srow[par][ww];
+    const double pvl = lane < B ? ps[lane] : 0.0;
+#define PROW(c) lane_bcast(pvl, (c))
+    const double a = bad ? 0.0 : PROW(0);
+    if (bad || !(fabs(a) > 0.0) || !isfinite(a)) sing = true;
+    {
+      int e;
+      pm *= frexp(fabs(a), &e);
+      pe += e;
+    }
+    // 1 / a: hardware reciprocal and two Newton steps
+    double ra = __builtin_amdgcn_rcp(a);
+    ra = fma(ra, fma(-a, ra, 1.0), ra);
+    ra = fma(ra, fma(-a, ra, 1.0), ra);
+    if (tid == 0) pivl[j] = p;
+    // Every broadcast (readlane of pvl) runs in uniform control flow, so every
+    // source lane has loaded its element.  The pivot row takes f = 0 in the
+    // common update and is then rewritten in place from its own registers.
+    double f[RPT];
+    bool isp[RPT];
 #pragma unroll
-      for (int c = 0; c < (PRE ? B : 1); ++c) prow[c] = ps[c];
-#define PROW(c) (PRE ? prow[(c) % (PRE ? B : 1)] : ps[c])
-      const double a = bad ? 0.0 : PROW(j);
-      if (bad || !(fabs(a) > 0.0) || !isfinite(a)) sing = true;
-      {
-        int e;
-        pm *= frexp(fabs(a), &e);
-        pe += e;
+    for (int r = 0; r < RPT; ++r) {
+      isp[r] = tid + r * nt == p;
+      f[r] = isp[r] ? 0.0 : x[r][0] * ra;
+      if (isp[r]) {
+        act[r] = false;
+        pos[r] = j;
       }
-      // 1 / a: hardware reciprocal and two Newton steps
-      double ra = __builtin_amdgcn_rcp(a);
-      ra = fma(ra, fma(-a, ra, 1.0), ra);
-      ra = fma(ra, fma(-a, ra, 1.0), ra);
-      if (tid == 0) pivl[j] = p;
-      double f[RPT];
-      bool isp[RPT];
+    }
+    {
+      const double p1 = PROW(1);
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) x[r][1] -= f[r] * p1;
+    }
+    if (j + 1 < b) {
+      key = 0;
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
-        isp[r] = tid + r * nt == p;
-        f[r] = x[r][j] * ra;
-        if (isp[r]) {
-          act[r] = false;
-          pos[r] = j;
-        } else if (j + 1 < B) {
-          x[r][j + 1] -= f[r] * PROW(j + 1);
-        }
+        mine[r] = act[r] ? pivot_key(x[r][1], tid + r * nt) : 0ull;
+        key = umax64(key, mine[r]);
       }
-      if (j + 1 < b) {
-        key = 0;
+      key = wave_max_u64(key);
+    }
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-          const double v = isp[r] ? 0.0 : x[r][(j + 1) % B];
-          mine[r] = act[r] ? pivot_key(v, tid + r * nt) : 0ull;
-          key = umax64(key, mine[r]);
-        }
-        key = wave_max_u64(key);
+    for (int c = 2; c < B; ++c) {
+      const double pc = PROW(c);
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) x[r][c] -= f[r] * pc;
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      if (isp[r]) {
+#pragma unroll
+        for (int c = 1; c < B; ++c) x[r][c] = -x[r][c] * ra;
+        x[r][0] = ra;
+      } else {
+        x[r][0] = f[r];
       }
+      // rotate: column j + 1 becomes x[r][0]
+      const double t0 = x[r][0];
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        if (isp[r]) {
-#pragma unroll
-          for (int c = 0; c < B; ++c) x[r][c] = (c == j) ? ra : -x[r][c] * ra;
-        } else {
-#pragma unroll
-          for (int c = 0; c < B; ++c)
-            if (c != j && c != j + 1) x[r][c] -= f[r] * PROW(c);
-          x[r][j] = f[r];
-        }
-      }
+      for (int c = 0; c + 1 < B; ++c) x[r][c] = x[r][c + 1];
+      x[r][B - 1] = t0;
+    }
 #undef PROW
+  }
+  // after b steps column c sits at (c - b) mod B: rotate the rest of the way
+#pragma unroll 1
+  for (int j = b; j < B; ++j) {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const double t0 = x[r][0];
+#pragma unroll
+      for (int c = 0; c + 1 < B; ++c) x[r][c] = x[r][c + 1];
+      x[r][B - 1] = t0;
     }
   }
   if (tid == 0) {
