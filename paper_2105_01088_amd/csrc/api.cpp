@@ -32,6 +32,8 @@ struct Arena {
 
 struct JobTable {
   GemmJob* dev = nullptr;
+  int* dmap = nullptr;  // workgroup -> job
+  int map_cap = 0;
   std::vector<GemmJob> host;
   int ntiles = 0;
   bool cplx = false;
@@ -99,6 +101,18 @@ void place_jobs(JobTable& t) {
     t.xm.max_tiles = std::max(t.xm.max_tiles, load[x]);
   }
   t.xm.off[8] = (int)t.host.size();
+}
+
+// workgroup -> job map of a placed table (entries 8 * tile + xcd)
+std::vector<int> job_map(const JobTable& t) {
+  std::vector<int> m(8 * (size_t)t.xm.max_tiles, -1);
+  for (int x = 0; x < 8; ++x)
+    for (int jid = t.xm.off[x]; jid < t.xm.off[x + 1]; ++jid) {
+      const GemmJob& j = t.host[jid];
+      const int nt = gemm_tiles(j.M, j.N, j.mirror);
+      for (int u = 0; u < nt; ++u) m[8 * (size_t)(j.tile_begin + u) + x] = jid;
+    }
+  return m;
 }
 
 GemmJob job(const double* A, int lda, int ta, const double* B, int ldb, int tb, const double* C, int ldc,
@@ -318,23 +332,32 @@ static void carve(Prob& q, Arena& ar) {
 
 static void carve_jobs(Prob& q, Arena& ar) {
   const int n = q.n;
+  const int T = (n + 63) / 64;
+  // job array plus a workgroup -> job map sized for jobs x T^2 tiles (every
+  // job of a table is at most n x n)
+  auto table = [&](JobTable& t, int jobs) {
+    jobs = std::max(1, jobs);
+    t.dev = ar.take<GemmJob>(jobs);
+    t.map_cap = 8 * jobs * T * T;
+    t.dmap = ar.take<int>((size_t)t.map_cap);
+  };
   const int ngj = (n + q.gj_nb - 1) / q.gj_nb;
   q.jgj0.assign(ngj, JobTable());
   q.jgj1.assign(ngj, JobTable());
-  for (auto& t : q.jgj0) t.dev = ar.take<GemmJob>(std::max(1, q.R - 1));
-  for (auto& t : q.jgj1) t.dev = ar.take<GemmJob>(std::max(1, q.P - (q.R - 1)));
+  for (auto& t : q.jgj0) table(t, q.R - 1);
+  for (auto& t : q.jgj1) table(t, q.P - (q.R - 1));
   int npf = 0;
   for (int m = n; m > 0; m -= 2 * pf_panel_shape(m).ns) ++npf;
   q.jpf.assign(npf, JobTable());
-  for (auto& t : q.jpf) t.dev = ar.take<GemmJob>(std::max(1, q.Q));
-  q.jdi.dev = ar.take<GemmJob>(std::max(1, q.P));
-  q.jt1.dev = ar.take<GemmJob>(std::max(1, q.R - 1));
-  q.jxr.dev = ar.take<GemmJob>(std::max(1, q.R - 1));
+  for (auto& t : q.jpf) table(t, q.Q);
+  table(q.jdi, q.P);
+  table(q.jt1, q.R - 1);
+  table(q.jxr, q.R - 1);
   for (int k = 0; k < 2; ++k) {
-    q.jnsq[k].dev = ar.take<GemmJob>(q.R);
-    q.jnsx[k].dev = ar.take<GemmJob>(q.R);
+    table(q.jnsq[k], q.R);
+    table(q.jnsx[k], q.R);
   }
-  q.jval.dev = ar.take<GemmJob>(q.R);
+  table(q.jval, q.R);
 }
 
 static int pick_gj_nb(int n, int lds_max) {
@@ -429,8 +452,16 @@ static hipError_t up(T* dev, const std::vector<T>& host) {
 
 static hipError_t upload_jobs(JobTable& t) {
   place_jobs(t);
+  t.xm.map = nullptr;
   if (t.host.empty()) return hipSuccess;
-  return hipMemcpy(t.dev, t.host.data(), t.host.size() * sizeof(GemmJob), hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(t.dev, t.host.data(), t.host.size() * sizeof(GemmJob), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  const std::vector<int> m = job_map(t);
+  if (t.dmap && (int)m.size() <= t.map_cap) {
+    e = hipMemcpy(t.dmap, m.data(), m.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) t.xm.map = t.dmap;
+  }
+  return e;
 }
 
 static int build_tables(Prob& q, const sgs_problem& sp) {

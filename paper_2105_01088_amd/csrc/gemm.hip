@@ -76,7 +76,10 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, XcdM
   const int x = blockIdx.x & 7;
   const int tile = blockIdx.x >> 3;
   if (xm.off[x] >= xm.off[x + 1]) return;
-  const int jid = find_job(jobs, xm.off[x], xm.off[x + 1] - 1, tile);
+  // one load instead of a chain of dependent ones: for the short-K updates
+  // the prologue's latency is a large part of the kernel
+  const int jid = xm.map ? xm.map[blockIdx.x] : find_job(jobs, xm.off[x], xm.off[x + 1] - 1, tile);
+  if (jid < 0) return;
   const Job J = jobs[jid];  // by value: the fields live in scalar registers
   const int mirror = J.mirror;
   const int ntile_job = mirror ? J.tiles_n * (J.tiles_n + 1) / 2 : J.tiles_n * ((J.M + 63) / 64);

@@ -66,9 +66,12 @@ __device__ __forceinline__ SGS_GLOBAL T* as_global(T* p) {
 
 // Jobs of XCD x occupy table entries [off[x], off[x+1]); their tile_begin
 // counts tiles within that XCD; max_tiles = largest per-XCD tile count.
+// map (optional, device): the job of every workgroup b (tile b / 8 of XCD
+// b % 8), -1 for none; without it the job is found by binary search.
 struct XcdMap {
   int off[9];
   int max_tiles;
+  const int* map;
 };
 
 // Launch helpers (gemm.hip).  jobs: device table ordered by XCD.
