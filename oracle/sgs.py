@@ -18,6 +18,9 @@ covariance-matrix step):
 4. First-order step, Eq. (RKstep), Gamma + ds dGamma, then the canonical form
    Eq. (CM-normal-form) with every lambda_j rescaled to unit modulus, i.e. the
    polar factor of the updated matrix (computed exactly with eigh).
+   Alternative (App. A, Eq. ExpStep): the orthogonal update R Gamma R^T with
+   R the matrix exponential of a multiple of [Gamma, dGamma] (scipy's expm),
+   with the coefficient read so that its first-order term is the Euler step.
 """
 
 from __future__ import annotations
@@ -26,6 +29,7 @@ from dataclasses import dataclass
 from typing import List, Optional
 
 import numpy as np
+import scipy.linalg
 import scipy.sparse as sparse
 
 from .gaussian import delta, fock_matrix, overlap_table, poly_value, quartic_tensor
@@ -115,6 +119,23 @@ def purify(x: np.ndarray) -> np.ndarray:
     return 0.5 * (g - g.T)
 
 
+# Exponential-map update (App. A, Eq. ExpStep): Gamma <- R Gamma R^T with R
+# the exponential of a multiple of the commutator [Gamma, dGamma].  For a
+# tangent dGamma (it anticommutes with Gamma, pinned) [[Gamma, dGamma], Gamma]
+# = 4 dGamma, so R = exp(c ds [Gamma, dGamma]) moves Gamma by 2 c ds dGamma to
+# first order: c = 1/4 agrees with the Euler step of Eq. RKstep, the printed
+# c = 1/2 takes a step of 2 ds.  EXP_COEF is the reading used here.
+EXP_COEF = 0.25
+
+
+def exp_update(g: np.ndarray, dg: np.ndarray, dtau: float, coef: float = EXP_COEF) -> np.ndarray:
+    K = coef * dtau * (g @ dg - dg @ g)
+    K = 0.5 * (K - K.T)
+    Rm = scipy.linalg.expm(K)
+    out = Rm @ g @ Rm.T
+    return 0.5 * (out - out.T)
+
+
 @dataclass
 class StepResult:
     gammas: np.ndarray
@@ -125,11 +146,17 @@ class StepResult:
 
 
 def step(ham, gammas: np.ndarray, dtau: float, mode: str = "printed",
-         rel_threshold: float = 1e-12, hpoly=None) -> StepResult:
+         rel_threshold: float = 1e-12, hpoly=None, update: str = "euler") -> StepResult:
+    """One step: tables, amplitudes, force, then either the Euler step with
+    purification (Eqs. RKstep, CM-normal-form) or the exponential map
+    (Eq. ExpStep), update = "euler" | "exp"."""
     tab = pair_tables(ham, gammas, hpoly=hpoly)
     E, lam = solve_amplitudes(tab.G, tab.h, rel_threshold)
     dg = forces(ham, gammas, tab, E, lam, mode)
-    new = np.stack([purify(gammas[m] + dtau * dg[m]) for m in range(gammas.shape[0])])
+    if update == "exp":
+        new = np.stack([exp_update(gammas[m], dg[m], dtau) for m in range(gammas.shape[0])])
+    else:
+        new = np.stack([purify(gammas[m] + dtau * dg[m]) for m in range(gammas.shape[0])])
     return StepResult(gammas=new, E=E, lam=lam, tables=tab, dgamma=dg)
 
 
@@ -140,13 +167,13 @@ def energy(ham, gammas: np.ndarray, hpoly=None):
 
 
 def run(ham, gammas: np.ndarray, dtau: float, nsteps: int, mode: str = "printed",
-        callback=None) -> tuple:
+        callback=None, update: str = "euler") -> tuple:
     """nsteps steps; returns (final gammas, energies of the states entering each step)."""
     hp = ham.poly()
     es: List[float] = []
     g = gammas
     for k in range(nsteps):
-        r = step(ham, g, dtau, mode, hpoly=hp)
+        r = step(ham, g, dtau, mode, hpoly=hp, update=update)
         es.append(r.E)
         g = r.gammas
         if callback is not None:

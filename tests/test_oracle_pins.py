@@ -327,3 +327,46 @@ def test_integrated_correlation_sum_rule_for_singlet():
     C = np.array([ob.expectation(g, lam, tab.G, si.spin_dot_poly((0, 1), (2 * r, 2 * r + 1))).real
                   for r in range(2)])
     assert ob.integrated_correlation(C)[-1] == pytest.approx(0.0, abs=1e-9)
+
+
+# ---------------------------------------------------------------- exp-map update (App. A)
+
+def test_exp_update_is_orthogonal_and_first_order_euler():
+    """Eq. ExpStep: R Gamma R^T keeps Gamma pure to rounding; with the 1/4
+    reading its first-order term is the Euler step of Eq. RKstep (the
+    difference to polar(Gamma + ds dGamma) shrinks as ds^3), and the printed
+    1/2 moves twice as far."""
+    ham = si.anderson(2, 1.3, 0.6)
+    g = si.random_states(ham.N, 3, seed=5)
+    r = sgs.step(ham, g, 0.05)
+    dg = r.dgamma
+    for m in range(3):
+        assert np.abs(dg[m] @ g[m] + g[m] @ dg[m]).max() < 1e-12  # tangent
+        out = sgs.exp_update(g[m], dg[m], 0.05)
+        assert np.abs(out @ out + np.eye(g.shape[1])).max() < 1e-13
+        errs = []
+        for ds in (0.02, 0.01, 0.005):
+            e = np.abs(sgs.exp_update(g[m], dg[m], ds) - sgs.purify(g[m] + ds * dg[m])).max()
+            errs.append(e)
+        # both are second-order retractions: the generator anticommutes with
+        # Gamma, so R Gamma R^T is the geodesic, and the polar projection
+        # matches the geodesic through second order; the gap is O(ds^3)
+        assert 6.5 < errs[0] / errs[1] < 9.5 and 6.5 < errs[1] / errs[2] < 9.5
+        # first order: (exp_update - Gamma) / ds -> dGamma; the printed 1/2 -> 2 dGamma
+        ds = 1e-5
+        d1 = (sgs.exp_update(g[m], dg[m], ds) - g[m]) / ds
+        d2 = (sgs.exp_update(g[m], dg[m], ds, coef=0.5) - g[m]) / ds
+        scale = np.abs(dg[m]).max()
+        assert np.abs(d1 - dg[m]).max() < 1e-3 * scale
+        assert np.abs(d2 - 2 * dg[m]).max() < 1e-3 * scale
+
+
+def test_exp_update_descends_and_reaches_ground_state():
+    """N = 4, R = 3 with the exponential map: monotone descent to the exact
+    even-sector ground state, as with the Euler step."""
+    N, terms = si.anderson_terms(1, 1.3, 0.7)
+    ham = si.anderson(1, 1.3, 0.7)
+    e_ed = ed.even_sector_ground_energy(N, terms)
+    _, es = sgs.run(ham, si.random_states(N, 3, seed=5), 0.05, 300, update="exp")
+    assert np.all(np.diff(es) <= 1e-12)
+    assert es[-1] == pytest.approx(e_ed, abs=1e-10)
