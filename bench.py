@@ -49,6 +49,8 @@ def main(argv=None):
     ap.add_argument("--weight", choices=["unit", "printed"], default="unit")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="fp32: the force's dense product on the FP32 matrix cores")
+    ap.add_argument("--update", choices=["euler", "exp"], default="euler",
+                    help="exp: the orthogonal exponential-map update instead of Euler + purification")
     ap.add_argument("--dtau", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -87,7 +89,8 @@ def main(argv=None):
     weight = 1 if args.weight == "unit" else 0
 
     prec = 1 if args.precision == "fp32" else 0
-    ctx = SGS([ham], [gam], options=default_options(weight=weight, precision=prec))
+    upd = 1 if args.update == "exp" else 0
+    ctx = SGS([ham], [gam], options=default_options(weight=weight, precision=prec, update=upd))
     stream = ctx.stream
     # warmup
     e_first = ctx.step(dtau, 1)
@@ -141,7 +144,7 @@ def main(argv=None):
             "workload": args.config,
             "model": cfg["model"], "L": cfg["L"], "N_modes": ham.N, "n_majoranas": n, "R": R,
             "pairs_per_step": P, "dtau": dtau, "seed": cfg["seed"],
-            "weights": args.weight, "precision": args.precision,
+            "weights": args.weight, "precision": args.precision, "update": args.update,
         },
         "roofline": {
             "bound": "mfma",
@@ -179,7 +182,7 @@ def main(argv=None):
             cores = os.cpu_count() or 1
         hp = ham.poly()
         c0 = time.time()
-        ref = osgs.step(ham, gam, dtau, mode=args.weight, hpoly=hp)
+        ref = osgs.step(ham, gam, dtau, mode=args.weight, hpoly=hp, update=args.update)
         c_dt = time.time() - c0
         out["cpu_baseline"] = {
             "value": P / c_dt,

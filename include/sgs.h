@@ -57,6 +57,8 @@ extern "C" {
 #define SGS_EHIP (-7)      /* a HIP runtime call failed                         */
 #define SGS_ESTATE (-8)    /* call order: e.g. sgs_energy before any evaluation */
 #define SGS_EWORKSPACE (-9)/* workspace smaller than sgs_workspace_bytes        */
+#define SGS_ERANGE (-10)   /* exponential map: |c dtau [Gamma, dGamma]|_1 above */
+                           /* 2^12 (or not finite) for some state             */
 
 /* sgs_options.precision */
 #define SGS_FP64 0          /* every stage in float64                          */
@@ -69,6 +71,14 @@ extern "C" {
 /* sgs_options.weight: the scalar c_mu of Eq. (Bmu) (Sec. III.A) */
 #define SGS_W_PRINTED 0     /* c_mu = 1 / (lambda_mu lambda~_mu^*)             */
 #define SGS_W_UNIT 1        /* c_mu = lambda~_mu lambda_mu^* / |lambda~_mu lambda_mu| */
+
+/* sgs_options.update: how a step moves the states (App. A) */
+#define SGS_UPD_EULER 0     /* Eq. (RKstep) Gamma + dtau dGamma, then the polar */
+                            /* factor (Eq. CM-normal-form with unit moduli)    */
+#define SGS_UPD_EXP 1       /* Eq. (ExpStep) R Gamma R^T, R = exp(c dtau        */
+                            /* [Gamma, dGamma]) with c = exp_coef: orthogonal, */
+                            /* no purification; scaling and squaring with a   */
+                            /* degree-17 Taylor polynomial (error < 2e-16)    */
 
 /* sgs_observables kinds */
 #define SGS_OBS_POLY 1      /* <psi| O |psi> for Majorana polynomials O        */
@@ -100,6 +110,12 @@ typedef struct {
   int32_t streams;         /* independent problems run concurrently on up to  */
                            /* this many HIP streams, each with its own scratch*/
                            /* (1..4, default 4)                               */
+  int32_t update;          /* SGS_UPD_EULER (default) or SGS_UPD_EXP           */
+  double exp_coef;         /* c of SGS_UPD_EXP, 0 < c <= 1e6 (default 1/4:    */
+                           /* for a tangent dGamma [[Gamma, dGamma], Gamma] = */
+                           /* 4 dGamma, so 1/4 makes the first-order term the */
+                           /* Euler step; the value printed in App. A, 1/2,   */
+                           /* takes a step of 2 dtau)                         */
 } sgs_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -173,7 +189,7 @@ int sgs_observables(sgs_ctx* ctx, int32_t kind, const int32_t* iargs,
                     double* out);
 
 /* Wait for the context's stream and return the device status word:
- * SGS_OK, SGS_ESINGULAR or SGS_ENOCONV (first failure since the last call;
+ * SGS_OK, SGS_ESINGULAR, SGS_ENOCONV or SGS_ERANGE (first failure since the last call;
  * reading it clears it), or SGS_EHIP. */
 int sgs_status(sgs_ctx* ctx);
 
@@ -192,7 +208,8 @@ int sgs_status(sgs_ctx* ctx);
 #define SGS_STAGE_PFAFFIAN 4  /* complex Pfaffians of C_ab                       */
 #define SGS_STAGE_SOLVE 5     /* h lambda = E G lambda, weights, coefficients   */
 #define SGS_STAGE_FORCE 6     /* Eq. (EOM-Gamma3) accumulation                   */
-#define SGS_STAGE_PURIFY 7    /* Euler step and polar purification               */
+#define SGS_STAGE_PURIFY 7    /* Euler step and polar purification, or the      */
+                              /* exponential map                                 */
 #define SGS_NSTAGE 8
 int sgs_set_timing(sgs_ctx* ctx, int32_t enable);
 int sgs_stage_times(sgs_ctx* ctx, double* ms, int32_t* launches, int32_t nstage);

@@ -16,6 +16,8 @@ from ._lib import (  # noqa: F401
     SGS_FP32_REFINE,
     SGS_W_PRINTED,
     SGS_W_UNIT,
+    SGS_UPD_EULER,
+    SGS_UPD_EXP,
     SGS_OBS_POLY,
     SGS_OBS_RENYI2,
 )

@@ -20,6 +20,8 @@ SGS_FP64 = 0
 SGS_FP32_REFINE = 1
 SGS_W_PRINTED = 0
 SGS_W_UNIT = 1
+SGS_UPD_EULER = 0
+SGS_UPD_EXP = 1
 SGS_OBS_POLY = 1
 SGS_OBS_RENYI2 = 2
 STAGES = ("inverse", "delta", "wick", "phase", "pfaffian", "solve", "force", "purify")
@@ -39,7 +41,7 @@ class sgs_problem(ctypes.Structure):
 class sgs_options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("weight", c_int32), ("g_rel_threshold", c_double),
                 ("purify_tol", c_double), ("purify_iters", c_int32),
-                ("streams", c_int32)]
+                ("streams", c_int32), ("update", c_int32), ("exp_coef", c_double)]
 
 
 _lib = None

@@ -44,6 +44,7 @@ struct Prob {
   int N = 0, n = 0, R = 0, P = 0, Q = 0, M = 0, nq = 0, nnz_up = 0, nnz = 0;
   int gj_nb = 16;
   int worker = 0;  // stream (and scratch region) this problem runs on
+  bool expmap = false;  // exponential-map update instead of Euler + purification
   double e0 = 0.0;
   double* gam = nullptr;
   // dense work
@@ -57,6 +58,11 @@ struct Prob {
   int* nsctl;
   ForceTerm* terms;
   JobTable jdi, jt1, jxr, jnsq[2], jnsx[2], jval;
+  // exponential map: P = Gamma dGamma, Y = K^2, Z = Y^2, the three
+  // Paterson-Stockmeyer steps, R = C + K S, squarings, R Gamma, (R Gamma) R^T
+  double *ex0 = nullptr, *ex1 = nullptr, *ex2 = nullptr, *ex3 = nullptr, *exrow = nullptr, *expar = nullptr;
+  JobTable jexp_p, jexp_y, jexp_z, jexp_h[3], jexp_r, jexp_sq[2], jexp_q, jexp_g;
+  ExpCoef excf{};
   std::vector<JobTable> jgj0, jgj1, jpf;  // GJ updates: pairs (0, a), then the rest
   std::vector<int> gj_k, gj_b, pf_m;
   long long uvstride = 0, uv_im = 0;
@@ -286,6 +292,14 @@ static void carve_scratch(Prob& q, Arena& ar) {
   q.nsX1 = ar.take<double>(R * nn);
   q.nsQ = ar.take<double>(R * nn);
   q.piv = ar.take<int>(std::max(1LL, 2LL * P * n));  // pivots, then unscramble sources
+  if (q.expmap) {
+    q.ex0 = ar.take<double>(R * nn);
+    q.ex1 = ar.take<double>(R * nn);
+    q.ex2 = ar.take<double>(R * nn);
+    q.ex3 = ar.take<double>(R * nn);
+    q.exrow = ar.take<double>((long long)R * n);
+    q.expar = ar.take<double>(4);
+  }
 }
 
 // Per-problem state that persists between calls (tables, amplitudes, the
@@ -358,6 +372,16 @@ static void carve_jobs(Prob& q, Arena& ar) {
     table(q.jnsx[k], q.R);
   }
   table(q.jval, q.R);
+  if (q.expmap) {
+    table(q.jexp_p, q.R);
+    table(q.jexp_y, q.R);
+    table(q.jexp_z, q.R);
+    for (auto& t : q.jexp_h) table(t, 2 * q.R);
+    table(q.jexp_r, q.R);
+    for (auto& t : q.jexp_sq) table(t, q.R);
+    table(q.jexp_q, q.R);
+    table(q.jexp_g, q.R);
+  }
 }
 
 static int pick_gj_nb(int n, int lds_max) {
@@ -375,7 +399,7 @@ static int device_lds_max() {
 constexpr int MAX_WORKERS = 4;  // concurrent streams for independent problems
 
 static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, char* base, int lds_max,
-                   int max_workers, ObsBuf* ob = nullptr, int* nworkers = nullptr) {
+                   int max_workers, bool expmap, ObsBuf* ob = nullptr, int* nworkers = nullptr) {
   Arena ar{base, 0};
   ar.take<int>(64);  // status word and spare
   {
@@ -397,6 +421,7 @@ static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, c
     q.M = sp.nq > 0 ? impurity_count(sp) : 0;
     q.nnz = nnz_count(sp, &q.nnz_up);
     q.gj_nb = pick_gj_nb(q.n, lds_max);
+    q.expmap = expmap;
     carve(q, ar);
     carve_jobs(q, ar);
   }
@@ -462,6 +487,65 @@ static hipError_t upload_jobs(JobTable& t) {
     if (e == hipSuccess) t.xm.map = t.dmap;
   }
   return e;
+}
+
+// Job tables of the exponential-map update (buffers: P -> nsX0, K -> nsQ,
+// Y -> nsX1, Z -> dG; the even / odd polynomials ping-pong between ex0 / ex1
+// and ex2 / ex3; R -> nsX0, squarings nsX0 <-> ex0; R Gamma -> nsQ).
+static hipError_t build_exp_jobs(Prob& q) {
+  const int n = q.n, R = q.R;
+  const long long nn = (long long)n * n;
+  double cf[9], sf[9];
+  {
+    double f = 1.0;  // k!
+    for (int k = 0; k <= 17; ++k) {
+      if (k > 0) f *= k;
+      if (k % 2 == 0) cf[k / 2] = 1.0 / f; else sf[k / 2] = 1.0 / f;
+    }
+  }
+  auto reset = [](JobTable& t) { t.host.clear(); t.ntiles = 0; };
+  JobTable* all[] = {&q.jexp_p, &q.jexp_y, &q.jexp_z, &q.jexp_h[0], &q.jexp_h[1], &q.jexp_h[2],
+                     &q.jexp_r, &q.jexp_sq[0], &q.jexp_sq[1], &q.jexp_q, &q.jexp_g};
+  for (JobTable* t : all) reset(*t);
+  for (int mu = 0; mu < R; ++mu) {
+    const long long o = mu * nn;
+    double *P = q.nsX0 + o, *K = q.nsQ + o, *Y = q.nsX1 + o, *Z = q.dG + o, *G = q.gam + o;
+    add_job(q.jexp_p, job(G, n, 0, q.dG + o, n, 0, nullptr, n, P, n, n, n, n, 1.0, 0.0));
+    GemmJob jy = job(K, n, 0, K, n, 0, nullptr, n, Y, n, n, n, n, 1.0, 0.0);
+    jy.mirror = 1;
+    add_job(q.jexp_y, jy);
+    GemmJob jz = job(Y, n, 0, Y, n, 0, nullptr, n, Z, n, n, n, n, 1.0, 0.0);
+    jz.mirror = 1;
+    add_job(q.jexp_z, jz);
+    // B_{k} = Z B_{k+1} + c_{2k+1} Y + c_{2k} I for k = 2, 1, 0 (C and S)
+    double* cin[3] = {q.ex0 + o, q.ex2 + o, q.ex0 + o};
+    double* cout[3] = {q.ex2 + o, q.ex0 + o, q.ex2 + o};
+    double* sin_[3] = {q.ex1 + o, q.ex3 + o, q.ex1 + o};
+    double* sout[3] = {q.ex3 + o, q.ex1 + o, q.ex3 + o};
+    for (int h = 0; h < 3; ++h) {
+      const int k = 2 - h;
+      GemmJob jc = job(Z, n, 0, cin[h], n, 0, Y, n, cout[h], n, n, n, n, 1.0, cf[2 * k + 1], cf[2 * k]);
+      jc.mirror = 1;
+      add_job(q.jexp_h[h], jc);
+      GemmJob js = job(Z, n, 0, sin_[h], n, 0, Y, n, sout[h], n, n, n, n, 1.0, sf[2 * k + 1], sf[2 * k]);
+      js.mirror = 1;
+      add_job(q.jexp_h[h], js);
+    }
+    // R = K S + C into nsX0 (P is no longer needed)
+    add_job(q.jexp_r, job(K, n, 0, q.ex3 + o, n, 0, q.ex2 + o, n, q.nsX0 + o, n, n, n, n, 1.0, 1.0));
+    add_job(q.jexp_sq[0], job(q.nsX0 + o, n, 0, q.nsX0 + o, n, 0, nullptr, n, q.ex0 + o, n, n, n, n, 1.0, 0.0));
+    add_job(q.jexp_sq[1], job(q.ex0 + o, n, 0, q.ex0 + o, n, 0, nullptr, n, q.nsX0 + o, n, n, n, n, 1.0, 0.0));
+    add_job(q.jexp_q, job(q.nsX0 + o, n, 0, G, n, 0, nullptr, n, q.nsQ + o, n, n, n, n, 1.0, 0.0));
+    GemmJob jg = job(q.nsQ + o, n, 0, q.nsX0 + o, n, 1, nullptr, n, G, n, n, n, n, 1.0, 0.0);
+    jg.mirror = -1;  // R Gamma R^T is skew
+    add_job(q.jexp_g, jg);
+  }
+  for (JobTable* t : all) {
+    hipError_t e = upload_jobs(*t);
+    if (e != hipSuccess) return e;
+  }
+  for (int k = 0; k < 9; ++k) { q.excf.c[k] = cf[k]; q.excf.s[k] = sf[k]; }
+  return hipSuccess;
 }
 
 static int build_tables(Prob& q, const sgs_problem& sp) {
@@ -594,6 +678,7 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
   for (int mu = 0; mu < R; ++mu)
     add_job(q.jval, job(q.gam + mu * nn, n, 0, q.gam + mu * nn, n, 0, nullptr, n, q.nsQ + mu * nn, n, n, n, n, 1.0, 0.0));
   HIPCHK(upload_jobs(q.jval));
+  if (q.expmap) HIPCHK(build_exp_jobs(q));
 
   // force descriptors
   std::vector<ForceTerm> terms((size_t)R * R);
@@ -725,6 +810,24 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
   tm.end(SGS_STAGE_FORCE, s);
   (void)nn;
   tm.begin(SGS_STAGE_PURIFY, s);
+  if (q.expmap) {
+    HCHK(run_gemm(q.jexp_p, s));
+    HCHK(launch_exp_gen(q.nsX0, n, R, c->opt.exp_coef * dtau, q.nsQ, q.exrow, EXP_SMAX, q.nsctl, q.expar,
+                        c->status, s));
+    HCHK(run_gemm(q.jexp_y, s));
+    HCHK(run_gemm(q.jexp_z, s));
+    HCHK(launch_exp_b3(q.nsX1, q.dG, n, R, q.excf, q.ex0, q.ex1, s));
+    for (int h = 0; h < 3; ++h) HCHK(run_gemm(q.jexp_h[h], s));
+    HCHK(run_gemm(q.jexp_r, s));
+    for (int it = 0; it < EXP_SMAX; ++it)
+      HCHK(launch_gemm(q.jexp_sq[it & 1].dev, q.jexp_sq[it & 1].xm, false, s, q.nsctl, it, nullptr, 0.0, nullptr));
+    HCHK(launch_exp_pick(q.nsX0, q.ex0, n, R, q.nsctl, s));
+    HCHK(run_gemm(q.jexp_q, s));
+    HCHK(run_gemm(q.jexp_g, s));
+    HCHK(launch_exp_skew_diag(q.gam, n, R, s));
+    tm.end(SGS_STAGE_PURIFY, s);
+    return hipSuccess;
+  }
   const int maxit = c->opt.purify_iters;
   unsigned long long* rs = q.resid + 8;
   HCHK(launch_euler(q.gam, q.dG, dtau, n, R, q.nsX0, q.nsctl, rs, maxit, q.dgnorm, s));
@@ -754,6 +857,8 @@ void sgs_default_options(sgs_options* o) {
   o->purify_tol = 1e-12;
   o->purify_iters = 24;
   o->streams = MAX_WORKERS;
+  o->update = SGS_UPD_EULER;
+  o->exp_coef = 0.25;
 }
 
 static int check_options(const sgs_options& o) {
@@ -762,6 +867,8 @@ static int check_options(const sgs_options& o) {
   if (!(o.g_rel_threshold > 0.0 && o.g_rel_threshold < 1.0)) return SGS_EINVAL;
   if (!(o.purify_tol > 0.0) || o.purify_iters < 1 || o.purify_iters > 64) return SGS_EINVAL;
   if (o.streams < 1 || o.streams > MAX_WORKERS) return SGS_EINVAL;
+  if (o.update != SGS_UPD_EULER && o.update != SGS_UPD_EXP) return SGS_EINVAL;
+  if (!(o.exp_coef > 0.0 && o.exp_coef <= 1e6)) return SGS_EINVAL;
   return SGS_OK;
 }
 
@@ -775,7 +882,7 @@ int sgs_workspace_bytes(const sgs_problem* probs, int32_t nprob, const sgs_optio
   for (int p = 0; p < nprob; ++p)
     if ((rc = check_problem(probs[p]))) return rc;
   std::vector<Prob> pr;
-  *bytes = plan(pr, probs, nprob, nullptr, device_lds_max(), o.streams);
+  *bytes = plan(pr, probs, nprob, nullptr, device_lds_max(), o.streams, o.update == SGS_UPD_EXP);
   return SGS_OK;
 }
 
@@ -796,7 +903,8 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
   c->s = (hipStream_t)stream;
   c->lds_max = device_lds_max();
   int nworkers = 1;
-  const size_t need = plan(c->pr, probs, nprob, (char*)workspace, c->lds_max, c->opt.streams, &c->obs, &nworkers);
+  const size_t need = plan(c->pr, probs, nprob, (char*)workspace, c->lds_max, c->opt.streams,
+                           c->opt.update == SGS_UPD_EXP, &c->obs, &nworkers);
   if (ws_bytes < need) { delete c; return SGS_EWORKSPACE; }
   c->status = (int*)workspace;
   double* g = gamma;
@@ -1028,6 +1136,7 @@ const char* sgs_strerror(int code) {
     case SGS_EHIP: return "HIP runtime error";
     case SGS_ESTATE: return "call out of order";
     case SGS_EWORKSPACE: return "workspace too small";
+    case SGS_ERANGE: return "exponential-map generator too large (or not finite)";
     default: return "unknown error";
   }
 }

@@ -84,7 +84,7 @@ hipError_t launch_gemm_f32(const GemmJobF* jobs, const XcdMap& xm, hipStream_t s
 // ---------------------------------------------------------------------------
 // Status word (device int): first failure wins.
 // ---------------------------------------------------------------------------
-enum : int { ST_OK = 0, ST_SINGULAR = -5, ST_NOCONV = -6 };
+enum : int { ST_OK = 0, ST_SINGULAR = -5, ST_NOCONV = -6, ST_RANGE = -10 };
 
 // ---------------------------------------------------------------------------
 // Force accumulation: one output state mu, R descriptors (one per beta).
@@ -210,6 +210,19 @@ hipError_t launch_euler(const double* gam, const double* dG, double dtau, int n,
 hipError_t launch_ns_resid(const double* Q, int n, long long total, unsigned long long* out, hipStream_t s);
 hipError_t launch_ns_check(const double* Q, int n, int R, unsigned long long* resid, int* ctl, int it,
                            double thr, hipStream_t s);
+// Taylor coefficients of the even and odd parts of exp: c[j] = 1 / (2j)!,
+// s[j] = 1 / (2j + 1)!, j = 0..8.
+struct ExpCoef {
+  double c[9];
+  double s[9];
+};
+constexpr int EXP_SMAX = 12;  // squarings: |c ds [Gamma, dGamma]|_1 <= 2^12
+hipError_t launch_exp_gen(const double* P, int n, int R, double cds, double* K, double* rowsum, int smax,
+                          int* ctl, double* par, int* status, hipStream_t s);
+hipError_t launch_exp_b3(const double* Y, const double* Z, int n, int R, const ExpCoef& cf, double* E0, double* E1,
+                         hipStream_t s);
+hipError_t launch_exp_skew_diag(double* D, int n, int R, hipStream_t s);
+hipError_t launch_exp_pick(double* X0, const double* X1, int n, int R, const int* ctl, hipStream_t s);
 hipError_t launch_finalize(const double* X0, const double* X1, int n, int R, double* gam, const int* ctl,
                            int maxit, int* status, hipStream_t s);
 hipError_t launch_skew_resid(const double* G, int n, long long total, unsigned long long* out,

@@ -37,6 +37,7 @@ def test_default_options():
     o = default_options()
     assert o.precision == SGS_FP64 and o.weight == SGS_W_PRINTED
     assert o.g_rel_threshold == 1e-12 and o.purify_iters >= 3
+    assert o.update == 0 and o.exp_coef == 0.25  # Euler + purification; App. A coefficient read as 1/4
 
 
 def _ws(ham, R, **opt):
@@ -75,6 +76,21 @@ def test_rejects_bad_problems_and_options():
     assert _ws(ham, 2, weight=7)[0] == -1
     assert _ws(ham, 2, precision=5)[0] == -1
     assert _ws(ham, 2, purify_iters=0)[0] == -1
+    assert _ws(ham, 2, update=2)[0] == -1
+    assert _ws(ham, 2, update=1, exp_coef=0.0)[0] == -1
+    assert _ws(ham, 2, update=1, exp_coef=float("nan"))[0] == -1
+
+
+def test_exponential_map_workspace():
+    """The exponential map carves four more R n^2 buffers, the n R row sums
+    and its job tables; the Euler workspace is unchanged by the option's
+    existence."""
+    ham = si.anderson(7, 1.0, 0.5)
+    rc0, b0 = _ws(ham, 4)
+    rc1, b1 = _ws(ham, 4, update=1)
+    assert rc0 == 0 and rc1 == 0
+    n = ham.n
+    assert b1 - b0 >= 4 * 4 * n * n * 8
 
 
 def test_strerror_and_null_context():
@@ -82,6 +98,7 @@ def test_strerror_and_null_context():
     lib = load_library()
     assert lib.sgs_strerror(0) == b"ok"
     assert b"workspace" in lib.sgs_strerror(-9)
+    assert b"exponential" in lib.sgs_strerror(-10)
     assert lib.sgs_step(None, 0.05, 1, None) == -1
     assert lib.sgs_pair_eval(None, None, None, None) == -1
     assert lib.sgs_energy(None, None, None) == -1
