@@ -109,7 +109,9 @@ def main(argv=None):
     torch.cuda.synchronize()
     wall0 = time.time()
     t0.record(stream)
+    h0 = time.perf_counter()
     energies = ctx.step(dtau, args.steps)
+    host_enqueue = time.perf_counter() - h0
     t1.record(stream)
     torch.cuda.synchronize()
     wall = time.time() - wall0
@@ -119,6 +121,21 @@ def main(argv=None):
     st = ctx.status()
     if st != 0:
         raise SystemExit(f"device status {st} in the timed region")
+
+    # the standalone table evaluation (sgs_pair_eval: inverses, overlaps,
+    # phases, Wick elements and the amplitude solve, no force or update)
+    ctx.pair_eval()
+    torch.cuda.synchronize()
+    p0 = torch.cuda.Event(enable_timing=True)
+    p1 = torch.cuda.Event(enable_timing=True)
+    p0.record(stream)
+    for _ in range(args.steps):
+        ctx.pair_eval()
+    p1.record(stream)
+    torch.cuda.synchronize()
+    ms_pe = p0.elapsed_time(p1) / args.steps
+    if ctx.status() != 0:
+        raise SystemExit("device status error in sgs_pair_eval")
 
     ms_step = ms_total / args.steps
     value = P * args.steps / (ms_total / 1e3)
@@ -157,8 +174,10 @@ def main(argv=None):
             "force_avg_ms": f_avg_ms,
             "force_flops_per_launch": force_flops(n, R),
         },
+        "pair_eval": {"ms_per_call": ms_pe, "pair_evals_per_s": P / (ms_pe / 1e3)},
         "stages_ms_per_step": {k: v[0] / max(1, args.steps) for k, v in stages.items()},
         "wall_s": wall,
+        "host_enqueue_ms_per_step": host_enqueue * 1e3 / args.steps,
         "E_last": float(energies[-1].item()),
     }
 

@@ -54,6 +54,7 @@ struct Prob {
   double *up_v, *colval, *q_val;
   int *piv, *pa, *pb, *qa, *qb, *pidx, *qidx, *up_k, *up_l, *colptr, *rowidx, *imp, *impos, *q_idx, *q_loc, *pfperm;
   unsigned long long* resid;
+  unsigned long long* nsres;
   unsigned long long* dgnorm;
   int* nsctl;
   ForceTerm* terms;
@@ -187,8 +188,9 @@ struct ObsBuf {
 struct Worker {
   hipStream_t s = nullptr;
   bool own_s = false;
-  hipStream_t s2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_done = nullptr;
+  hipStream_t s2 = nullptr;  // phase chain
+  hipStream_t s3 = nullptr;  // inverses of the pairs not involving state 0
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_done = nullptr, ev_gj = nullptr, ev_gj_done = nullptr;
   int owner = -1;  // problem whose scratch tables are current
 };
 
@@ -209,7 +211,10 @@ struct sgs_ctx {
       if (w.ev_fork) (void)hipEventDestroy(w.ev_fork);
       if (w.ev_join) (void)hipEventDestroy(w.ev_join);
       if (w.ev_done) (void)hipEventDestroy(w.ev_done);
+      if (w.ev_gj) (void)hipEventDestroy(w.ev_gj);
+      if (w.ev_gj_done) (void)hipEventDestroy(w.ev_gj_done);
       if (w.s2) (void)hipStreamDestroy(w.s2);
+      if (w.s3) (void)hipStreamDestroy(w.s3);
       if (w.own_s && w.s) (void)hipStreamDestroy(w.s);
     }
     if (ev_start) (void)hipEventDestroy(ev_start);
@@ -338,8 +343,9 @@ static void carve(Prob& q, Arena& ar) {
   q.impos = ar.take<int>(n);
   q.q_idx = ar.take<int>(std::max(1, 4 * q.nq));
   q.q_loc = ar.take<int>(std::max(1, 4 * q.nq));
-  q.resid = ar.take<unsigned long long>(72);  // [0]: validation; [8 + it]: polar iterations
-  q.nsctl = ar.take<int>(4);
+  q.resid = ar.take<unsigned long long>(8);  // [0]: input validation
+  q.nsctl = ar.take<int>(std::max(4, R));  // one control word per state
+  q.nsres = ar.take<unsigned long long>(64 * (size_t)R);  // [it * R + mu]: polar residuals
   q.dgnorm = ar.take<unsigned long long>(32);
   q.terms = ar.take<ForceTerm>((size_t)R * R);
 }
@@ -665,10 +671,12 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
     for (int mu = 0; mu < R; ++mu) {
       GemmJob jq = job(Xin + mu * nn, n, 0, Xin + mu * nn, n, 0, nullptr, n, q.nsQ + mu * nn, n, n, n, n, 1.0, 0.0);
       jq.mirror = 1;  // X^2 is symmetric for skew X
+      jq.gate = mu;
       add_job(q.jnsq[par], jq);
       GemmJob jx = job(Xin + mu * nn, n, 0, q.nsQ + mu * nn, n, 0, Xin + mu * nn, n, Xout + mu * nn, n, n, n, n,
                        0.5, 1.5);
       jx.mirror = -1;  // X (3 + X^2) / 2 is skew
+      jx.gate = mu;
       add_job(q.jnsx[par], jx);
     }
     HIPCHK(upload_jobs(q.jnsq[par])); HIPCHK(upload_jobs(q.jnsx[par]));
@@ -733,41 +741,51 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
     // runs in the Di buffer (overwritten by the transition matrices next)
     tm.begin(SGS_STAGE_INVERSE, s);
     HCHK(launch_pair_sum(q.gam, n, q.pa, q.pb, P, q.Di, q.logdet, s));
-    for (int half = 0; half < 2; ++half) {
+    // one batch of inverses: panels, grouped updates, unscramble
+    auto inverses = [&](int half, hipStream_t st) -> hipError_t {
       const int off = half == 0 ? 0 : P0, cnt = half == 0 ? P0 : P - P0;
-      if (cnt > 0) {
-        for (size_t t = 0; t < q.gj_k.size(); ++t) {
-          HCHK(launch_gj_panel(q.Di + off * nn, nn, cnt, n, q.gj_k[t], q.gj_b[t],
-                               q.gjE + (long long)off * n * GJ_NB_MAX, (long long)n * GJ_NB_MAX,
-                               q.gjB + (long long)off * n * GJ_NB_MAX, (long long)n * GJ_NB_MAX,
-                               q.piv + (long long)off * n, q.piv + (long long)(P + off) * n, q.logdet + off,
-                               c->status, s));
-          HCHK(run_gemm(half == 0 ? q.jgj0[t] : q.jgj1[t], s));
-        }
-        HCHK(launch_gj_unscramble(q.Di + off * nn, q.W + off * nn, nn, cnt, n, q.piv + (long long)off * n,
-                                  q.piv + (long long)(P + off) * n, s));
+      for (size_t t = 0; t < q.gj_k.size(); ++t) {
+        HCHK(launch_gj_panel(q.Di + off * nn, nn, cnt, n, q.gj_k[t], q.gj_b[t],
+                             q.gjE + (long long)off * n * GJ_NB_MAX, (long long)n * GJ_NB_MAX,
+                             q.gjB + (long long)off * n * GJ_NB_MAX, (long long)n * GJ_NB_MAX,
+                             q.piv + (long long)off * n, q.piv + (long long)(P + off) * n, q.logdet + off,
+                             c->status, st));
+        HCHK(run_gemm(half == 0 ? q.jgj0[t] : q.jgj1[t], st));
       }
-      if (half == 0 && fork) {
-        // phases on the second stream, concurrent with the other inverses
-        HCHK(hipEventRecord(wk.ev_fork, s));
-        HCHK(hipStreamWaitEvent(wk.s2, wk.ev_fork, 0));
-        hipStream_t s2 = wk.s2;
-        tm.begin(SGS_STAGE_PHASE, s2);
-        HCHK(run_gemm(q.jt1, s2));
-        HCHK(run_gemm(q.jxr, s2));
-        HCHK(launch_build_c(n, q.gam, q.T1, q.Xr, q.qa, q.qb, q.Q, q.Cm, s2));
-        tm.end(SGS_STAGE_PHASE, s2);
-        tm.begin(SGS_STAGE_PFAFFIAN, s2);
-        for (size_t t = 0; t < q.pf_m.size(); ++t) {
-          const double* cin = (t & 1) ? q.Cm2 : q.Cm;
-          HCHK(launch_pf_panel(cin, 2 * nn, nn, n, q.pf_m[t], q.Q, q.UV, q.RM, q.uvstride, q.uv_im, q.pfperm, n,
-                               q.pfacc, t == 0, c->status, s2));
-          HCHK(run_gemm(q.jpf[t], s2));
-        }
-        tm.end(SGS_STAGE_PFAFFIAN, s2);
-        HCHK(hipEventRecord(wk.ev_join, s2));
-      }
+      return launch_gj_unscramble(q.Di + off * nn, q.W + off * nn, nn, cnt, n, q.piv + (long long)off * n,
+                                  q.piv + (long long)(P + off) * n, st);
+    };
+    // the pairs (a, b), 1 <= a < b, on the third stream from the start; the
+    // pairs (0, a) on the main stream, then the phase chain forks from it
+    const bool rest = P - P0 > 0;
+    if (rest) {
+      HCHK(hipEventRecord(wk.ev_gj, s));
+      HCHK(hipStreamWaitEvent(wk.s3, wk.ev_gj, 0));
+      HCHK(inverses(1, wk.s3));
+      HCHK(hipEventRecord(wk.ev_gj_done, wk.s3));
     }
+    if (P0 > 0) HCHK(inverses(0, s));
+    if (fork) {
+      // phases on the second stream, concurrent with the other inverses
+      HCHK(hipEventRecord(wk.ev_fork, s));
+      HCHK(hipStreamWaitEvent(wk.s2, wk.ev_fork, 0));
+      hipStream_t s2 = wk.s2;
+      tm.begin(SGS_STAGE_PHASE, s2);
+      HCHK(run_gemm(q.jt1, s2));
+      HCHK(run_gemm(q.jxr, s2));
+      HCHK(launch_build_c(n, q.gam, q.T1, q.Xr, q.qa, q.qb, q.Q, q.Cm, s2));
+      tm.end(SGS_STAGE_PHASE, s2);
+      tm.begin(SGS_STAGE_PFAFFIAN, s2);
+      for (size_t t = 0; t < q.pf_m.size(); ++t) {
+        const double* cin = (t & 1) ? q.Cm2 : q.Cm;
+        HCHK(launch_pf_panel(cin, 2 * nn, nn, n, q.pf_m[t], q.Q, q.UV, q.RM, q.uvstride, q.uv_im, q.pfperm, n,
+                             q.pfacc, t == 0, c->status, s2));
+        HCHK(run_gemm(q.jpf[t], s2));
+      }
+      tm.end(SGS_STAGE_PFAFFIAN, s2);
+      HCHK(hipEventRecord(wk.ev_join, s2));
+    }
+    if (rest) HCHK(hipStreamWaitEvent(s, wk.ev_gj_done, 0));
     tm.end(SGS_STAGE_INVERSE, s);
     // transition matrices
     tm.begin(SGS_STAGE_DELTA, s);
@@ -829,15 +847,17 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
     return hipSuccess;
   }
   const int maxit = c->opt.purify_iters;
-  unsigned long long* rs = q.resid + 8;
-  HCHK(launch_euler(q.gam, q.dG, dtau, n, R, q.nsX0, q.nsctl, rs, maxit, q.dgnorm, s));
+  unsigned long long* rs = q.nsres;
+  HCHK(launch_euler(q.gam, q.dG, dtau, n, R, q.nsX0, q.nsctl, rs, maxit * R, q.dgnorm, s));
   const double thr = std::min(1e-8, std::sqrt(c->opt.purify_tol));
   for (int it = 0; it < maxit; ++it) {
     const int par = it & 1;
-    // Q = X X with max|Q + 1| into rs[it]; then X' = X (3 + Q) / 2, which
-    // marks this iteration as the last when rs[it] < thr
-    HCHK(launch_gemm(q.jnsq[par].dev, q.jnsq[par].xm, false, s, q.nsctl, it, nullptr, 0.0, rs + it));
-    HCHK(launch_gemm(q.jnsx[par].dev, q.jnsx[par].xm, false, s, q.nsctl, it, rs + it, thr, nullptr));
+    // Q = X X with max|Q + 1| of state mu into rs[it R + mu]; then
+    // X' = X (3 + Q) / 2, which marks this iteration as state mu's last when
+    // that residual is below thr
+    unsigned long long* ri = rs + (size_t)it * R;
+    HCHK(launch_gemm(q.jnsq[par].dev, q.jnsq[par].xm, false, s, q.nsctl, it, nullptr, 0.0, ri));
+    HCHK(launch_gemm(q.jnsx[par].dev, q.jnsx[par].xm, false, s, q.nsctl, it, ri, thr, nullptr));
   }
   HCHK(launch_finalize(q.nsX0, q.nsX1, n, R, q.gam, q.nsctl, c->opt.purify_iters, c->status, s));
   tm.end(SGS_STAGE_PURIFY, s);
@@ -937,6 +957,9 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
       k.own_s = true;
     }
     if (hipStreamCreateWithFlags(&k.s2, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&k.s3, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&k.ev_gj, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&k.ev_gj_done, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&k.ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&k.ev_join, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&k.ev_done, hipEventDisableTiming) != hipSuccess) { delete c; return SGS_EHIP; }

@@ -51,22 +51,18 @@ __device__ __forceinline__ int find_job(const Job* __restrict__ jobs, int lo, in
 constexpr int TK = 16;
 constexpr int LDP = 64 + 1;  // LDS row pitch (elements), padded
 
-// Iterative callers (the polar iteration) pass a control word ctl: the launch
-// of iteration `it` exits at once when ctl[0] < it.  rchk (optional) is the
-// residual measured on this iteration's input: if it is below thr, this
-// iteration is the last one (ctl[0] = it).  rmax (optional) receives
-// max |D + 1| over the launch (D square), as an ordered bit pattern.
+// Iterative callers (the polar iteration) pass control words ctl, one per
+// gate (a job's `gate` field, its state): the workgroups of a job of
+// iteration `it` exit at once when ctl[gate] < it.  rchk (optional) holds the
+// residuals measured on this iteration's inputs: if rchk[gate] is below thr,
+// this iteration is the job's last one (ctl[gate] = it).  rmax (optional)
+// receives max |D + 1| over each job's outputs (D square) in rmax[gate], as
+// an ordered bit pattern.
 template <typename T, typename Job, bool CPLX>
 __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, XcdMap xm,
                                               int* __restrict__ ctl, int it,
                                               const unsigned long long* __restrict__ rchk, double thr,
                                               unsigned long long* __restrict__ rmax) {
-  if (ctl != nullptr) {
-    if (ctl[0] < it) return;
-    if (rchk != nullptr && __longlong_as_double((long long)rchk[0]) < thr) {
-      if (threadIdx.x == 0 && ctl[0] > it) ctl[0] = it;
-    }
-  }
   typedef typename VecOf<T>::type V4;
   constexpr int NP = CPLX ? 2 : 1;
   __shared__ T smem_ab[2 * NP * TK * LDP];  // As, Bs; reused by the mirrored write
@@ -81,6 +77,13 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, XcdM
   const int jid = xm.map ? xm.map[blockIdx.x] : find_job(jobs, xm.off[x], xm.off[x + 1] - 1, tile);
   if (jid < 0) return;
   const Job J = jobs[jid];  // by value: the fields live in scalar registers
+  if (ctl != nullptr) {
+    const int g = J.gate;
+    if (ctl[g] < it) return;
+    if (rchk != nullptr && __longlong_as_double((long long)rchk[g]) < thr) {
+      if (threadIdx.x == 0 && ctl[g] > it) ctl[g] = it;
+    }
+  }
   const int mirror = J.mirror;
   const int ntile_job = mirror ? J.tiles_n * (J.tiles_n + 1) / 2 : J.tiles_n * ((J.M + 63) / 64);
   if (tile - J.tile_begin >= ntile_job) return;
@@ -272,7 +275,7 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, XcdM
       if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
       __syncthreads();
     }
-    if (threadIdx.x == 0) atomicMax(rmax, (unsigned long long)__double_as_longlong(red[0]));
+    if (threadIdx.x == 0) atomicMax(rmax + J.gate, (unsigned long long)__double_as_longlong(red[0]));
   }
 }
 

@@ -8,9 +8,10 @@
 // 1/sqrt(1 + ds^2 |dGamma|_1^2) (|.|_1 >= |.|_2 for a skew matrix), which puts
 // the spectrum in (0, 1], inside the convergence region (0, sqrt 3) of the
 // Newton-Schulz iteration X <- X (3 - X^T X) / 2 = X (3 + X^2) / 2 (two grouped
-// GEMMs; the polar factor is unchanged by the scaling).  After each square,
-// k_ns_check records the first iteration whose max |X^2 + 1| is below the
-// detection threshold; later GEMMs of the step exit at once (ctl[0]).
+// GEMMs; the polar factor is unchanged by the scaling).  Each state converges
+// on its own: the square's epilogue records max |X_mu^2 + 1| per state, and
+// the next product marks the first iteration below the detection threshold
+// as that state's last (ctl[mu]); later GEMM jobs of the state exit at once.
 #include "sgs_internal.h"
 
 namespace sgs {
@@ -46,7 +47,8 @@ __global__ __launch_bounds__(256) void k_dg_norm(const double* __restrict__ dG, 
 }
 
 // X = alpha_mu (Gamma + ds dGamma), alpha_mu = 1/sqrt(1 + (ds |dGamma_mu|_1)^2);
-// also resets the polar iteration's control word and residual slots.
+// also resets the polar iteration's control words (one per state) and
+// residual slots.
 __global__ __launch_bounds__(256) void k_euler(const double* __restrict__ gam, const double* __restrict__ dG,
                                                double dtau, int n, int R, double* __restrict__ X,
                                                const unsigned long long* __restrict__ nrm,
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(256) void k_euler(const double* __restrict__ gam, c
     X[e] = alpha * (gam[e] + dtau * dG[e]);
   }
   if (blockIdx.x == 0) {
-    if (threadIdx.x == 0) ctl[0] = 0x7fffffff;
+    for (int t = threadIdx.x; t < R; t += blockDim.x) ctl[t] = 0x7fffffff;
     for (int t = threadIdx.x; t < nresid; t += blockDim.x) resid[t] = 0ull;
   }
 }
@@ -70,8 +72,7 @@ __global__ void k_zero_u64(unsigned long long* p) { p[0] = 0ull; }
 
 // max over all states of |Q + 1| (Q = X X), as an ordered bit pattern
 __global__ void k_ns_resid(const double* __restrict__ Q, int n, long long total,
-                           unsigned long long* __restrict__ out, const int* __restrict__ ctl, int it) {
-  if (ctl != nullptr && ctl[0] < it) return;
+                           unsigned long long* __restrict__ out) {
   __shared__ double red[256];
   double mx = 0.0;
   const long long nn = (long long)n * n;
@@ -91,29 +92,26 @@ __global__ void k_ns_resid(const double* __restrict__ Q, int n, long long total,
   if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
 }
 
-__global__ void k_ns_flag(const unsigned long long* __restrict__ resid, int* __restrict__ ctl, int it,
-                          double thr) {
-  if (ctl[0] < it) return;
-  const double d = __longlong_as_double((long long)resid[0]);
-  if (d < thr) ctl[0] = it;  // this iteration's update is the last one
-}
-
-// Gamma <- (X - X^T) / 2 from the buffer holding the last iterate
+// Gamma_mu <- (X - X^T) / 2 from the buffer holding state mu's last iterate
 __global__ void k_finalize(const double* __restrict__ X0, const double* __restrict__ X1, int n, int R,
                            double* __restrict__ gam, const int* __restrict__ ctl, int maxit,
                            int* __restrict__ status) {
-  const int c = ctl[0];
-  const int last = (c == 0x7fffffff) ? maxit : c + 1;
-  const double* X = (last & 1) ? X1 : X0;
   const long long nn = (long long)n * n;
   const long long total = nn * R;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
     const long long mu = e / nn, r = e - mu * nn;
+    const int c = ctl[mu];
+    const int last = (c == 0x7fffffff) ? maxit : c + 1;
+    const double* X = (last & 1) ? X1 : X0;
     const int i = (int)(r / n), j = (int)(r - (long long)i * n);
     gam[e] = 0.5 * (X[e] - X[mu * nn + (long long)j * n + i]);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && c == 0x7fffffff) atomicCAS(status, ST_OK, ST_NOCONV);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    bool conv = true;
+    for (int mu = 0; mu < R; ++mu) conv = conv && ctl[mu] != 0x7fffffff;
+    if (!conv) atomicCAS(status, ST_OK, ST_NOCONV);
+  }
 }
 
 hipError_t launch_euler(const double* gam, const double* dG, double dtau, int n, int R, double* X, int* ctl,
@@ -126,16 +124,7 @@ hipError_t launch_euler(const double* gam, const double* dG, double dtau, int n,
 
 hipError_t launch_ns_resid(const double* Q, int n, long long total, unsigned long long* out, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, out);
-  hipLaunchKernelGGL(k_ns_resid, dim3(grid_for(total)), dim3(256), 0, s, Q, n, total, out, (const int*)nullptr, 0);
-  return hipGetLastError();
-}
-
-hipError_t launch_ns_check(const double* Q, int n, int R, unsigned long long* resid, int* ctl, int it,
-                           double thr, hipStream_t s) {
-  const long long total = (long long)n * n * R;
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, resid);
-  hipLaunchKernelGGL(k_ns_resid, dim3(grid_for(total)), dim3(256), 0, s, Q, n, total, resid, (const int*)ctl, it);
-  hipLaunchKernelGGL(k_ns_flag, dim3(1), dim3(1), 0, s, (const unsigned long long*)resid, ctl, it, thr);
+  hipLaunchKernelGGL(k_ns_resid, dim3(grid_for(total)), dim3(256), 0, s, Q, n, total, out);
   return hipGetLastError();
 }
 

@@ -29,6 +29,8 @@ struct GemmJob {
   const int* cperm;  // optional: C element (i, j) read at (cperm[i], cperm[j])
   int mirror;        // 0, or +1 / -1: D (square) is symmetric / skew; only
                      // tiles I <= J run and write the mirrored block too
+  int gate;          // iterative callers: index of this job's control word
+                     // and residual slots (the job's state)
 };
 
 // float32 twin used by the precision path (same layout, float operands).
@@ -46,6 +48,7 @@ struct GemmJobF {
   int tile_begin;
   const int* cperm;
   int mirror;
+  int gate;
 };
 
 constexpr int GEMM_TILE = 64;
@@ -208,8 +211,6 @@ hipError_t launch_euler(const double* gam, const double* dG, double dtau, int n,
                         int* ctl, unsigned long long* resid, int nresid, unsigned long long* nrm,
                         hipStream_t s);
 hipError_t launch_ns_resid(const double* Q, int n, long long total, unsigned long long* out, hipStream_t s);
-hipError_t launch_ns_check(const double* Q, int n, int R, unsigned long long* resid, int* ctl, int it,
-                           double thr, hipStream_t s);
 // Taylor coefficients of the even and odd parts of exp: c[j] = 1 / (2j)!,
 // s[j] = 1 / (2j + 1)!, j = 0..8.
 struct ExpCoef {
