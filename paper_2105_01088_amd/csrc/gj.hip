@@ -118,109 +118,126 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   int pe = 0;
   bool sing = false;
 
-  // The column loop stays rolled (its unrolled form is tens of KB of code,
-  // fetched once per panel: instruction-cache bound).  Instead the registers
-  // rotate by one column per step, so the current column is always x[r][0]
-  // and the next x[r][1]; posted rows carry the same rotation.
+  // The column loop stays rolled over groups of U columns (its unrolled form
+  // is tens of KB of code, fetched once per panel: instruction-cache bound).
+  // Inside a group the current column is x[r][u]; after the group the
+  // registers rotate by U columns, so the next group starts at x[r][0].
+  // Posted rows carry the same rotation.
+  constexpr int U = B < 4 ? B : 4;
 #pragma unroll 1
-  for (int j = 0; j < b; ++j) {
-    const int par = j & 1;
-    if (lane == 0) skey[par][w] = key;
-    int sel = -1;  // which owned row posts (selected by value, not by address)
+  for (int j0 = 0; j0 < b; j0 += U) {
 #pragma unroll
-    for (int r = 0; r < RPT; ++r)
-      if (key != 0ull && mine[r] == key) sel = r;
-    if (sel >= 0) {
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u;
+      if (j < b) {
+        const int par = j & 1;
+        if (lane == 0) skey[par][w] = key;
+        int sel = -1;  // which owned row posts (selected by value, not by address)
 #pragma unroll
-      for (int c = 0; c < B; ++c) {
-        double v = x[0][c];
+        for (int r = 0; r < RPT; ++r)
+          if (key != 0ull && mine[r] == key) sel = r;
+        if (sel >= 0) {
 #pragma unroll
-        for (int r = 1; r < RPT; ++r) v = (sel == r) ? x[r][c] : v;
-        srow[par][w][c] = v;
+          for (int c = 0; c < B; ++c) {
+            double v = x[0][c];
+#pragma unroll
+            for (int r = 1; r < RPT; ++r) v = (sel == r) ? x[r][c] : v;
+            srow[par][w][c] = v;
+          }
+        }
+        __syncthreads();
+        // best of the waves' posts: lane q < nw holds wave q's key
+        const unsigned long long best = max8_u64(lane < nw ? skey[par][lane] : 0ull);
+        int p = 0xffff - (int)(best & 0xffffull);
+        const bool bad = best == 0ull || p >= n;
+        if (bad) p = 0;  // cannot happen for b <= n - k; keeps every index in range
+        const int ww = (p % nt) >> 6;  // the wave holding row p posted it
+        // the pivot row, read by every lane from the same LDS address
+        // (broadcast); ps is 16-byte aligned, so these are 128-bit reads
+        const double* __restrict__ ps = srow[par][ww];
+        double prow[B];
+#pragma unroll
+        for (int c = 0; c < B; ++c) prow[c] = ps[c];
+        const double a = bad ? 0.0 : prow[u];
+        if (bad || !(fabs(a) > 0.0) || !isfinite(a)) sing = true;
+        {
+          int e;
+          pm *= frexp(fabs(a), &e);
+          pe += e;
+        }
+        // 1 / a: hardware reciprocal and two Newton steps
+        double ra = __builtin_amdgcn_rcp(a);
+        ra = fma(ra, fma(-a, ra, 1.0), ra);
+        ra = fma(ra, fma(-a, ra, 1.0), ra);
+        if (tid == 0) pivl[j] = p;
+        // the pivot row takes f = 0 in the common update and is then
+        // rewritten in place from its own registers
+        double f[RPT];
+        bool isp[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+          isp[r] = tid + r * nt == p;
+          f[r] = isp[r] ? 0.0 : x[r][u] * ra;
+          if (isp[r]) {
+            act[r] = false;
+            pos[r] = j;
+          }
+        }
+        const int un = (u + 1) % B;  // the next column
+        {
+          const double p1 = prow[un];
+#pragma unroll
+          for (int r = 0; r < RPT; ++r) x[r][un] -= f[r] * p1;
+        }
+        if (j + 1 < b) {
+          key = 0;
+#pragma unroll
+          for (int r = 0; r < RPT; ++r) {
+            mine[r] = act[r] ? pivot_key(x[r][un], tid + r * nt) : 0ull;
+            key = umax64(key, mine[r]);
+          }
+          key = wave_max_u64(key);
+        }
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+          if (c != u && c != un) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) x[r][c] -= f[r] * prow[c];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) x[r][u] = f[r];
+        // the pivot row's rewrite, behind a branch that is uniform per wave
+        // (only the wave holding row p takes it)
+        if (ww == w) {
+#pragma unroll
+          for (int r = 0; r < RPT; ++r) {
+            if (isp[r]) {
+#pragma unroll
+              for (int c = 0; c < B; ++c)
+                if (c != u) x[r][c] = -x[r][c] * ra;
+              x[r][u] = ra;
+            }
+          }
+        }
       }
     }
-    __syncthreads();
-    unsigned long long kq[GJ_MAX_WAVES];
-#pragma unroll
-    for (int q = 0; q < GJ_MAX_WAVES; ++q) kq[q] = q < nw ? skey[par][q] : 0ull;
-    unsigned long long best = kq[0];
-    int ww = 0;
-#pragma unroll
-    for (int q = 1; q < GJ_MAX_WAVES; ++q)
-      if (kq[q] > best) { best = kq[q]; ww = q; }
-    int p = 0xffff - (int)(best & 0xffffull);
-    const bool bad = best == 0ull || p >= n;
-    if (bad) p = 0;  // cannot happen for b <= n - k; keeps every index in range
-    // the pivot row: one element per lane, broadcast from lane c
-    const double* __restrict__ ps = srow[par][ww];
-    const double pvl = lane < B ? ps[lane] : 0.0;
-#define PROW(c) lane_bcast(pvl, (c))
-    const double a = bad ? 0.0 : PROW(0);
-    if (bad || !(fabs(a) > 0.0) || !isfinite(a)) sing = true;
-    {
-      int e;
-      pm *= frexp(fabs(a), &e);
-      pe += e;
-    }
-    // 1 / a: hardware reciprocal and two Newton steps
-    double ra = __builtin_amdgcn_rcp(a);
-    ra = fma(ra, fma(-a, ra, 1.0), ra);
-    ra = fma(ra, fma(-a, ra, 1.0), ra);
-    if (tid == 0) pivl[j] = p;
-    // Every broadcast (readlane of pvl) runs in uniform control flow, so every
-    // source lane has loaded its element.  The pivot row takes f = 0 in the
-    // common update and is then rewritten in place from its own registers.
-    double f[RPT];
-    bool isp[RPT];
+    // rotate by U: column j0 + U becomes x[r][0]
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-      isp[r] = tid + r * nt == p;
-      f[r] = isp[r] ? 0.0 : x[r][0] * ra;
-      if (isp[r]) {
-        act[r] = false;
-        pos[r] = j;
-      }
+      double t[U];
+#pragma unroll
+      for (int c = 0; c < U; ++c) t[c] = x[r][c];
+#pragma unroll
+      for (int c = 0; c + U < B; ++c) x[r][c] = x[r][c + U];
+#pragma unroll
+      for (int c = 0; c < U; ++c) x[r][B - U + c] = t[c];
     }
-    {
-      const double p1 = PROW(1);
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) x[r][1] -= f[r] * p1;
-    }
-    if (j + 1 < b) {
-      key = 0;
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        mine[r] = act[r] ? pivot_key(x[r][1], tid + r * nt) : 0ull;
-        key = umax64(key, mine[r]);
-      }
-      key = wave_max_u64(key);
-    }
-#pragma unroll
-    for (int c = 2; c < B; ++c) {
-      const double pc = PROW(c);
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) x[r][c] -= f[r] * pc;
-    }
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      if (isp[r]) {
-#pragma unroll
-        for (int c = 1; c < B; ++c) x[r][c] = -x[r][c] * ra;
-        x[r][0] = ra;
-      } else {
-        x[r][0] = f[r];
-      }
-      // rotate: column j + 1 becomes x[r][0]
-      const double t0 = x[r][0];
-#pragma unroll
-      for (int c = 0; c + 1 < B; ++c) x[r][c] = x[r][c + 1];
-      x[r][B - 1] = t0;
-    }
-#undef PROW
   }
-  // after b steps column c sits at (c - b) mod B: rotate the rest of the way
+  // after the groups column c sits at (c - U ceil(b / U)) mod B: rotate the
+  // rest of the way
 #pragma unroll 1
-  for (int j = b; j < B; ++j) {
+  for (int j = U * ((b + U - 1) / U); j < B; ++j) {
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const double t0 = x[r][0];

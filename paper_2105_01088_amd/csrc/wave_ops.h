@@ -43,6 +43,15 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
                 umax64(readlane_u64(v, 32), readlane_u64(v, 48)));
 }
 
+// Maximum over lanes 0..7 (every lane active), returned uniform: swap
+// neighbours, swap pairs, half-row mirror, then lane 0 read as a scalar.
+__device__ __forceinline__ unsigned long long max8_u64(unsigned long long v) {
+  v = umax64(v, dpp_u64<0xb1>(v));
+  v = umax64(v, dpp_u64<0x4e>(v));
+  v = umax64(v, dpp_u64<0x141>(v));
+  return readlane_u64(v, 0);
+}
+
 // Lane `src` (a constant) of v, as a wave-uniform value (scalar registers).
 // A uniform row is read from LDS one element per lane and broadcast this way:
 // one LDS access per wave instead of one per element, and the FMAs that use
