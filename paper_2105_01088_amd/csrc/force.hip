@@ -97,8 +97,10 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
 
   // A slab: rows row0..+63, k kc..kc+15  (thread: row tid>>2, 4 consecutive k)
   const int a_i = tid >> 2, a_k = (tid & 3) * 4;
-  // B slab: k kc..kc+15, cols col0..+63 (thread: k tid>>4, 4 consecutive cols)
-  const int b_k = tid >> 4, b_j = (tid & 15) * 4;
+  // B slab: k kc..kc+15, cols col0..+63 (thread: column tid & 63, k rows
+  // 4 (tid >> 6) + r: every wave reads and writes 64 consecutive columns, so
+  // the loads are row segments and the LDS stores hit distinct banks)
+  const int b_k = (tid >> 6) * 4, b_j = tid & 63;
 
   // one term's GEMM; IM: the term has imaginary planes (uniform per term, so
   // the matrix-core loop carries no branch)
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
         const long long o = (long long)gi * n + gk;
         ra[0][r] = ok ? Yr[o] : 0.0;
         ra[1][r] = (IM && ok) ? Yi[o] : 0.0;
-        const int gk2 = kc + b_k, gj = col0 + b_j + r;
+        const int gk2 = kc + b_k + r, gj = col0 + b_j;
         const bool okb = gk2 < n && gj < n;
         const long long ob = (long long)gk2 * n + gj;
         rd[0][r] = okb ? Dr[ob] : 0.0;
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           if (!IM && (u & 1)) continue;
-          TT* dst = u < 2 ? &As[u][a_k + r][a_i] : &Bs[u - 2][b_k][b_j + r];
+          TT* dst = u < 2 ? &As[u][a_k + r][a_i] : &Bs[u - 2][b_k + r][b_j];
           *dst = (TT)v[u];
         }
       }

@@ -145,25 +145,27 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, XcdM
 
   T ra[NP][4], rb[NP][4];
 
-  // index pattern of this thread's 4 A and 4 B elements inside a slab
-  const int a_i = ta ? (tid & 15) * 4 : (tid >> 2);
-  const int a_k = ta ? (tid >> 4) : (tid & 3) * 4;
-  const int b_k = tb ? (tid & 3) * 4 : (tid >> 4);
-  const int b_j = tb ? (tid >> 2) : (tid & 15) * 4;
+  // index pattern of this thread's 4 A and 4 B elements inside a slab: a
+  // thread holds one row (A) or column (B) of the tile at 4 consecutive k.
+  // Row-major operands put 4 threads on one row (A: 128-byte row segments);
+  // the others put a wave on 64 consecutive rows / columns of one k, so the
+  // loads are row segments and the LDS stores below hit distinct banks.
+  const int a_i = ta ? (tid & 63) : (tid >> 2);
+  const int a_k = ta ? (tid >> 6) * 4 : (tid & 3) * 4;
+  const int b_k = tb ? (tid & 3) * 4 : (tid >> 6) * 4;
+  const int b_j = tb ? (tid >> 2) : (tid & 63);
 
   auto load = [&](int kc) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int gi = row0 + a_i + (ta ? r : 0);
-      int gk = kc + a_k + (ta ? 0 : r);
-      bool ok = gi < M && gk < K;
-      long long off = ta ? (long long)gk * lda + gi : (long long)gi * lda + gk;
+      const int gi = row0 + a_i, gk = kc + a_k + r;
+      const bool ok = gi < M && gk < K;
+      const long long off = ta ? (long long)gk * lda + gi : (long long)gi * lda + gk;
 #pragma unroll
       for (int p = 0; p < NP; ++p) ra[p][r] = ok ? A[off + p * aim] : T(0);
-      int gj = col0 + b_j + (tb ? 0 : r);
-      int gk2 = kc + b_k + (tb ? r : 0);
-      bool okb = gj < N && gk2 < K;
-      long long offb = tb ? (long long)gj * ldb + gk2 : (long long)gk2 * ldb + gj;
+      const int gj = col0 + b_j, gk2 = kc + b_k + r;
+      const bool okb = gj < N && gk2 < K;
+      const long long offb = tb ? (long long)gj * ldb + gk2 : (long long)gk2 * ldb + gj;
 #pragma unroll
       for (int p = 0; p < NP; ++p) rb[p][r] = okb ? B[offb + p * bim] : T(0);
     }
@@ -173,8 +175,8 @@ __global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, XcdM
     for (int r = 0; r < 4; ++r) {
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
-        if (ta) As[p][a_k][a_i + r] = ra[p][r]; else As[p][a_k + r][a_i] = ra[p][r];
-        if (tb) Bs[p][b_k + r][b_j] = rb[p][r]; else Bs[p][b_k][b_j + r] = rb[p][r];
+        As[p][a_k + r][a_i] = ra[p][r];
+        Bs[p][b_k + r][b_j] = rb[p][r];
       }
     }
   };
