@@ -740,7 +740,6 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
     // overlap magnitudes and W = (Gamma_a + Gamma_b)^{-1}; the elimination
     // runs in the Di buffer (overwritten by the transition matrices next)
     tm.begin(SGS_STAGE_INVERSE, s);
-    HCHK(launch_pair_sum(q.gam, n, q.pa, q.pb, P, q.Di, q.logdet, s));
     // one batch of inverses: panels, grouped updates, unscramble
     auto inverses = [&](int half, hipStream_t st) -> hipError_t {
       const int off = half == 0 ? 0 : P0, cnt = half == 0 ? P0 : P - P0;
@@ -761,10 +760,14 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
     if (rest) {
       HCHK(hipEventRecord(wk.ev_gj, s));
       HCHK(hipStreamWaitEvent(wk.s3, wk.ev_gj, 0));
+      HCHK(launch_pair_sum(q.gam, n, q.pa + P0, q.pb + P0, P - P0, q.Di + P0 * nn, q.logdet + P0, wk.s3));
       HCHK(inverses(1, wk.s3));
       HCHK(hipEventRecord(wk.ev_gj_done, wk.s3));
     }
-    if (P0 > 0) HCHK(inverses(0, s));
+    if (P0 > 0) {
+      HCHK(launch_pair_sum(q.gam, n, q.pa, q.pb, P0, q.Di, q.logdet, s));
+      HCHK(inverses(0, s));
+    }
     if (fork) {
       // phases on the second stream, concurrent with the other inverses
       HCHK(hipEventRecord(wk.ev_fork, s));
