@@ -48,7 +48,7 @@ struct Prob {
   double e0 = 0.0;
   double* gam = nullptr;
   // dense work
-  double *W, *Di, *Y, *Yd, *T1, *Xr, *Cm, *Cm2, *UV, *RM, *gjE, *gjB, *dG, *nsX0, *nsX1, *nsQ, *Adense;
+  double *W, *Di, *Y, *Yd, *T1, *Xr, *Cm, *Cm2, *UV, *RM, *gjE, *gjB, *dG, *dE, *nsX0, *nsX1, *nsQ, *Adense;
   // small
   double *pfacc, *logdet, *eps, *Fc, *coef, *Gt, *ht, *lam, *lamt, *E, *tab_la, *tab_arg, *tab_eps;
   double *up_v, *colval, *q_val;
@@ -191,6 +191,7 @@ struct Worker {
   hipStream_t s2 = nullptr;  // phase chain
   hipStream_t s3 = nullptr;  // inverses of the pairs not involving state 0
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_done = nullptr, ev_gj = nullptr, ev_gj_done = nullptr;
+  hipEvent_t ev_f = nullptr, ev_fe = nullptr;  // elementwise force terms on s2
   int owner = -1;  // problem whose scratch tables are current
 };
 
@@ -213,6 +214,8 @@ struct sgs_ctx {
       if (w.ev_done) (void)hipEventDestroy(w.ev_done);
       if (w.ev_gj) (void)hipEventDestroy(w.ev_gj);
       if (w.ev_gj_done) (void)hipEventDestroy(w.ev_gj_done);
+      if (w.ev_f) (void)hipEventDestroy(w.ev_f);
+      if (w.ev_fe) (void)hipEventDestroy(w.ev_fe);
       if (w.s2) (void)hipStreamDestroy(w.s2);
       if (w.s3) (void)hipStreamDestroy(w.s3);
       if (w.own_s && w.s) (void)hipStreamDestroy(w.s);
@@ -293,6 +296,7 @@ static void carve_scratch(Prob& q, Arena& ar) {
   q.gjE = ar.take<double>(std::max(1LL, (long long)P * n * GJ_NB_MAX));
   q.gjB = ar.take<double>(std::max(1LL, (long long)P * n * GJ_NB_MAX));
   q.dG = ar.take<double>(R * nn);
+  q.dE = ar.take<double>(R * nn);  // elementwise force terms, added into dG
   q.nsX0 = ar.take<double>(R * nn);
   q.nsX1 = ar.take<double>(R * nn);
   q.nsQ = ar.take<double>(R * nn);
@@ -821,14 +825,23 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
 }
 
 static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
-  hipStream_t s = c->wk[q.worker].s;
+  Worker& wk = c->wk[q.worker];
+  hipStream_t s = wk.s;
   const int n = q.n, R = q.R;
   const long long nn = (long long)n * n;
   StageTimer& tm = q.worker == 0 ? c->timer : c->mute;
   tm.begin(SGS_STAGE_FORCE, s);
   const int fmode = c->opt.precision == SGS_FP64 ? FORCE_FP64 : FORCE_FP32;
-  HCHK(launch_force(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, q.dG, q.dgnorm, fmode, s));
+  // the elementwise terms on the second stream (idle here: the phase chain
+  // joined before the solve), concurrent with the dense products
+  HCHK(hipEventRecord(wk.ev_f, s));
+  HCHK(hipStreamWaitEvent(wk.s2, wk.ev_f, 0));
+  HCHK(launch_force_elem(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, q.dE, wk.s2));
+  HCHK(hipEventRecord(wk.ev_fe, wk.s2));
+  HCHK(launch_force(n, R, q.terms, q.coef, q.dG, q.dgnorm, fmode, s));
   tm.end(SGS_STAGE_FORCE, s);
+  HCHK(hipStreamWaitEvent(s, wk.ev_fe, 0));
+  HCHK(launch_force_join(q.dG, q.dE, n, R, q.dgnorm, s));
   (void)nn;
   tm.begin(SGS_STAGE_PURIFY, s);
   if (q.expmap) {
@@ -963,6 +976,8 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
         hipStreamCreateWithFlags(&k.s3, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&k.ev_gj, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&k.ev_gj_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&k.ev_f, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&k.ev_fe, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&k.ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&k.ev_join, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&k.ev_done, hipEventDisableTiming) != hipSuccess) { delete c; return SGS_EHIP; }

@@ -6,10 +6,14 @@
 // and c2 = -2 w_mu lambda_b (h_mb - E G_mb) (tables from the amplitude solve):
 //   dGamma_mu = sum_b Re{c1 (F + i (Y - Y^T) + Y D) + c2 D}.
 // The dense part Re(c1 Y D) = Y_r Re(c1 D) - Y_i Im(c1 D) is one real GEMM of
-// depth 2n per term; the workgroup for an output tile streams every term b
-// through the matrix cores, forming the B operand Re(c1 D) / -Im(c1 D) on the
-// fly from W (D_r = -2 W) and D_i, then adds the remaining terms and writes
-// the tile and its skew mirror (the force is skew: only tiles I <= J run).
+// depth 2n per term; in k_force the workgroup for an output tile streams
+// every term b through the matrix cores, forming the B operand Re(c1 D) /
+// -Im(c1 D) on the fly from W (D_r = -2 W) and D_i, and writes the tile and
+// its skew mirror (the force is skew: only tiles I <= J run).  The remaining
+// terms, Re{c1 (F + i (Y - Y^T)) + c2 D}, are elementwise and memory-bound:
+// k_force_elem sums them into a second buffer on another stream while the
+// matrix cores run (few registers, many waves to hide the loads), and
+// k_force_join adds the two and takes the 1-norm the Euler step needs.
 // The pair (a < b) stores Delta^{ba}; the term for mu = b uses its complex
 // conjugate (sgn = -1 on every imaginary part).
 //
@@ -59,8 +63,6 @@ constexpr size_t force_lds_bytes(size_t elem) {
 template <typename TT>
 __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceTerm* __restrict__ terms,
                                                const double* __restrict__ coef,
-                                               const double* __restrict__ Adense,
-                                               const int* __restrict__ impos, int M,
                                                double* __restrict__ dG,
                                                unsigned long long* __restrict__ nrm) {
   typedef typename Vec4<TT>::type V4;
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
   const int mu = xcd + 8 * (loc / ntri);
   if (mu >= R) return;
   // upper-triangular tile index -> (I, J), I <= J
-  if (loc % ntri == 0 && threadIdx.x == 0) nrm[mu] = 0ull;  // read by the Euler step after this kernel
+  if (loc % ntri == 0 && threadIdx.x == 0) nrm[mu] = 0ull;  // k_force_join accumulates it after this kernel
   int tri = loc % ntri, I = 0;
   while (tri >= T - I) { tri -= T - I; ++I; }
   const int J = I + tri;
@@ -178,61 +180,6 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
     else run_term(tm, x1, y1, std::false_type{});
   }
 
-  // ---- remaining terms, per output element (i, j) of this lane ----
-  double lin[2][2][4];
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) lin[bi][bj][r] = 0.0;
-  double sx1 = 0.0;
-  for (int b = 0; b < R; ++b) {
-    const ForceTerm tm = terms[mu * R + b];
-    const double x1 = c1t[2 * tm.coef], y1 = c1t[2 * tm.coef + 1];
-    const double x2 = c2t[2 * tm.coef], y2 = c2t[2 * tm.coef + 1];
-    const bool has_im = tm.Yi != nullptr;
-    const double im = has_im ? 1.0 : 0.0;  // terms without imaginary planes read Yr / Dr in their place
-    const double sg = tm.sgn, ds = tm.dr_scale;
-    const SGS_GLOBAL double* __restrict__ Yr = as_global(tm.Yr);
-    const SGS_GLOBAL double* __restrict__ Yi = as_global(has_im ? tm.Yi : tm.Yr);
-    const SGS_GLOBAL double* __restrict__ Dr = as_global(tm.Dr);
-    const SGS_GLOBAL double* __restrict__ Di = as_global(has_im ? tm.Di : tm.Dr);
-    sx1 += x1;
-    // transposed block: Tt[c][r] = (x1 sg Yi + y1 Yr)(col0 + r, row0 + c)
-    __syncthreads();
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int r = e >> 6, c = e & 63;
-      const int gr = col0 + r, gc = row0 + c;
-      const bool ok = gr < n && gc < n;
-      const long long o = ok ? (long long)gr * n + gc : 0;
-      const double v = y1 * Yr[o] + im * x1 * sg * Yi[o];
-      Tt[c][r] = ok ? v : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int li = wm * 32 + bi * 16 + acc_row<TT>(lane, r);
-          const int lj = wn * 32 + bj * 16 + (lane & 15);
-          const int gi = row0 + li, gj = col0 + lj;
-          const bool ok = gi < n && gj < n;
-          const long long o = ok ? (long long)gi * n + gj : 0;
-          double v = Tt[li][lj] - y1 * Yr[o] + x2 * ds * Dr[o] + im * (-x1 * sg * Yi[o] - y2 * sg * Di[o]);
-          if (M > 0 && ok) {
-            const int pi = impos[gi], pj = impos[gj];
-            if (pi >= 0 && pj >= 0) {
-              v += x1 * as_global(tm.Fcr)[pi * M + pj];
-              if (tm.Fci) v -= y1 * sg * as_global(tm.Fci)[pi * M + pj];
-            }
-          }
-          if (ok) lin[bi][bj][r] += v;
-        }
-  }
-
   // ---- total, skew write-out ----
   __syncthreads();
   double* out = dG + (long long)mu * nn;
@@ -246,7 +193,7 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
         const int lj = wn * 32 + bj * 16 + (lane & 15);
         const int gi = row0 + li, gj = col0 + lj;
         double v = 0.0;
-        if (gi < n && gj < n) v = (double)acc[bi][bj][r] + lin[bi][bj][r] + sx1 * Adense[(long long)gi * n + gj];
+        if (gi < n && gj < n) v = (double)acc[bi][bj][r];
         if (I == J) Tt[li][lj] = v;
         else if (gi < n && gj < n) {
           out[(long long)gi * n + gj] = v;
@@ -263,16 +210,149 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
   }
 }
 
-hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
-                        const int* impos, int M, double* dG, unsigned long long* nrm, int mode, hipStream_t s) {
+// Elementwise terms of state mu, tile (I, J), I <= J:
+//   sum_b Re{c1 (F + i (Y - Y^T)) + c2 D} = sum_b [x1 (F_r + Y^T-part) ...]
+// written out: (y1 Yr + x1 sg Yi)(j, i) - y1 Yr(i, j) - x1 sg Yi(i, j)
+// + x2 ds Dr(i, j) - y2 sg Di(i, j), plus x1 F_r - y1 sg F_i on the impurity
+// block, plus (sum_b x1) A (F = A + the impurity correction).  The (j, i)
+// block comes in through LDS, transposed, so every load is row-contiguous.
+// grid: (ntri, R), 256 threads; thread: column tid & 63, rows tid >> 6 + 4 k.
+__global__ __launch_bounds__(256) void k_force_elem(int n, int R, int T, const ForceTerm* __restrict__ terms,
+                                                    const double* __restrict__ coef,
+                                                    const double* __restrict__ Adense,
+                                                    const int* __restrict__ impos, int M,
+                                                    double* __restrict__ dE) {
+  __shared__ double Tt[64][64 + 1];
+  const int mu = blockIdx.y;
+  int tri = blockIdx.x, I = 0;
+  while (tri >= T - I) { tri -= T - I; ++I; }
+  const int J = I + tri;
+  const int row0 = I * 64, col0 = J * 64;
+  const long long nn = (long long)n * n;
+  const int tid = threadIdx.x, lj = tid & 63, lr = tid >> 6;
+  const int gj = col0 + lj;
+  const double* c1t = coef;
+  const double* c2t = coef + 2 * R * R;
+  double lin[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) lin[k] = 0.0;
+  double sx1 = 0.0;
+  for (int b = 0; b < R; ++b) {
+    const ForceTerm tm = terms[mu * R + b];
+    const double x1 = c1t[2 * tm.coef], y1 = c1t[2 * tm.coef + 1];
+    const double x2 = c2t[2 * tm.coef], y2 = c2t[2 * tm.coef + 1];
+    const bool has_im = tm.Yi != nullptr;
+    const double im = has_im ? 1.0 : 0.0;  // terms without imaginary planes read Yr / Dr in their place
+    const double sg = tm.sgn, ds = tm.dr_scale;
+    const SGS_GLOBAL double* __restrict__ Yr = as_global(tm.Yr);
+    const SGS_GLOBAL double* __restrict__ Yi = as_global(has_im ? tm.Yi : tm.Yr);
+    const SGS_GLOBAL double* __restrict__ Dr = as_global(tm.Dr);
+    const SGS_GLOBAL double* __restrict__ Di = as_global(has_im ? tm.Di : tm.Dr);
+    sx1 += x1;
+    // Tt[c][r] = (y1 Yr + x1 sg Yi)(col0 + r, row0 + c)
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int r = lr + 4 * k, c = lj;
+      const int gr = col0 + r, gc = row0 + c;
+      const bool ok = gr < n && gc < n;
+      const long long o = ok ? (long long)gr * n + gc : 0;
+      const double v = y1 * Yr[o] + im * x1 * sg * Yi[o];
+      Tt[c][r] = ok ? v : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int li = lr + 4 * k, gi = row0 + li;
+      const bool ok = gi < n && gj < n;
+      const long long o = ok ? (long long)gi * n + gj : 0;
+      double v = Tt[li][lj] - y1 * Yr[o] + x2 * ds * Dr[o] + im * (-x1 * sg * Yi[o] - y2 * sg * Di[o]);
+      if (M > 0 && ok) {
+        const int pi = impos[gi], pj = impos[gj];
+        if (pi >= 0 && pj >= 0) {
+          v += x1 * as_global(tm.Fcr)[pi * M + pj];
+          if (tm.Fci) v -= y1 * sg * as_global(tm.Fci)[pi * M + pj];
+        }
+      }
+      if (ok) lin[k] += v;
+    }
+  }
+  // total, skew write-out (the diagonal tile antisymmetrized through LDS)
+  __syncthreads();
+  double* out = dE + (long long)mu * nn;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int li = lr + 4 * k, gi = row0 + li;
+    double v = 0.0;
+    if (gi < n && gj < n) v = lin[k] + sx1 * Adense[(long long)gi * n + gj];
+    if (I == J) Tt[li][lj] = v;
+    else if (gi < n && gj < n) {
+      out[(long long)gi * n + gj] = v;
+      out[(long long)gj * n + gi] = -v;
+    }
+  }
+  if (I == J) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int li = lr + 4 * k, gi = row0 + li;
+      if (gi < n && gj < n) out[(long long)gi * n + gj] = 0.5 * (Tt[li][lj] - Tt[lj][li]);
+    }
+  }
+}
+
+// dG <- dG + dE, and the largest row sum of |dG_mu| (= 1-norm: skew) into
+// nrm[mu] as an ordered bit pattern (k_force cleared it).  grid:
+// (ceil(n / 16), R); one wave per row.
+__global__ __launch_bounds__(256) void k_force_join(double* __restrict__ dG, const double* __restrict__ dE, int n,
+                                                    unsigned long long* __restrict__ nrm) {
+  __shared__ double red[4];
+  const int mu = blockIdx.y;
+  const long long nn = (long long)n * n;
+  double* d = dG + mu * nn;
+  const double* de = dE + mu * nn;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double mx = 0.0;
+  for (int i = blockIdx.x * 16 + wv; i < min(n, (int)blockIdx.x * 16 + 16); i += 4) {
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) {
+      const long long o = (long long)i * n + j;
+      const double v = d[o] + de[o];
+      d[o] = v;
+      s += fabs(v);
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    mx = fmax(mx, s);
+  }
+  if (lane == 0) red[wv] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(nrm + mu, (unsigned long long)__double_as_longlong(fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))));
+}
+
+hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, double* dG,
+                        unsigned long long* nrm, int mode, hipStream_t s) {
   const int T = (n + 63) / 64;
   const int ntri = T * (T + 1) / 2;
   const int per_xcd = (R + 7) / 8;
   const dim3 grid(8 * per_xcd * ntri), block(256);
   if (mode == FORCE_FP64)
-    hipLaunchKernelGGL((k_force<double>), grid, block, 0, s, n, R, T, terms, coef, A, impos, M, dG, nrm);
+    hipLaunchKernelGGL((k_force<double>), grid, block, 0, s, n, R, T, terms, coef, dG, nrm);
   else
-    hipLaunchKernelGGL((k_force<float>), grid, block, 0, s, n, R, T, terms, coef, A, impos, M, dG, nrm);
+    hipLaunchKernelGGL((k_force<float>), grid, block, 0, s, n, R, T, terms, coef, dG, nrm);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_elem(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
+                             const int* impos, int M, double* dE, hipStream_t s) {
+  const int T = (n + 63) / 64;
+  hipLaunchKernelGGL(k_force_elem, dim3(T * (T + 1) / 2, R), dim3(256), 0, s, n, R, T, terms, coef, A, impos, M,
+                     dE);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_join(double* dG, const double* dE, int n, int R, unsigned long long* nrm, hipStream_t s) {
+  hipLaunchKernelGGL(k_force_join, dim3((n + 15) / 16, R), dim3(256), 0, s, dG, dE, n, nrm);
   return hipGetLastError();
 }
 

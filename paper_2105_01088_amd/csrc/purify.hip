@@ -23,29 +23,6 @@ static int grid_for(long long total) {
   return (int)b;
 }
 
-// max row sum of |dGamma_mu| (= max column sum: skew) into nrm[mu] as an
-// ordered bit pattern.  grid: (ceil(n / 16), R); one wave per row.  The force
-// kernel clears nrm[] before it writes dGamma.
-__global__ __launch_bounds__(256) void k_dg_norm(const double* __restrict__ dG, int n,
-                                                 unsigned long long* __restrict__ nrm) {
-  __shared__ double red[4];
-  const int mu = blockIdx.y;
-  const long long nn = (long long)n * n;
-  const double* d = dG + mu * nn;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  double mx = 0.0;
-  for (int i = blockIdx.x * 16 + wv; i < min(n, (int)blockIdx.x * 16 + 16); i += 4) {
-    double s = 0.0;
-    for (int j = lane; j < n; j += 64) s += fabs(d[(long long)i * n + j]);
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    mx = fmax(mx, s);
-  }
-  if (lane == 0) red[wv] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    atomicMax(nrm + mu, (unsigned long long)__double_as_longlong(fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))));
-}
-
 // X = alpha_mu (Gamma + ds dGamma), alpha_mu = 1/sqrt(1 + (ds |dGamma_mu|_1)^2);
 // also resets the polar iteration's control words (one per state) and
 // residual slots.
@@ -116,7 +93,6 @@ __global__ void k_finalize(const double* __restrict__ X0, const double* __restri
 
 hipError_t launch_euler(const double* gam, const double* dG, double dtau, int n, int R, double* X, int* ctl,
                         unsigned long long* resid, int nresid, unsigned long long* nrm, hipStream_t s) {
-  hipLaunchKernelGGL(k_dg_norm, dim3((n + 15) / 16, R), dim3(256), 0, s, dG, n, nrm);
   hipLaunchKernelGGL(k_euler, dim3(grid_for((long long)n * n * R)), dim3(256), 0, s, gam, dG, dtau, n, R, X,
                      (const unsigned long long*)nrm, ctl, resid, nresid);
   return hipGetLastError();
