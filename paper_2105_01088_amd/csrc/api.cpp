@@ -48,7 +48,7 @@ struct Prob {
   double e0 = 0.0;
   double* gam = nullptr;
   // dense work
-  double *W, *Di, *Y, *Yd, *T1, *Xr, *Cm, *Cm2, *UV, *RM, *gjE, *gjB, *dG, *dE, *nsX0, *nsX1, *nsQ, *Adense;
+  double *W, *Di, *Y, *Yd, *T1, *Xr, *Cm, *Cm2, *UV, *RM, *gjE, *gjB, *dG, *dP, *dE, *nsX0, *nsX1, *nsQ, *Adense;
   // small
   double *pfacc, *logdet, *eps, *Fc, *coef, *Gt, *ht, *lam, *lamt, *E, *tab_la, *tab_arg, *tab_eps;
   double *up_v, *colval, *q_val;
@@ -296,6 +296,7 @@ static void carve_scratch(Prob& q, Arena& ar) {
   q.gjE = ar.take<double>(std::max(1LL, (long long)P * n * GJ_NB_MAX));
   q.gjB = ar.take<double>(std::max(1LL, (long long)P * n * GJ_NB_MAX));
   q.dG = ar.take<double>(R * nn);
+  q.dP = ar.take<double>(R * nn);  // second half of the force products, added into dG
   q.dE = ar.take<double>(R * nn);  // elementwise force terms, added into dG
   q.nsX0 = ar.take<double>(R * nn);
   q.nsX1 = ar.take<double>(R * nn);
@@ -838,10 +839,10 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
   HCHK(hipStreamWaitEvent(wk.s2, wk.ev_f, 0));
   HCHK(launch_force_elem(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, q.dE, wk.s2));
   HCHK(hipEventRecord(wk.ev_fe, wk.s2));
-  HCHK(launch_force(n, R, q.terms, q.coef, q.dG, q.dgnorm, fmode, s));
+  HCHK(launch_force(n, R, q.terms, q.coef, q.dG, q.dP, q.dgnorm, fmode, s));
   tm.end(SGS_STAGE_FORCE, s);
   HCHK(hipStreamWaitEvent(s, wk.ev_fe, 0));
-  HCHK(launch_force_join(q.dG, q.dE, n, R, q.dgnorm, s));
+  HCHK(launch_force_join(q.dG, q.dP, q.dE, n, R, q.dgnorm, s));
   (void)nn;
   tm.begin(SGS_STAGE_PURIFY, s);
   if (q.expmap) {

@@ -48,6 +48,7 @@ template <> struct Vec4<double> { typedef dvec4 type; };
 template <> struct Vec4<float> { typedef fvec4 type; };
 
 constexpr int FTK = 16;
+constexpr int FORCE_SPLIT = 2;  // workgroups per output tile (term ranges)
 constexpr int FLP = 64 + 1;
 
 constexpr size_t force_lds_bytes(size_t elem) {
@@ -63,7 +64,7 @@ constexpr size_t force_lds_bytes(size_t elem) {
 template <typename TT>
 __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceTerm* __restrict__ terms,
                                                const double* __restrict__ coef,
-                                               double* __restrict__ dG,
+                                               double* __restrict__ dG, double* __restrict__ dP,
                                                unsigned long long* __restrict__ nrm) {
   typedef typename Vec4<TT>::type V4;
   // K-loop staging As[re/im], Bs[re/im] and the epilogue's transposed block
@@ -75,11 +76,15 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
   double (*Tt)[FLP] = (double (*)[FLP])lds_raw;  // 64 x FLP
 
   const int ntri = T * (T + 1) / 2;
-  const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
+  const int xcd = blockIdx.x & 7, loc2 = blockIdx.x >> 3;
+  // each tile's terms are split over FORCE_SPLIT workgroups (the same XCD);
+  // split h sums terms [h R / S, (h + 1) R / S) into dG (h = 0) or dP
+  const int split = loc2 % FORCE_SPLIT, loc = loc2 / FORCE_SPLIT;
   const int mu = xcd + 8 * (loc / ntri);
   if (mu >= R) return;
+  const int b_lo = split * R / FORCE_SPLIT, b_hi = (split + 1) * R / FORCE_SPLIT;
   // upper-triangular tile index -> (I, J), I <= J
-  if (loc % ntri == 0 && threadIdx.x == 0) nrm[mu] = 0ull;  // k_force_join accumulates it after this kernel
+  if (loc % ntri == 0 && split == 0 && threadIdx.x == 0) nrm[mu] = 0ull;  // k_force_join accumulates it
   int tri = loc % ntri, I = 0;
   while (tri >= T - I) { tri -= T - I; ++I; }
   const int J = I + tri;
@@ -173,7 +178,7 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
       }
     }
   };
-  for (int b = 0; b < R; ++b) {
+  for (int b = b_lo; b < b_hi; ++b) {
     const ForceTerm tm = terms[mu * R + b];
     const double x1 = c1t[2 * tm.coef], y1 = c1t[2 * tm.coef + 1];
     if (tm.Yi != nullptr) run_term(tm, x1, y1, std::true_type{});
@@ -182,7 +187,7 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
 
   // ---- total, skew write-out ----
   __syncthreads();
-  double* out = dG + (long long)mu * nn;
+  double* out = (split == 0 ? dG : dP) + (long long)mu * nn;
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -301,23 +306,26 @@ __global__ __launch_bounds__(256) void k_force_elem(int n, int R, int T, const F
   }
 }
 
-// dG <- dG + dE, and the largest row sum of |dG_mu| (= 1-norm: skew) into
+// dG <- dG + dP + dE (the two product halves and the elementwise terms), and
+// the largest row sum of |dG_mu| (= 1-norm: skew) into
 // nrm[mu] as an ordered bit pattern (k_force cleared it).  grid:
 // (ceil(n / 16), R); one wave per row.
-__global__ __launch_bounds__(256) void k_force_join(double* __restrict__ dG, const double* __restrict__ dE, int n,
+__global__ __launch_bounds__(256) void k_force_join(double* __restrict__ dG, const double* __restrict__ dP,
+                                                    const double* __restrict__ dE, int n,
                                                     unsigned long long* __restrict__ nrm) {
   __shared__ double red[4];
   const int mu = blockIdx.y;
   const long long nn = (long long)n * n;
   double* d = dG + mu * nn;
   const double* de = dE + mu * nn;
+  const double* dp = dP + mu * nn;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double mx = 0.0;
   for (int i = blockIdx.x * 16 + wv; i < min(n, (int)blockIdx.x * 16 + 16); i += 4) {
     double s = 0.0;
     for (int j = lane; j < n; j += 64) {
       const long long o = (long long)i * n + j;
-      const double v = d[o] + de[o];
+      const double v = d[o] + dp[o] + de[o];
       d[o] = v;
       s += fabs(v);
     }
@@ -330,16 +338,16 @@ __global__ __launch_bounds__(256) void k_force_join(double* __restrict__ dG, con
     atomicMax(nrm + mu, (unsigned long long)__double_as_longlong(fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))));
 }
 
-hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, double* dG,
+hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, double* dG, double* dP,
                         unsigned long long* nrm, int mode, hipStream_t s) {
   const int T = (n + 63) / 64;
   const int ntri = T * (T + 1) / 2;
   const int per_xcd = (R + 7) / 8;
-  const dim3 grid(8 * per_xcd * ntri), block(256);
+  const dim3 grid(8 * per_xcd * ntri * FORCE_SPLIT), block(256);
   if (mode == FORCE_FP64)
-    hipLaunchKernelGGL((k_force<double>), grid, block, 0, s, n, R, T, terms, coef, dG, nrm);
+    hipLaunchKernelGGL((k_force<double>), grid, block, 0, s, n, R, T, terms, coef, dG, dP, nrm);
   else
-    hipLaunchKernelGGL((k_force<float>), grid, block, 0, s, n, R, T, terms, coef, dG, nrm);
+    hipLaunchKernelGGL((k_force<float>), grid, block, 0, s, n, R, T, terms, coef, dG, dP, nrm);
   return hipGetLastError();
 }
 
@@ -351,8 +359,9 @@ hipError_t launch_force_elem(int n, int R, const ForceTerm* terms, const double*
   return hipGetLastError();
 }
 
-hipError_t launch_force_join(double* dG, const double* dE, int n, int R, unsigned long long* nrm, hipStream_t s) {
-  hipLaunchKernelGGL(k_force_join, dim3((n + 15) / 16, R), dim3(256), 0, s, dG, dE, n, nrm);
+hipError_t launch_force_join(double* dG, const double* dP, const double* dE, int n, int R, unsigned long long* nrm,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_force_join, dim3((n + 15) / 16, R), dim3(256), 0, s, dG, dP, dE, n, nrm);
   return hipGetLastError();
 }
 

@@ -205,13 +205,15 @@ hipError_t set_renyi2_lds_limit();
 hipError_t launch_renyi2(const ObsState& s, int nA, double* part, double* out, hipStream_t st);
 
 enum : int { FORCE_FP64 = 0, FORCE_FP32 = 1 };
-// k_force: the dense products into dG (clears nrm); k_force_elem: the
-// elementwise terms into dE; k_force_join: dG += dE and the 1-norms
-hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, double* dG,
+// k_force: the dense products, two term ranges into dG and dP (clears nrm);
+// k_force_elem: the elementwise terms into dE; k_force_join: dG += dP + dE
+// and the 1-norms
+hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, double* dG, double* dP,
                         unsigned long long* nrm, int mode, hipStream_t s);
 hipError_t launch_force_elem(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
                              const int* impos, int M, double* dE, hipStream_t s);
-hipError_t launch_force_join(double* dG, const double* dE, int n, int R, unsigned long long* nrm, hipStream_t s);
+hipError_t launch_force_join(double* dG, const double* dP, const double* dE, int n, int R, unsigned long long* nrm,
+                             hipStream_t s);
 hipError_t launch_euler(const double* gam, const double* dG, double dtau, int n, int R, double* X,
                         int* ctl, unsigned long long* resid, int nresid, unsigned long long* nrm,
                         hipStream_t s);
