@@ -59,7 +59,7 @@ constexpr int LDP = 64 + 1;  // LDS row pitch (elements), padded
 // receives max |D + 1| over each job's outputs (D square) in rmax[gate], as
 // an ordered bit pattern.
 template <typename T, typename Job, bool CPLX>
-__global__ __launch_bounds__(256) void k_gemm(const Job* __restrict__ jobs, XcdMap xm,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm(const Job* __restrict__ jobs, XcdMap xm,
                                               int* __restrict__ ctl, int it,
                                               const unsigned long long* __restrict__ rchk, double thr,
                                               unsigned long long* __restrict__ rmax) {
