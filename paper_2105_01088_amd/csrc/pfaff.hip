@@ -97,21 +97,32 @@ void k_pf_panel(const double* __restrict__ Aall, long long astride, long long pl
     // current column p and the pivot search keys
     unsigned long long mine[RPT];
     unsigned long long key = 0;
-    // row p's U, V: one element per lane, broadcast by readlane; every lane
-    // runs this (no divergent branch), so every source lane holds its element
-    const double bcv = lane < 4 * NBH ? bc[lane] : 0.0;
+    // row p's U, V are read by every lane from the same LDS addresses
+    // (broadcast reads; the VALU only multiplies)
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const int l = tid + r * nt;
       const bool act = l > p && l < m;
-      double xr = prr[r], xi = pri[r];
+      double xr = prr[r], xi = pri[r], yr = 0.0, yi = 0.0;
 #pragma unroll
       for (int t = 0; t < NBH; ++t) {
-        const double upr = lane_bcast(bcv, t), upi = lane_bcast(bcv, NBH + t);
-        const double vpr = lane_bcast(bcv, 2 * NBH + t), vpi = lane_bcast(bcv, 3 * NBH + t);
-        xr += ur[r][t] * vpr - ui[r][t] * vpi - (vr[r][t] * upr - vi[r][t] * upi);
-        xi += ur[r][t] * vpi + ui[r][t] * vpr - (vr[r][t] * upi + vi[r][t] * upr);
+        const double upr = bc[t], upi = bc[NBH + t];
+        const double vpr = bc[2 * NBH + t], vpi = bc[3 * NBH + t];
+        // (U_l V_p - V_l U_p)_t, four fused multiply-adds per component;
+        // even and odd t in separate accumulators (two dependency chains)
+        double& sr = (t & 1) ? yr : xr;
+        double& si = (t & 1) ? yi : xi;
+        sr = fma(ur[r][t], vpr, sr);
+        sr = fma(-ui[r][t], vpi, sr);
+        sr = fma(-vr[r][t], upr, sr);
+        sr = fma(vi[r][t], upi, sr);
+        si = fma(ur[r][t], vpi, si);
+        si = fma(ui[r][t], vpr, si);
+        si = fma(-vr[r][t], upi, si);
+        si = fma(-vi[r][t], upr, si);
       }
+      xr += yr;
+      xi += yi;
       c0r[r] = act ? xr : c0r[r];
       c0i[r] = act ? xi : c0i[r];
       mine[r] = act ? pivot_key(xr * xr + xi * xi, l) : 0ull;
@@ -185,7 +196,7 @@ void k_pf_panel(const double* __restrict__ Aall, long long astride, long long pl
     // gathers: row pl_q now (c1) and the next step's pivot row
     const int p2 = (q == p + 2) ? pp1 : pp2;
     const bool more = s + 1 < ns;
-    const double rqv = lane < 4 * NBH ? rq[lane] : 0.0;  // row q's U, V: one element per lane
+    // row q's U, V: broadcast reads from its LDS record
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const int l = tid + r * nt;
@@ -195,14 +206,26 @@ void k_pf_panel(const double* __restrict__ Aall, long long astride, long long pl
       const double g1r = act ? Ar[o1] : 0.0, g1i = act ? Ai[o1] : 0.0;
       const bool nxt = more && l > p + 2 && l < m;
       const double g2r = nxt ? Ar[o2] : 0.0, g2i = nxt ? Ai[o2] : 0.0;
-      double xr = -g1r, xi = -g1i;
+      double xr = -g1r, xi = -g1i, yr = 0.0, yi = 0.0;
 #pragma unroll
       for (int t = 0; t < NBH; ++t) {
-        const double upr = lane_bcast(rqv, t), upi = lane_bcast(rqv, NBH + t);
-        const double vpr = lane_bcast(rqv, 2 * NBH + t), vpi = lane_bcast(rqv, 3 * NBH + t);
-        xr += ur[r][t] * vpr - ui[r][t] * vpi - (vr[r][t] * upr - vi[r][t] * upi);
-        xi += ur[r][t] * vpi + ui[r][t] * vpr - (vr[r][t] * upi + vi[r][t] * upr);
+        const double upr = rq[t], upi = rq[NBH + t];
+        const double vpr = rq[2 * NBH + t], vpi = rq[3 * NBH + t];
+        // (U_l V_p - V_l U_p)_t, four fused multiply-adds per component;
+        // even and odd t in separate accumulators (two dependency chains)
+        double& sr = (t & 1) ? yr : xr;
+        double& si = (t & 1) ? yi : xi;
+        sr = fma(ur[r][t], vpr, sr);
+        sr = fma(-ui[r][t], vpi, sr);
+        sr = fma(-vr[r][t], upr, sr);
+        sr = fma(vi[r][t], upi, sr);
+        si = fma(ur[r][t], vpi, si);
+        si = fma(ui[r][t], vpr, si);
+        si = fma(-vr[r][t], upi, si);
+        si = fma(-vi[r][t], upr, si);
       }
+      xr += yr;
+      xi += yi;
       // U[l][s] = b1_l = -c1_l ; V[l][s] = b0_l / a = -c0_l / a, appended after a shift
       const double br = -c0r[r], bi = -c0i[r];
 #pragma unroll
