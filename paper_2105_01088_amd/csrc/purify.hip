@@ -4,11 +4,15 @@
 // lambda_j rescaled to unit modulus is the orthogonal polar factor of X.
 // Because dGamma anticommutes with Gamma (purity is preserved to first
 // order, Sec. III.B), X^T X = 1 + ds^2 dGamma^T dGamma: every singular value of
-// X lies in [1, sqrt(1 + ds^2 |dGamma|_2^2)].  k_euler scales each state by
-// 1/sqrt(1 + ds^2 |dGamma|_1^2) (|.|_1 >= |.|_2 for a skew matrix), which puts
-// the spectrum in (0, 1], inside the convergence region (0, sqrt 3) of the
-// Newton-Schulz iteration X <- X (3 - X^T X) / 2 = X (3 + X^2) / 2 (two grouped
-// GEMMs; the polar factor is unchanged by the scaling).  Each state converges
+// X lies in [1, sqrt(1 + ds^2 |dGamma|_2^2)].  The Newton-Schulz iteration
+// X <- X (3 - X^T X) / 2 = X (3 + X^2) / 2 (two grouped GEMMs) converges for
+// singular values in (0, sqrt 3) and fastest near 1; the polar factor is
+// unchanged by a positive scaling.  k_euler scales each state by
+// min(1, 1.6 / sqrt(1 + ds^2 |dGamma|_1^2)) (|.|_1 >= |.|_2 for a skew
+// matrix): the spectrum stays below 1.6 < sqrt 3, and the smallest singular
+// values (exactly 1) are not pushed down unless the bound forces it.  (The
+// plain 1 / sqrt(1 + ds^2 |dGamma|_1^2) put them at ~0.6 for the usual step
+// sizes: 6 iterations where this takes 4.)  Each state converges
 // on its own: the square's epilogue records max |X_mu^2 + 1| per state, and
 // the next product marks the first iteration below the detection threshold
 // as that state's last (ctl[mu]); later GEMM jobs of the state exit at once.
@@ -23,7 +27,7 @@ static int grid_for(long long total) {
   return (int)b;
 }
 
-// X = alpha_mu (Gamma + ds dGamma), alpha_mu = 1/sqrt(1 + (ds |dGamma_mu|_1)^2);
+// X = alpha_mu (Gamma + ds dGamma), alpha_mu = min(1, 1.6 / sqrt(1 + (ds |dGamma_mu|_1)^2));
 // also resets the polar iteration's control words (one per state) and
 // residual slots.
 __global__ __launch_bounds__(256) void k_euler(const double* __restrict__ gam, const double* __restrict__ dG,
@@ -36,7 +40,7 @@ __global__ __launch_bounds__(256) void k_euler(const double* __restrict__ gam, c
        e += (long long)gridDim.x * blockDim.x) {
     const int mu = (int)(e / nn);
     const double t = dtau * __longlong_as_double((long long)nrm[mu]);
-    const double alpha = 1.0 / sqrt(1.0 + t * t);
+    const double alpha = fmin(1.0, 1.6 / sqrt(1.0 + t * t));
     X[e] = alpha * (gam[e] + dtau * dG[e]);
   }
   if (blockIdx.x == 0) {
