@@ -216,13 +216,15 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
 }
 
 // Elementwise terms of state mu, tile (I, J), I <= J:
-//   sum_b Re{c1 (F + i (Y - Y^T)) + c2 D} = sum_b [x1 (F_r + Y^T-part) ...]
+//   sum_b Re{c1 (F + i (Y - Y^T)) + c2 D}
 // written out: (y1 Yr + x1 sg Yi)(j, i) - y1 Yr(i, j) - x1 sg Yi(i, j)
 // + x2 ds Dr(i, j) - y2 sg Di(i, j), plus x1 F_r - y1 sg F_i on the impurity
-// block, plus (sum_b x1) A (F = A + the impurity correction).  The (j, i)
-// block comes in through LDS, transposed, so every load is row-contiguous.
-// grid: (ntri, R), 256 threads; thread: column tid & 63, rows tid >> 6 + 4 k.
-__global__ __launch_bounds__(256) void k_force_elem(int n, int R, int T, const ForceTerm* __restrict__ terms,
+// block, plus (sum_b x1) A (F = A + the impurity correction).
+// grid: (ntri, R), 512 threads; thread: column tid & 63, rows tid >> 6 + 8 k.
+// The (j, i) terms are read row-contiguous from block (J, I) and summed over
+// b in registers at the thread's own (J, I) positions; one transpose through
+// LDS at the end puts them at (i, j), so the term loop has no barrier.
+__global__ __launch_bounds__(512) void k_force_elem(int n, int R, int T, const ForceTerm* __restrict__ terms,
                                                     const double* __restrict__ coef,
                                                     const double* __restrict__ Adense,
                                                     const int* __restrict__ impos, int M,
@@ -235,12 +237,13 @@ __global__ __launch_bounds__(256) void k_force_elem(int n, int R, int T, const F
   const int row0 = I * 64, col0 = J * 64;
   const long long nn = (long long)n * n;
   const int tid = threadIdx.x, lj = tid & 63, lr = tid >> 6;
-  const int gj = col0 + lj;
+  const int gj = col0 + lj;   // direct element (row0 + li, gj)
+  const int gc = row0 + lj;   // transposed element (col0 + li, gc)
   const double* c1t = coef;
   const double* c2t = coef + 2 * R * R;
-  double lin[16];
+  double lin[8], tsum[8];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) lin[k] = 0.0;
+  for (int k = 0; k < 8; ++k) { lin[k] = 0.0; tsum[k] = 0.0; }
   double sx1 = 0.0;
   for (int b = 0; b < R; ++b) {
     const ForceTerm tm = terms[mu * R + b];
@@ -254,24 +257,19 @@ __global__ __launch_bounds__(256) void k_force_elem(int n, int R, int T, const F
     const SGS_GLOBAL double* __restrict__ Dr = as_global(tm.Dr);
     const SGS_GLOBAL double* __restrict__ Di = as_global(has_im ? tm.Di : tm.Dr);
     sx1 += x1;
-    // Tt[c][r] = (y1 Yr + x1 sg Yi)(col0 + r, row0 + c)
-    __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int r = lr + 4 * k, c = lj;
-      const int gr = col0 + r, gc = row0 + c;
-      const bool ok = gr < n && gc < n;
-      const long long o = ok ? (long long)gr * n + gc : 0;
-      const double v = y1 * Yr[o] + im * x1 * sg * Yi[o];
-      Tt[c][r] = ok ? v : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int li = lr + 4 * k, gi = row0 + li;
+    for (int k = 0; k < 8; ++k) {
+      const int li = lr + 8 * k;
+      // (y1 Yr + x1 sg Yi) at (col0 + li, row0 + lj): the (j, i) term of
+      // output element (row0 + lj, col0 + li)
+      const int gr = col0 + li;
+      const bool okt = gr < n && gc < n;
+      const long long ot = okt ? (long long)gr * n + gc : 0;
+      tsum[k] += okt ? y1 * Yr[ot] + im * x1 * sg * Yi[ot] : 0.0;
+      const int gi = row0 + li;
       const bool ok = gi < n && gj < n;
       const long long o = ok ? (long long)gi * n + gj : 0;
-      double v = Tt[li][lj] - y1 * Yr[o] + x2 * ds * Dr[o] + im * (-x1 * sg * Yi[o] - y2 * sg * Di[o]);
+      double v = -y1 * Yr[o] + x2 * ds * Dr[o] + im * (-x1 * sg * Yi[o] - y2 * sg * Di[o]);
       if (M > 0 && ok) {
         const int pi = impos[gi], pj = impos[gj];
         if (pi >= 0 && pj >= 0) {
@@ -282,26 +280,36 @@ __global__ __launch_bounds__(256) void k_force_elem(int n, int R, int T, const F
       if (ok) lin[k] += v;
     }
   }
-  // total, skew write-out (the diagonal tile antisymmetrized through LDS)
+  // Tt[lj][li] = tsum: the (j, i) sums of output element (row0 + lj, col0 + li)
+#pragma unroll
+  for (int k = 0; k < 8; ++k) Tt[lj][lr + 8 * k] = tsum[k];
   __syncthreads();
   double* out = dE + (long long)mu * nn;
+  double v[8];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int li = lr + 4 * k, gi = row0 + li;
-    double v = 0.0;
-    if (gi < n && gj < n) v = lin[k] + sx1 * Adense[(long long)gi * n + gj];
-    if (I == J) Tt[li][lj] = v;
-    else if (gi < n && gj < n) {
-      out[(long long)gi * n + gj] = v;
-      out[(long long)gj * n + gi] = -v;
-    }
+  for (int k = 0; k < 8; ++k) {
+    const int li = lr + 8 * k, gi = row0 + li;
+    v[k] = (gi < n && gj < n) ? lin[k] + Tt[li][lj] + sx1 * Adense[(long long)gi * n + gj] : 0.0;
   }
   if (I == J) {
+    // the diagonal tile antisymmetrized through LDS
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int li = lr + 4 * k, gi = row0 + li;
+    for (int k = 0; k < 8; ++k) Tt[lr + 8 * k][lj] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int li = lr + 8 * k, gi = row0 + li;
       if (gi < n && gj < n) out[(long long)gi * n + gj] = 0.5 * (Tt[li][lj] - Tt[lj][li]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int li = lr + 8 * k, gi = row0 + li;
+      if (gi < n && gj < n) {
+        out[(long long)gi * n + gj] = v[k];
+        out[(long long)gj * n + gi] = -v[k];
+      }
     }
   }
 }
@@ -354,7 +362,7 @@ hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef
 hipError_t launch_force_elem(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
                              const int* impos, int M, double* dE, hipStream_t s) {
   const int T = (n + 63) / 64;
-  hipLaunchKernelGGL(k_force_elem, dim3(T * (T + 1) / 2, R), dim3(256), 0, s, n, R, T, terms, coef, A, impos, M,
+  hipLaunchKernelGGL(k_force_elem, dim3(T * (T + 1) / 2, R), dim3(512), 0, s, n, R, T, terms, coef, A, impos, M,
                      dE);
   return hipGetLastError();
 }
