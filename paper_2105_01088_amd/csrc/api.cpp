@@ -349,8 +349,8 @@ static void carve(Prob& q, Arena& ar) {
   q.q_idx = ar.take<int>(std::max(1, 4 * q.nq));
   q.q_loc = ar.take<int>(std::max(1, 4 * q.nq));
   q.resid = ar.take<unsigned long long>(8);  // [0]: input validation
-  q.nsctl = ar.take<int>(std::max(4, R));  // one control word per state
-  q.nsres = ar.take<unsigned long long>(64 * (size_t)R);  // [it * R + mu]: polar residuals
+  q.nsctl = ar.take<int>(R + 4);  // [0] all done, [1] count, [2 + mu] per state
+  q.nsres = ar.take<unsigned long long>(64 * (size_t)(R + 2));  // [it (R + 2) + 2 + mu]: polar residuals
   q.dgnorm = ar.take<unsigned long long>(32);
   q.terms = ar.take<ForceTerm>((size_t)R * R);
 }
@@ -676,12 +676,12 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
     for (int mu = 0; mu < R; ++mu) {
       GemmJob jq = job(Xin + mu * nn, n, 0, Xin + mu * nn, n, 0, nullptr, n, q.nsQ + mu * nn, n, n, n, n, 1.0, 0.0);
       jq.mirror = 1;  // X^2 is symmetric for skew X
-      jq.gate = mu;
+      jq.gate = 2 + mu;
       add_job(q.jnsq[par], jq);
       GemmJob jx = job(Xin + mu * nn, n, 0, q.nsQ + mu * nn, n, 0, Xin + mu * nn, n, Xout + mu * nn, n, n, n, n,
                        0.5, 1.5);
       jx.mirror = -1;  // X (3 + X^2) / 2 is skew
-      jx.gate = mu;
+      jx.gate = 2 + mu;
       add_job(q.jnsx[par], jx);
     }
     HIPCHK(upload_jobs(q.jnsq[par])); HIPCHK(upload_jobs(q.jnsx[par]));
@@ -865,14 +865,14 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
   }
   const int maxit = c->opt.purify_iters;
   unsigned long long* rs = q.nsres;
-  HCHK(launch_euler(q.gam, q.dG, dtau, n, R, q.nsX0, q.nsctl, rs, maxit * R, q.dgnorm, s));
+  HCHK(launch_euler(q.gam, q.dG, dtau, n, R, q.nsX0, q.nsctl, rs, maxit * (R + 2), q.dgnorm, s));
   const double thr = std::min(1e-8, std::sqrt(c->opt.purify_tol));
   for (int it = 0; it < maxit; ++it) {
     const int par = it & 1;
-    // Q = X X with max|Q + 1| of state mu into rs[it R + mu]; then
-    // X' = X (3 + Q) / 2, which marks this iteration as state mu's last when
-    // that residual is below thr
-    unsigned long long* ri = rs + (size_t)it * R;
+    // Q = X X with max|Q + 1| of state mu into rs[it (R + 2) + 2 + mu] (the
+    // job's gate); then X' = X (3 + Q) / 2, which marks this iteration as
+    // state mu's last when that residual is below thr
+    unsigned long long* ri = rs + (size_t)it * (R + 2);
     HCHK(launch_gemm(q.jnsq[par].dev, q.jnsq[par].xm, false, s, q.nsctl, it, nullptr, 0.0, ri));
     HCHK(launch_gemm(q.jnsx[par].dev, q.jnsx[par].xm, false, s, q.nsctl, it, ri, thr, nullptr));
   }

@@ -57,7 +57,10 @@ constexpr int LDP = 64 + 1;  // LDS row pitch (elements), padded
 // residuals measured on this iteration's inputs: if rchk[gate] is below thr,
 // this iteration is the job's last one (ctl[gate] = it).  rmax (optional)
 // receives max |D + 1| over each job's outputs (D square) in rmax[gate], as
-// an ordered bit pattern.
+// an ordered bit pattern.  ctl[0] is the last iteration of every job (the
+// whole launch exits at once past it, before reading its job) and ctl[1]
+// counts the gates not yet marked: the workgroup that marks the last one sets
+// ctl[0].  Gates of marked jobs start at 2.
 template <typename T, typename Job, bool CPLX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm(const Job* __restrict__ jobs, XcdMap xm,
                                               int* __restrict__ ctl, int it,
@@ -69,6 +72,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   T(*As)[TK][LDP] = (T(*)[TK][LDP])smem_ab;
   T(*Bs)[TK][LDP] = (T(*)[TK][LDP])(smem_ab + NP * TK * LDP);
 
+  if (ctl != nullptr && ctl[0] < it) return;
   const int x = blockIdx.x & 7;
   const int tile = blockIdx.x >> 3;
   if (xm.off[x] >= xm.off[x + 1]) return;
@@ -80,8 +84,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   if (ctl != nullptr) {
     const int g = J.gate;
     if (ctl[g] < it) return;
-    if (rchk != nullptr && __longlong_as_double((long long)rchk[g]) < thr) {
-      if (threadIdx.x == 0 && ctl[g] > it) ctl[g] = it;
+    if (rchk != nullptr && threadIdx.x == 0 && __longlong_as_double((long long)rchk[g]) < thr) {
+      // exactly one workgroup of the job sees the old value above it
+      if (atomicMin(ctl + g, it) > it && atomicSub(ctl + 1, 1) == 1) ctl[0] = it;
     }
   }
   const int mirror = J.mirror;

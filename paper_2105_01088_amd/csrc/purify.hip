@@ -15,7 +15,8 @@
 // sizes: 6 iterations where this takes 4.)  Each state converges
 // on its own: the square's epilogue records max |X_mu^2 + 1| per state, and
 // the next product marks the first iteration below the detection threshold
-// as that state's last (ctl[mu]); later GEMM jobs of the state exit at once.
+// as that state's last (ctl[2 + mu]); later GEMM jobs of the state exit at
+// once, and once every state is marked whole launches do (ctl[0], ctl[1]).
 #include "sgs_internal.h"
 
 namespace sgs {
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(256) void k_euler(const double* __restrict__ gam, c
     X[e] = alpha * (gam[e] + dtau * dG[e]);
   }
   if (blockIdx.x == 0) {
-    for (int t = threadIdx.x; t < R; t += blockDim.x) ctl[t] = 0x7fffffff;
+    for (int t = threadIdx.x; t < R + 2; t += blockDim.x) ctl[t] = t == 1 ? R : 0x7fffffff;
     for (int t = threadIdx.x; t < nresid; t += blockDim.x) resid[t] = 0ull;
   }
 }
@@ -82,7 +83,7 @@ __global__ void k_finalize(const double* __restrict__ X0, const double* __restri
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
     const long long mu = e / nn, r = e - mu * nn;
-    const int c = ctl[mu];
+    const int c = ctl[2 + mu];
     const int last = (c == 0x7fffffff) ? maxit : c + 1;
     const double* X = (last & 1) ? X1 : X0;
     const int i = (int)(r / n), j = (int)(r - (long long)i * n);
@@ -90,7 +91,7 @@ __global__ void k_finalize(const double* __restrict__ X0, const double* __restri
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     bool conv = true;
-    for (int mu = 0; mu < R; ++mu) conv = conv && ctl[mu] != 0x7fffffff;
+    for (int mu = 0; mu < R; ++mu) conv = conv && ctl[2 + mu] != 0x7fffffff;
     if (!conv) atomicCAS(status, ST_OK, ST_NOCONV);
   }
 }
