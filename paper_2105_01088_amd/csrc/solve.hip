@@ -8,21 +8,34 @@
 //        Pf(Gamma_a + Gamma_0) > 0 for states of equal parity), h_ab = G_ab eps_ab.
 //  2. h lambda = E G lambda (Eq. eigLambda): canonical orthogonalization
 //     (eigenvectors of G below g_rel_threshold * max dropped) and the lowest
-//     root of the projected h, both by cyclic Jacobi on the real 2R x 2R
-//     embedding [[Re, -Im], [Im, Re]] of the Hermitian matrices.
+//     root of the projected h, both by cyclic complex Jacobi on the
+//     Hermitian parts of G and h.
 //  3. lambda~ = G lambda; w_mu lambda_b for the chosen c_mu (Eq. Bmu);
 //     force coefficients c1 = 4 w_mu lambda_b G_mb, c2 = -2 w_mu lambda_b (h_mb - E G_mb).
 #include "sgs_internal.h"
 
 namespace sgs {
 
+struct JacobiSlots {
+  double *c, *s, *er, *ei;  // rotation and phase of each pair of a round
+  int *p, *q;
+};
 
-// Cyclic Jacobi (round-robin ordering) on the symmetric m x m matrix A
-// (pitch ld) in LDS; V receives the eigenvectors (columns).  64 threads.
-__device__ void jacobi(double* A, double* V, int m, int ld, double* rc, double* rs, int* rp,
-                       int* rq, int* flag) {
+// Cyclic Jacobi (round-robin ordering) on the Hermitian m x m matrix
+// A = Ar + i Ai (pitch ld) in LDS; V = Vr + i Vi receives the eigenvectors
+// (columns), the diagonal of Ar the eigenvalues.  The rotation of a pair
+// (p, q) with a_pq = r e^{i phi} is U = D G: D = diag(1, e^{-i phi}) makes the
+// pivot real, G = [[c, s], [-s, c]] is the real symmetric rotation that
+// zeroes it; A <- U^H A U, V <- V U.  Sweeps end when a whole sweep finds
+// every |a_pq| <= 1e-18 (|a_pp| + |a_qq|).  64 threads.
+__device__ void jacobi_herm(double* Ar, double* Ai, double* Vr, double* Vi, int m, int ld, const JacobiSlots& r,
+                            int* flag) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < m * m; e += blockDim.x) V[(e / m) * ld + e % m] = (e / m == e % m) ? 1.0 : 0.0;
+  for (int e = tid; e < m * m; e += blockDim.x) {
+    const int i = e / m, j = e % m;
+    Vr[i * ld + j] = (i == j) ? 1.0 : 0.0;
+    Vi[i * ld + j] = 0.0;
+  }
   __syncthreads();
   if (m < 2) return;
   const int mm = m + (m & 1);  // round-robin needs an even count: pad with a dummy index
@@ -36,43 +49,65 @@ __device__ void jacobi(double* A, double* V, int m, int ld, double* rc, double* 
         if (t == 0) { x = mm - 1; y = round; }
         else { x = (round + t) % (mm - 1); y = (round - t + (mm - 1)) % (mm - 1); }
         const int p = x < y ? x : y, q = x < y ? y : x;
-        double c = 1.0, s = 0.0;
-        const bool real_pair = q < m;
-        const double app = real_pair ? A[p * ld + p] : 0.0, aqq = real_pair ? A[q * ld + q] : 0.0;
-        const double apq = real_pair ? A[p * ld + q] : 0.0;
-        if (real_pair && apq != 0.0 && fabs(apq) > 1e-18 * (fabs(app) + fabs(aqq))) {
-          const double th = (aqq - app) / (2.0 * apq);
-          const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-          c = 1.0 / sqrt(tt * tt + 1.0);
-          s = tt * c;
-          *flag = 1;
+        double c = 1.0, sn = 0.0, er = 1.0, ei = 0.0;
+        if (q < m) {
+          const double app = Ar[p * ld + p], aqq = Ar[q * ld + q];
+          const double xr = Ar[p * ld + q], xi = Ai[p * ld + q];
+          const double rr = hypot(xr, xi);
+          if (rr != 0.0 && rr > 1e-18 * (fabs(app) + fabs(aqq))) {
+            er = xr / rr;
+            ei = xi / rr;
+            const double th = (aqq - app) / (2.0 * rr);
+            const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(tt * tt + 1.0);
+            sn = tt * c;
+            *flag = 1;
+          }
         }
-        rc[t] = c; rs[t] = s; rp[t] = p; rq[t] = q;
+        r.c[t] = c; r.s[t] = sn; r.er[t] = er; r.ei[t] = ei; r.p[t] = p; r.q[t] = q;
       }
       __syncthreads();
-      // rows: A <- P^T A
+      // rows: a_p <- c a_p - s e^{i phi} a_q,  a_q <- s a_p + c e^{i phi} a_q
       for (int e = tid; e < half * m; e += blockDim.x) {
         const int t = e / m, j = e % m;
-        const double c = rc[t], s = rs[t];
-        if (s == 0.0) continue;
-        const int p = rp[t], q = rq[t];
-        const double ap = A[p * ld + j], aq = A[q * ld + j];
-        A[p * ld + j] = c * ap - s * aq;
-        A[q * ld + j] = s * ap + c * aq;
+        const double sn = r.s[t];
+        if (sn == 0.0) continue;
+        const double c = r.c[t], er = r.er[t], ei = r.ei[t];
+        const int p = r.p[t], q = r.q[t];
+        const double apr = Ar[p * ld + j], api = Ai[p * ld + j];
+        const double aqr = Ar[q * ld + j], aqi = Ai[q * ld + j];
+        const double br = er * aqr - ei * aqi, bi = er * aqi + ei * aqr;
+        Ar[p * ld + j] = c * apr - sn * br;
+        Ai[p * ld + j] = c * api - sn * bi;
+        Ar[q * ld + j] = sn * apr + c * br;
+        Ai[q * ld + j] = sn * api + c * bi;
       }
       __syncthreads();
-      // columns: A <- A P, V <- V P
+      // columns of A and V: x_p <- c x_p - s e^{-i phi} x_q,  x_q <- s x_p + c e^{-i phi} x_q
       for (int e = tid; e < half * m; e += blockDim.x) {
         const int t = e / m, i = e % m;
-        const double c = rc[t], s = rs[t];
-        if (s == 0.0) continue;
-        const int p = rp[t], q = rq[t];
-        const double ap = A[i * ld + p], aq = A[i * ld + q];
-        A[i * ld + p] = c * ap - s * aq;
-        A[i * ld + q] = s * ap + c * aq;
-        const double vp = V[i * ld + p], vq = V[i * ld + q];
-        V[i * ld + p] = c * vp - s * vq;
-        V[i * ld + q] = s * vp + c * vq;
+        const double sn = r.s[t];
+        if (sn == 0.0) continue;
+        const double c = r.c[t], er = r.er[t], ei = r.ei[t];
+        const int p = r.p[t], q = r.q[t];
+        {
+          const double apr = Ar[i * ld + p], api = Ai[i * ld + p];
+          const double aqr = Ar[i * ld + q], aqi = Ai[i * ld + q];
+          const double br = er * aqr + ei * aqi, bi = er * aqi - ei * aqr;
+          Ar[i * ld + p] = c * apr - sn * br;
+          Ai[i * ld + p] = c * api - sn * bi;
+          Ar[i * ld + q] = sn * apr + c * br;
+          Ai[i * ld + q] = sn * api + c * bi;
+        }
+        {
+          const double vpr = Vr[i * ld + p], vpi = Vi[i * ld + p];
+          const double vqr = Vr[i * ld + q], vqi = Vi[i * ld + q];
+          const double br = er * vqr + ei * vqi, bi = er * vqi - ei * vqr;
+          Vr[i * ld + p] = c * vpr - sn * br;
+          Vi[i * ld + p] = c * vpi - sn * bi;
+          Vr[i * ld + q] = sn * vpr + c * br;
+          Vi[i * ld + q] = sn * vpi + c * bi;
+        }
       }
       __syncthreads();
     }
@@ -82,27 +117,34 @@ __device__ void jacobi(double* A, double* V, int m, int ld, double* rc, double* 
   }
 }
 
-// dynamic LDS: 3 m*m + 12 R + 4 m doubles-ish (see solve_lds_bytes)
+// dynamic LDS: see solve_lds_bytes
 __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
   extern __shared__ double smem[];
-  const int R = a.R, m = 2 * R, ld = m;
-  double* A = smem;
-  double* V = A + m * m;
-  double* C = V + m * m;
-  double* Gr = C + m * m;      // R*R
+  const int R = a.R, ld = R + 1;  // odd pitch: column walks spread over the banks
+  const int RL = R * ld;
+  double* Ar = smem;           // working Hermitian matrix
+  double* Ai = Ar + RL;
+  double* Vr = Ai + RL;        // eigenvectors of G, then X
+  double* Vi = Vr + RL;
+  double* Cr = Vi + RL;        // He X, then the eigenvectors of h'
+  double* Ci = Cr + RL;
+  double* Gr = Ci + RL;        // R*R (pitch R)
   double* Gi = Gr + R * R;
   double* Hr = Gi + R * R;
   double* Hi = Hr + R * R;
-  double* sv = Hi + R * R;     // m eigenvalues of G
-  double* lr = sv + m;         // R
+  double* sv = Hi + R * R;     // R eigenvalues of G
+  double* lr = sv + R;         // R
   double* li = lr + R;
   double* ltr = li + R;
   double* lti = ltr + R;
-  double* rc = lti + R;        // m/2 + 1 rotation slots
-  double* rs = rc + R + 1;
-  int* rp = (int*)(rs + R + 1);
-  int* rq = rp + R + 1;
-  int* keep = rq + R + 1;      // m
+  JacobiSlots js;
+  js.c = lti + R;              // R/2 + 1 rotation slots each
+  js.s = js.c + R + 1;
+  js.er = js.s + R + 1;
+  js.ei = js.er + R + 1;
+  js.p = (int*)(js.ei + R + 1);
+  js.q = js.p + R + 1;
+  int* keep = js.q + R + 1;    // R
   __shared__ int flag, K;
   __shared__ double Es;
   const int tid = threadIdx.x;
@@ -143,89 +185,99 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
   }
   __syncthreads();
 
-  // 2a. Jacobi on the embedding of G (Hermitian parts)
-  for (int e = tid; e < m * m; e += blockDim.x) {
-    const int i = e / m, j = e % m;
-    const int ii = i % R, jj = j % R;
-    const double re = 0.5 * (Gr[ii * R + jj] + Gr[jj * R + ii]);
-    const double im = 0.5 * (Gi[ii * R + jj] - Gi[jj * R + ii]);
-    double v;
-    if ((i < R) == (j < R)) v = re;
-    else if (i < R) v = -im;   // top-right block: -Im
-    else v = im;               // bottom-left: +Im
-    A[i * ld + j] = v;
+  // 2a. Jacobi on the Hermitian part of G
+  for (int e = tid; e < R * R; e += blockDim.x) {
+    const int i = e / R, j = e % R;
+    Ar[i * ld + j] = 0.5 * (Gr[i * R + j] + Gr[j * R + i]);
+    Ai[i * ld + j] = 0.5 * (Gi[i * R + j] - Gi[j * R + i]);
   }
   __syncthreads();
-  jacobi(A, V, m, ld, rc, rs, rp, rq, &flag);
-  for (int k = tid; k < m; k += blockDim.x) sv[k] = A[k * ld + k];
+  jacobi_herm(Ar, Ai, Vr, Vi, R, ld, js, &flag);
+  for (int k = tid; k < R; k += blockDim.x) sv[k] = Ar[k * ld + k];
   __syncthreads();
   if (tid == 0) {
     double smax = 0.0;
-    for (int k = 0; k < m; ++k) smax = fmax(smax, sv[k]);
+    for (int k = 0; k < R; ++k) smax = fmax(smax, sv[k]);
     int cnt = 0;
     if (!(smax > 0.0) || !isfinite(smax)) atomicCAS(a.status, ST_OK, ST_SINGULAR);
-    for (int k = 0; k < m; ++k)
+    for (int k = 0; k < R; ++k)
       if (sv[k] > a.g_thr * smax) keep[cnt++] = k;
     K = cnt;
   }
   __syncthreads();
   const int Kk = K;
   // X = V[:, keep] diag(s^{-1/2}), compacted in place (row by row)
-  for (int i = tid; i < m; i += blockDim.x)
-    for (int c = 0; c < Kk; ++c) V[i * ld + c] = V[i * ld + keep[c]] / sqrt(sv[keep[c]]);
+  for (int i = tid; i < R; i += blockDim.x)
+    for (int c = 0; c < Kk; ++c) {
+      const double f = 1.0 / sqrt(sv[keep[c]]);
+      Vr[i * ld + c] = Vr[i * ld + keep[c]] * f;
+      Vi[i * ld + c] = Vi[i * ld + keep[c]] * f;
+    }
   __syncthreads();
-  // 2b. h' = X^T He X
-  for (int e = tid; e < m * m; e += blockDim.x) {
-    const int i = e / m, j = e % m;
-    const int ii = i % R, jj = j % R;
-    const double re = 0.5 * (Hr[ii * R + jj] + Hr[jj * R + ii]);
-    const double im = 0.5 * (Hi[ii * R + jj] - Hi[jj * R + ii]);
-    double v;
-    if ((i < R) == (j < R)) v = re;
-    else if (i < R) v = -im;
-    else v = im;
-    A[i * ld + j] = v;
+  // 2b. h' = X^H He X with He the Hermitian part of h
+  for (int e = tid; e < R * R; e += blockDim.x) {
+    const int i = e / R, j = e % R;
+    Ar[i * ld + j] = 0.5 * (Hr[i * R + j] + Hr[j * R + i]);
+    Ai[i * ld + j] = 0.5 * (Hi[i * R + j] - Hi[j * R + i]);
   }
   __syncthreads();
-  for (int e = tid; e < m * Kk; e += blockDim.x) {  // C = He X  (m x K)
+  for (int e = tid; e < R * Kk; e += blockDim.x) {  // C = He X  (R x K)
     const int i = e / Kk, c = e % Kk;
-    double s = 0.0;
-    for (int k = 0; k < m; ++k) s += A[i * ld + k] * V[k * ld + c];
-    C[i * ld + c] = s;
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < R; ++k) {
+      const double ar = Ar[i * ld + k], ai = Ai[i * ld + k], xr = Vr[k * ld + c], xi = Vi[k * ld + c];
+      sr += ar * xr - ai * xi;
+      si += ar * xi + ai * xr;
+    }
+    Cr[i * ld + c] = sr;
+    Ci[i * ld + c] = si;
   }
   __syncthreads();
-  for (int e = tid; e < Kk * Kk; e += blockDim.x) {  // A = X^T C (K x K)
-    const int r = e / Kk, c = e % Kk;
-    double s = 0.0;
-    for (int k = 0; k < m; ++k) s += V[k * ld + r] * C[k * ld + c];
-    A[r * ld + c] = s;
+  for (int e = tid; e < Kk * Kk; e += blockDim.x) {  // A = X^H C (K x K)
+    const int rr = e / Kk, c = e % Kk;
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < R; ++k) {
+      const double xr = Vr[k * ld + rr], xi = -Vi[k * ld + rr], yr = Cr[k * ld + c], yi = Ci[k * ld + c];
+      sr += xr * yr - xi * yi;
+      si += xr * yi + xi * yr;
+    }
+    Ar[rr * ld + c] = sr;
+    Ai[rr * ld + c] = si;
   }
   __syncthreads();
-  for (int e = tid; e < Kk * Kk; e += blockDim.x) {  // exact symmetry
-    const int r = e / Kk, c = e % Kk;
-    if (r < c) {
-      const double s = 0.5 * (A[r * ld + c] + A[c * ld + r]);
-      A[r * ld + c] = s;
-      A[c * ld + r] = s;
+  for (int e = tid; e < Kk * Kk; e += blockDim.x) {  // exactly Hermitian
+    const int rr = e / Kk, c = e % Kk;
+    if (rr < c) {
+      const double sr = 0.5 * (Ar[rr * ld + c] + Ar[c * ld + rr]);
+      const double si = 0.5 * (Ai[rr * ld + c] - Ai[c * ld + rr]);
+      Ar[rr * ld + c] = sr; Ai[rr * ld + c] = si;
+      Ar[c * ld + rr] = sr; Ai[c * ld + rr] = -si;
+    } else if (rr == c) {
+      Ai[rr * ld + c] = 0.0;
     }
   }
   __syncthreads();
-  jacobi(A, C, Kk, ld, rc, rs, rp, rq, &flag);
+  jacobi_herm(Ar, Ai, Cr, Ci, Kk, ld, js, &flag);
   if (tid == 0) {
     int k0 = 0;
     for (int k = 1; k < Kk; ++k)
-      if (A[k * ld + k] < A[k0 * ld + k0]) k0 = k;
-    Es = A[k0 * ld + k0];
+      if (Ar[k * ld + k] < Ar[k0 * ld + k0]) k0 = k;
+    Es = Ar[k0 * ld + k0];
     flag = k0;
   }
   __syncthreads();
   const int k0 = flag;
   const double E = Es;
-  // lambda_e = X z
-  for (int i = tid; i < m; i += blockDim.x) {
-    double s = 0.0;
-    for (int c = 0; c < Kk; ++c) s += V[i * ld + c] * C[c * ld + k0];
-    if (i < R) lr[i] = s; else li[i - R] = s;
+  // lambda = X z
+  for (int i = tid; i < R; i += blockDim.x) {
+    double sr = 0.0, si = 0.0;
+    for (int c = 0; c < Kk; ++c) {
+      const double xr = Vr[i * ld + c], xi = Vi[i * ld + c], zr = Cr[c * ld + k0], zi = Ci[c * ld + k0];
+      sr += xr * zr - xi * zi;
+      si += xr * zi + xi * zr;
+    }
+    lr[i] = sr;
+    li[i] = si;
   }
   __syncthreads();
   // 3. lambda~ = G lambda, weights, coefficients
@@ -276,9 +328,9 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
 }
 
 size_t solve_lds_bytes(int R) {
-  const int m = 2 * R;
-  return sizeof(double) * (3 * (size_t)m * m + 4 * (size_t)R * R + m + 4 * R + 2 * (R + 1)) +
-         sizeof(int) * (2 * (R + 1) + m) + 64;
+  const size_t RL = (size_t)R * (R + 1);
+  return sizeof(double) * (6 * RL + 4 * (size_t)R * R + 5 * (size_t)R + 4 * (size_t)(R + 1)) +
+         sizeof(int) * (2 * (size_t)(R + 1) + R) + 64;
 }
 
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
