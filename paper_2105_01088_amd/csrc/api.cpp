@@ -296,7 +296,7 @@ static void carve_scratch(Prob& q, Arena& ar) {
   q.gjE = ar.take<double>(std::max(1LL, (long long)P * n * GJ_NB_MAX));
   q.gjB = ar.take<double>(std::max(1LL, (long long)P * n * GJ_NB_MAX));
   q.dG = ar.take<double>(R * nn);
-  q.dP = ar.take<double>(R * nn);  // second half of the force products, added into dG
+  q.dP = ar.take<double>(std::max(1LL, (FORCE_SPLIT - 1) * R * nn));  // partial force products, added into dG
   q.dE = ar.take<double>(R * nn);  // elementwise force terms, added into dG
   q.nsX0 = ar.take<double>(R * nn);
   q.nsX1 = ar.take<double>(R * nn);

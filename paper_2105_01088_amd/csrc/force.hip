@@ -48,7 +48,6 @@ template <> struct Vec4<double> { typedef dvec4 type; };
 template <> struct Vec4<float> { typedef fvec4 type; };
 
 constexpr int FTK = 16;
-constexpr int FORCE_SPLIT = 2;  // workgroups per output tile (term ranges)
 constexpr int FLP = 64 + 1;
 
 constexpr size_t force_lds_bytes(size_t elem) {
@@ -78,7 +77,8 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
   const int ntri = T * (T + 1) / 2;
   const int xcd = blockIdx.x & 7, loc2 = blockIdx.x >> 3;
   // each tile's terms are split over FORCE_SPLIT workgroups (the same XCD);
-  // split h sums terms [h R / S, (h + 1) R / S) into dG (h = 0) or dP
+  // split h sums terms [h R / S, (h + 1) R / S) into dG (h = 0) or slice
+  // h - 1 of dP
   const int split = loc2 % FORCE_SPLIT, loc = loc2 / FORCE_SPLIT;
   const int mu = xcd + 8 * (loc / ntri);
   if (mu >= R) return;
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
 
   // ---- total, skew write-out ----
   __syncthreads();
-  double* out = (split == 0 ? dG : dP) + (long long)mu * nn;
+  double* out = (split == 0 ? dG : dP + (long long)(split - 1) * R * nn) + (long long)mu * nn;
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -314,12 +314,12 @@ __global__ __launch_bounds__(512) void k_force_elem(int n, int R, int T, const F
   }
 }
 
-// dG <- dG + dP + dE (the two product halves and the elementwise terms), and
+// dG <- dG + (the partial products in dP) + dE (the elementwise terms), and
 // the largest row sum of |dG_mu| (= 1-norm: skew) into
 // nrm[mu] as an ordered bit pattern (k_force cleared it).  grid:
 // (ceil(n / 16), R); one wave per row.
 __global__ __launch_bounds__(256) void k_force_join(double* __restrict__ dG, const double* __restrict__ dP,
-                                                    const double* __restrict__ dE, int n,
+                                                    const double* __restrict__ dE, int n, int R,
                                                     unsigned long long* __restrict__ nrm) {
   __shared__ double red[4];
   const int mu = blockIdx.y;
@@ -327,13 +327,16 @@ __global__ __launch_bounds__(256) void k_force_join(double* __restrict__ dG, con
   double* d = dG + mu * nn;
   const double* de = dE + mu * nn;
   const double* dp = dP + mu * nn;
+  const long long pstride = (long long)R * nn;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double mx = 0.0;
   for (int i = blockIdx.x * 16 + wv; i < min(n, (int)blockIdx.x * 16 + 16); i += 4) {
     double s = 0.0;
     for (int j = lane; j < n; j += 64) {
       const long long o = (long long)i * n + j;
-      const double v = d[o] + dp[o] + de[o];
+      double v = d[o] + de[o];
+#pragma unroll
+      for (int h = 0; h + 1 < FORCE_SPLIT; ++h) v += dp[h * pstride + o];
       d[o] = v;
       s += fabs(v);
     }
@@ -369,7 +372,7 @@ hipError_t launch_force_elem(int n, int R, const ForceTerm* terms, const double*
 
 hipError_t launch_force_join(double* dG, const double* dP, const double* dE, int n, int R, unsigned long long* nrm,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_force_join, dim3((n + 15) / 16, R), dim3(256), 0, s, dG, dP, dE, n, nrm);
+  hipLaunchKernelGGL(k_force_join, dim3((n + 15) / 16, R), dim3(256), 0, s, dG, dP, dE, n, R, nrm);
   return hipGetLastError();
 }
 

@@ -117,15 +117,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
 
-  // C values of this lane's outputs, loaded before the K loop: their latency
-  // hides behind it, and no load of C can wait on a store of D (they may
-  // alias: the in-place updates pass C == D)
+  // C values of this lane's outputs.  Real jobs load them before the K loop:
+  // their latency hides behind it, and no load of C can wait on a store of D
+  // (they may alias: the in-place updates pass C == D).  Complex jobs (short
+  // K, never in place) load them after it: the 64 registers they would hold
+  // across the loop are the difference between 2 and 3 waves per SIMD.
   const T beta = J.beta;
   const SGS_GLOBAL T* __restrict__ C = as_global(J.C);
   const int ldc = J.ldc;
   const SGS_GLOBAL int* __restrict__ cperm = as_global(J.cperm);
   const long long cim = J.c_im;
   T cval[NP][2][2][4];
+  if constexpr (!CPLX) {
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -139,6 +142,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int p = 0; p < NP; ++p) cval[p][bi][bj][r] = ok ? C[co + p * cim] : T(0);
       }
+  }
 
   V4 acc[NP][2][2];
 #pragma unroll
@@ -219,6 +223,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
   }
 
+  if constexpr (CPLX) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wm * 32 + bi * 16 + AccRow<T>::row(lane, r);
+        const int col = col0 + wn * 32 + bj * 16 + (lane & 15);
+        const bool ok = beta != T(0) && row < M && col < N;
+        const long long co = !ok ? 0 : (cperm ? (long long)cperm[row] * ldc + cperm[col] : (long long)row * ldc + col);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) cval[p][bi][bj][r] = ok ? C[co + p * cim] : T(0);
+      }
+  }
   const T alpha = J.alpha, diag = J.diag;
   SGS_GLOBAL T* D = as_global(J.D);
   const int ldd = J.ldd;

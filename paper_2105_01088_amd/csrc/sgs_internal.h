@@ -205,9 +205,13 @@ hipError_t set_renyi2_lds_limit();
 hipError_t launch_renyi2(const ObsState& s, int nA, double* part, double* out, hipStream_t st);
 
 enum : int { FORCE_FP64 = 0, FORCE_FP32 = 1 };
-// k_force: the dense products, two term ranges into dG and dP (clears nrm);
-// k_force_elem: the elementwise terms into dE; k_force_join: dG += dP + dE
-// and the 1-norms
+// k_force: the dense products, FORCE_SPLIT workgroups per output tile, each
+// summing one range of the terms b: range 0 into dG, range h > 0 into slice
+// h - 1 of dP ((FORCE_SPLIT - 1) R n^2 float64; clears nrm); k_force_elem:
+// the elementwise terms into dE; k_force_join: dG += (the dP slices) + dE and
+// the 1-norms.  (One, three, four or five ranges measured no faster than two
+// at n = 400, R = 16.)
+constexpr int FORCE_SPLIT = 2;
 hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, double* dG, double* dP,
                         unsigned long long* nrm, int mode, hipStream_t s);
 hipError_t launch_force_elem(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
