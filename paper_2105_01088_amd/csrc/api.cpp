@@ -37,6 +37,7 @@ struct JobTable {
   std::vector<GemmJob> host;
   int ntiles = 0;
   bool cplx = false;
+  bool late_c = false;  // real, short K: the C tile is loaded after the K loop
   XcdMap xm{};
 };
 
@@ -612,7 +613,7 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
     // pairs are ordered (0,1) .. (0,R-1), (1,2), ...: the first R - 1 feed the phases
     for (int half = 0; half < 2; ++half) {
       JobTable& jt = half == 0 ? q.jgj0[t] : q.jgj1[t];
-      jt.host.clear(); jt.ntiles = 0;
+      jt.host.clear(); jt.ntiles = 0; jt.late_c = true;
       const int p0 = half == 0 ? 0 : std::min(P, R - 1), p1 = half == 0 ? std::min(P, R - 1) : P;
       for (int pp = p0; pp < p1; ++pp)
         add_job(jt, job(q.gjE + (long long)pp * n * GJ_NB_MAX, b, 0, q.gjB + (long long)pp * n * GJ_NB_MAX, n, 0,
@@ -723,7 +724,7 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
 // stages
 // ---------------------------------------------------------------------------
 static hipError_t run_gemm(const JobTable& t, hipStream_t s) {
-  return launch_gemm(t.dev, t.xm, t.cplx, s);
+  return t.late_c ? launch_gemm_late_c(t.dev, t.xm, s) : launch_gemm(t.dev, t.xm, t.cplx, s);
 }
 
 #define HCHK(x)                               \

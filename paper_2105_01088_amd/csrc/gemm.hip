@@ -61,7 +61,7 @@ constexpr int LDP = 64 + 1;  // LDS row pitch (elements), padded
 // whole launch exits at once past it, before reading its job) and ctl[1]
 // counts the gates not yet marked: the workgroup that marks the last one sets
 // ctl[0].  Gates of marked jobs start at 2.
-template <typename T, typename Job, bool CPLX>
+template <typename T, typename Job, bool CPLX, bool LATE_C = CPLX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm(const Job* __restrict__ jobs, XcdMap xm,
                                               int* __restrict__ ctl, int it,
                                               const unsigned long long* __restrict__ rchk, double thr,
@@ -117,18 +117,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
 
-  // C values of this lane's outputs.  Real jobs load them before the K loop:
-  // their latency hides behind it, and no load of C can wait on a store of D
-  // (they may alias: the in-place updates pass C == D).  Complex jobs (short
-  // K, never in place) load them after it: the 64 registers they would hold
-  // across the loop are the difference between 2 and 3 waves per SIMD.
+  // C values of this lane's outputs.  For long K they are loaded before the
+  // K loop: their latency hides behind it, and no load of C can wait on a
+  // store of D (they may alias: in-place updates pass C == D).  Short-K
+  // tables (the complex Pfaffian updates, the Gauss-Jordan updates) load them
+  // after it, still before any store (every lane reads only the elements it
+  // writes): the registers they would hold across the loop cost a wave per
+  // SIMD.
   const T beta = J.beta;
   const SGS_GLOBAL T* __restrict__ C = as_global(J.C);
   const int ldc = J.ldc;
   const SGS_GLOBAL int* __restrict__ cperm = as_global(J.cperm);
   const long long cim = J.c_im;
   T cval[NP][2][2][4];
-  if constexpr (!CPLX) {
+  if constexpr (!LATE_C) {
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -223,7 +225,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
   }
 
-  if constexpr (CPLX) {
+  if constexpr (LATE_C) {
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -313,6 +315,13 @@ hipError_t launch_gemm(const GemmJob* jobs, const XcdMap& xm, bool cplx, hipStre
     hipLaunchKernelGGL((k_gemm<double, GemmJob, true>), grid, dim3(256), 0, s, jobs, xm, ctl, it, rchk, thr, rmax);
   else
     hipLaunchKernelGGL((k_gemm<double, GemmJob, false>), grid, dim3(256), 0, s, jobs, xm, ctl, it, rchk, thr, rmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_late_c(const GemmJob* jobs, const XcdMap& xm, hipStream_t s) {
+  if (xm.max_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gemm<double, GemmJob, false, true>), dim3(8 * xm.max_tiles), dim3(256), 0, s, jobs, xm,
+                     (int*)nullptr, 0, (const unsigned long long*)nullptr, 0.0, (unsigned long long*)nullptr);
   return hipGetLastError();
 }
 

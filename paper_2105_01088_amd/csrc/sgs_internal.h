@@ -82,6 +82,8 @@ hipError_t launch_gemm(const GemmJob* jobs, const XcdMap& xm, bool cplx,
                        hipStream_t s, int* ctl = nullptr, int it = 0,
                        const unsigned long long* rchk = nullptr, double thr = 0.0,
                        unsigned long long* rmax = nullptr);
+// real jobs with short K (C loaded after the K loop; may be in place)
+hipError_t launch_gemm_late_c(const GemmJob* jobs, const XcdMap& xm, hipStream_t s);
 hipError_t launch_gemm_f32(const GemmJobF* jobs, const XcdMap& xm, hipStream_t s);
 
 // ---------------------------------------------------------------------------
