@@ -61,7 +61,7 @@ constexpr size_t force_lds_bytes(size_t elem) {
 // streams the same Y and Delta panels).  terms: R*R descriptors (mu-major);
 // coef: c1 then c2 tables, complex interleaved, R*R each.
 template <typename TT>
-__global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceTerm* __restrict__ terms,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_force(int n, int R, int T, const ForceTerm* __restrict__ terms,
                                                const double* __restrict__ coef,
                                                double* __restrict__ dG, double* __restrict__ dP,
                                                unsigned long long* __restrict__ nrm) {
@@ -109,18 +109,21 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
   // the loads are row segments and the LDS stores hit distinct banks)
   const int b_k = (tid >> 6) * 4, b_j = tid & 63;
 
-  // one term's GEMM; IM: the term has imaginary planes (uniform per term, so
-  // the matrix-core loop carries no branch)
-  auto run_term = [&](const ForceTerm& tm, double x1, double y1, auto im_tag) {
-    constexpr bool IM = decltype(im_tag)::value;
+  // One loop for every term (one set of accumulator registers): `im` (the
+  // term has imaginary planes) is uniform, so its branches are scalar.
+  for (int b = b_lo; b < b_hi; ++b) {
+    const ForceTerm tm = terms[mu * R + b];
+    const double x1 = c1t[2 * tm.coef], y1 = c1t[2 * tm.coef + 1];
+    const bool im = tm.Yi != nullptr;
     const double sg = tm.sgn, ds = tm.dr_scale;
     const SGS_GLOBAL double* __restrict__ Yr = as_global(tm.Yr);
-    const SGS_GLOBAL double* __restrict__ Yi = as_global(IM ? tm.Yi : tm.Yr);
+    const SGS_GLOBAL double* __restrict__ Yi = as_global(im ? tm.Yi : tm.Yr);
     const SGS_GLOBAL double* __restrict__ Dr = as_global(tm.Dr);
-    const SGS_GLOBAL double* __restrict__ Di = as_global(IM ? tm.Di : tm.Dr);
+    const SGS_GLOBAL double* __restrict__ Di = as_global(im ? tm.Di : tm.Dr);
     // raw prefetch registers: the B operand Re(c1 D) / -Im(c1 D) is formed
     // when the slab is written to LDS, so the loads of the next slab stay in
-    // flight across the current slab's matrix-core work
+    // flight across the current slab's matrix-core work (a term without
+    // imaginary planes reads its real ones twice and ignores the copy)
     double ra[2][4], rd[2][4];
     auto load = [&](int kc) {
 #pragma unroll
@@ -129,60 +132,59 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
         const bool ok = gi < n && gk < n;
         const long long o = (long long)gi * n + gk;
         ra[0][r] = ok ? Yr[o] : 0.0;
-        ra[1][r] = (IM && ok) ? Yi[o] : 0.0;
+        ra[1][r] = ok ? Yi[o] : 0.0;
         const int gk2 = kc + b_k + r, gj = col0 + b_j;
         const bool okb = gk2 < n && gj < n;
         const long long ob = (long long)gk2 * n + gj;
         rd[0][r] = okb ? Dr[ob] : 0.0;
-        rd[1][r] = (IM && okb) ? Di[ob] : 0.0;
+        rd[1][r] = okb ? Di[ob] : 0.0;
       }
     };
+    const double sgi = im ? sg : 0.0;  // zero imaginary parts for a real term
     load(0);
     for (int kc = 0; kc < n; kc += FTK) {
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double dr = ds * rd[0][r], di = sg * rd[1][r];
-        const double v[4] = {ra[0][r], sg * ra[1][r], x1 * dr - y1 * di, -(x1 * di + y1 * dr)};
+        const double dr = ds * rd[0][r], di = sgi * rd[1][r];
         // A: Y_r, sg Y_i; B: Re(c1 D), -Im(c1 D)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (!IM && (u & 1)) continue;
-          TT* dst = u < 2 ? &As[u][a_k + r][a_i] : &Bs[u - 2][b_k + r][b_j];
-          *dst = (TT)v[u];
-        }
+        As[0][a_k + r][a_i] = (TT)ra[0][r];
+        As[1][a_k + r][a_i] = (TT)(sgi * ra[1][r]);
+        Bs[0][b_k + r][b_j] = (TT)(x1 * dr - y1 * di);
+        Bs[1][b_k + r][b_j] = (TT)(-(x1 * di + y1 * dr));
       }
       __syncthreads();
       if (kc + FTK < n) load(kc + FTK);
-#pragma unroll
-      for (int kk = 0; kk < FTK / 4; ++kk) {
+      // operand fragments of k-step kk + 1 are read from LDS while the
+      // matrix cores work on k-step kk
+      TT ah[2][2][2], bh[2][2][2];  // [buffer][re/im][q]
+      auto frag = [&](int kk, int buf) {
         const int kr = kk * 4 + (lane >> 4);
-        TT ah[2][2], bh[2][2];  // [re/im][q]
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          if (!IM && u) continue;
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
-            ah[u][q] = As[u][kr][wm * 32 + q * 16 + (lane & 15)];
-            bh[u][q] = Bs[u][kr][wn * 32 + q * 16 + (lane & 15)];
+            ah[buf][u][q] = As[u][kr][wm * 32 + q * 16 + (lane & 15)];
+            bh[buf][u][q] = Bs[u][kr][wn * 32 + q * 16 + (lane & 15)];
           }
-        }
+      };
+      frag(0, 0);
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          if (!IM && u) continue;
+      for (int kk = 0; kk < FTK / 4; ++kk) {
+        const int cur = kk & 1;
+        if (kk + 1 < FTK / 4) frag(kk + 1, cur ^ 1);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma_t(ah[cur][0][bi], bh[cur][0][bj], acc[bi][bj]);
+        if (im) {
 #pragma unroll
           for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma_t(ah[u][bi], bh[u][bj], acc[bi][bj]);
+            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma_t(ah[cur][1][bi], bh[cur][1][bj], acc[bi][bj]);
         }
       }
     }
-  };
-  for (int b = b_lo; b < b_hi; ++b) {
-    const ForceTerm tm = terms[mu * R + b];
-    const double x1 = c1t[2 * tm.coef], y1 = c1t[2 * tm.coef + 1];
-    if (tm.Yi != nullptr) run_term(tm, x1, y1, std::true_type{});
-    else run_term(tm, x1, y1, std::false_type{});
   }
 
   // ---- total, skew write-out ----
@@ -209,6 +211,148 @@ __global__ __launch_bounds__(256) void k_force(int n, int R, int T, const ForceT
     __syncthreads();
     for (int e = tid; e < 64 * 64; e += 256) {
       const int li = e >> 6, lj = e & 63;
+      const int gi = row0 + li, gj = col0 + lj;
+      if (gi < n && gj < n) out[(long long)gi * n + gj] = 0.5 * (Tt[li][lj] - Tt[lj][li]);
+    }
+  }
+}
+
+// The FP32 products with 80 x 80 output tiles, for n where they waste less
+// padding than 64 x 64 ones (n = 400 and 800 are multiples of 80: 15 and 55
+// upper tiles per state instead of 28 and 91 of 64, 16% and 6% fewer
+// matrix-core operations).  Five waves per workgroup, each owning a 16-row
+// strip of the tile (1 x 5 MFMA blocks): a wave reads its own A rows and
+// every B column from LDS.  Grid, XCD mapping, term split and write-out as
+// in k_force.  (At n = 400, R = 16: 0.72 ms instead of 0.96.  The float64
+// instance needs 190 VGPRs, one workgroup per CU, or stalls on LDS when held
+// to three waves per SIMD: 2.06 ms instead of 1.15, so float64 keeps the
+// 64 x 64 kernel.)
+constexpr int FS_T = 80;             // tile edge
+constexpr int FS_W = FS_T / 16;      // waves per workgroup
+constexpr int FS_LP = FS_T + 1;      // LDS pitch
+constexpr int FS_THREADS = 64 * FS_W;
+
+template <typename TT>
+__global__ __launch_bounds__(FS_THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_force_strip(int n, int R, int T, const ForceTerm* __restrict__ terms,
+                                                          const double* __restrict__ coef,
+                                                          double* __restrict__ dG, double* __restrict__ dP,
+                                                          unsigned long long* __restrict__ nrm) {
+  typedef typename Vec4<TT>::type V4;
+  constexpr size_t stage_bytes = 2 * 2 * FTK * FS_LP * sizeof(TT);
+  constexpr size_t tt_bytes = FS_T * FS_LP * sizeof(double);
+  __shared__ __attribute__((aligned(16))) char lds_raw[stage_bytes > tt_bytes ? stage_bytes : tt_bytes];
+  typedef TT Slab[FTK][FS_LP];
+  Slab* As = (Slab*)lds_raw;      // As[part]
+  Slab* Bs = (Slab*)lds_raw + 2;  // Bs[part]
+  double (*Tt)[FS_LP] = (double (*)[FS_LP])lds_raw;
+
+  const int ntri = T * (T + 1) / 2;
+  const int xcd = blockIdx.x & 7, loc2 = blockIdx.x >> 3;
+  const int split = loc2 % FORCE_SPLIT, loc = loc2 / FORCE_SPLIT;
+  const int mu = xcd + 8 * (loc / ntri);
+  if (mu >= R) return;
+  const int b_lo = split * R / FORCE_SPLIT, b_hi = (split + 1) * R / FORCE_SPLIT;
+  if (loc % ntri == 0 && split == 0 && threadIdx.x == 0) nrm[mu] = 0ull;  // k_force_join accumulates it
+  int tri = loc % ntri, I = 0;
+  while (tri >= T - I) { tri -= T - I; ++I; }
+  const int J = I + tri;
+  const int row0 = I * FS_T, col0 = J * FS_T;
+  const long long nn = (long long)n * n;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  V4 acc[FS_W];
+#pragma unroll
+  for (int j = 0; j < FS_W; ++j) acc[j] = V4{0, 0, 0, 0};
+
+  const double* c1t = coef;
+  // A slab: rows row0 .. +79, k kc .. kc+15 (thread: row tid >> 2, 4 consecutive k)
+  const int a_i = tid >> 2, a_k = (tid & 3) * 4;
+  // B slab: k kc .. kc+15, columns col0 .. +79 (thread: column tid % 80, 4 rows)
+  const int b_k = (tid / FS_T) * 4, b_j = tid % FS_T;
+
+  auto run_term = [&](const ForceTerm& tm, double x1, double y1, auto im_tag) {
+    constexpr bool IM = decltype(im_tag)::value;
+    const double sg = tm.sgn, ds = tm.dr_scale;
+    const SGS_GLOBAL double* __restrict__ Yr = as_global(tm.Yr);
+    const SGS_GLOBAL double* __restrict__ Yi = as_global(IM ? tm.Yi : tm.Yr);
+    const SGS_GLOBAL double* __restrict__ Dr = as_global(tm.Dr);
+    const SGS_GLOBAL double* __restrict__ Di = as_global(IM ? tm.Di : tm.Dr);
+    double ra[2][4], rd[2][4];
+    auto load = [&](int kc) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = row0 + a_i, gk = kc + a_k + r;
+        const bool ok = gi < n && gk < n;
+        const long long o = (long long)gi * n + gk;
+        ra[0][r] = ok ? Yr[o] : 0.0;
+        ra[1][r] = (IM && ok) ? Yi[o] : 0.0;
+        const int gk2 = kc + b_k + r, gj = col0 + b_j;
+        const bool okb = gk2 < n && gj < n;
+        const long long ob = (long long)gk2 * n + gj;
+        rd[0][r] = okb ? Dr[ob] : 0.0;
+        rd[1][r] = (IM && okb) ? Di[ob] : 0.0;
+      }
+    };
+    load(0);
+    for (int kc = 0; kc < n; kc += FTK) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double dr = ds * rd[0][r], di = sg * rd[1][r];
+        As[0][a_k + r][a_i] = (TT)ra[0][r];
+        Bs[0][b_k + r][b_j] = (TT)(x1 * dr - y1 * di);
+        if (IM) {
+          As[1][a_k + r][a_i] = (TT)(sg * ra[1][r]);
+          Bs[1][b_k + r][b_j] = (TT)(-(x1 * di + y1 * dr));
+        }
+      }
+      __syncthreads();
+      if (kc + FTK < n) load(kc + FTK);
+#pragma unroll
+      for (int kk = 0; kk < FTK / 4; ++kk) {
+        const int kr = kk * 4 + (lane >> 4);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          if (!IM && u) continue;
+          const TT ah = As[u][kr][w * 16 + (lane & 15)];
+          TT bh[FS_W];
+#pragma unroll
+          for (int bj = 0; bj < FS_W; ++bj) bh[bj] = Bs[u][kr][bj * 16 + (lane & 15)];
+#pragma unroll
+          for (int bj = 0; bj < FS_W; ++bj) acc[bj] = mfma_t(ah, bh[bj], acc[bj]);
+        }
+      }
+    }
+  };
+  for (int b = b_lo; b < b_hi; ++b) {
+    const ForceTerm tm = terms[mu * R + b];
+    const double x1 = c1t[2 * tm.coef], y1 = c1t[2 * tm.coef + 1];
+    if (tm.Yi != nullptr) run_term(tm, x1, y1, std::true_type{});
+    else run_term(tm, x1, y1, std::false_type{});
+  }
+
+  // ---- total, skew write-out ----
+  __syncthreads();
+  double* out = (split == 0 ? dG : dP + (long long)(split - 1) * R * nn) + (long long)mu * nn;
+#pragma unroll
+  for (int bj = 0; bj < FS_W; ++bj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int li = w * 16 + acc_row<TT>(lane, r);
+      const int lj = bj * 16 + (lane & 15);
+      const int gi = row0 + li, gj = col0 + lj;
+      double v = 0.0;
+      if (gi < n && gj < n) v = (double)acc[bj][r];
+      if (I == J) Tt[li][lj] = v;
+      else if (gi < n && gj < n) {
+        out[(long long)gi * n + gj] = v;
+        out[(long long)gj * n + gi] = -v;
+      }
+    }
+  if (I == J) {
+    __syncthreads();
+    for (int e = tid; e < FS_T * FS_T; e += FS_THREADS) {
+      const int li = e / FS_T, lj = e % FS_T;
       const int gi = row0 + li, gj = col0 + lj;
       if (gi < n && gj < n) out[(long long)gi * n + gj] = 0.5 * (Tt[li][lj] - Tt[lj][li]);
     }
@@ -349,11 +493,23 @@ __global__ __launch_bounds__(256) void k_force_join(double* __restrict__ dG, con
     atomicMax(nrm + mu, (unsigned long long)__double_as_longlong(fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))));
 }
 
+// upper-triangle tiles of edge e that cover n, times the tile area
+static long long force_area(int n, int e) {
+  const long long t = (n + e - 1) / e;
+  return t * (t + 1) / 2 * e * e;
+}
+
 hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, double* dG, double* dP,
                         unsigned long long* nrm, int mode, hipStream_t s) {
+  const int per_xcd = (R + 7) / 8;
+  if (mode == FORCE_FP32 && force_area(n, FS_T) < force_area(n, 64)) {
+    const int T = (n + FS_T - 1) / FS_T;
+    const dim3 grid(8 * per_xcd * (T * (T + 1) / 2) * FORCE_SPLIT), block(FS_THREADS);
+    hipLaunchKernelGGL((k_force_strip<float>), grid, block, 0, s, n, R, T, terms, coef, dG, dP, nrm);
+    return hipGetLastError();
+  }
   const int T = (n + 63) / 64;
   const int ntri = T * (T + 1) / 2;
-  const int per_xcd = (R + 7) / 8;
   const dim3 grid(8 * per_xcd * ntri * FORCE_SPLIT), block(256);
   if (mode == FORCE_FP64)
     hipLaunchKernelGGL((k_force<double>), grid, block, 0, s, n, R, T, terms, coef, dG, dP, nrm);
