@@ -29,7 +29,7 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 # counters on this workload (FETCH_SIZE scaled by 2.0, WRITE_SIZE by 1.0: the
 # factors a 1 GiB device copy reads back).  Only valid for the kernel and
 # workload it was taken on; any other combination reports null.
-FORCE_TRAFFIC_BYTES = {("anderson_L99_R16", "fp64"): 2.184e9}
+FORCE_TRAFFIC_BYTES = {("anderson_L99_R16", "fp64"): 2.666e9}
 
 
 def force_flops(n: int, R: int) -> float:
