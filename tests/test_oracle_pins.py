@@ -370,3 +370,68 @@ def test_exp_update_descends_and_reaches_ground_state():
     _, es = sgs.run(ham, si.random_states(N, 3, seed=5), 0.05, 300, update="exp")
     assert np.all(np.diff(es) <= 1e-12)
     assert es[-1] == pytest.approx(e_ed, abs=1e-10)
+
+
+# ---------------------------------------------------------------- variance
+
+def _bruteforce_moments(ham, g, lam):
+    """<H>, <H^2> of sum_mu lambda_mu |phi_mu> built in Fock space (same gauge as G)."""
+    vecs = fock.fix_gauge([fock.gaussian_state(x) for x in g], fock.gaussian_state(g[0]))
+    vecs = fock.fix_gauge(vecs, vecs[0])
+    psi = np.stack(vecs, 1) @ lam
+    H = fock.majorana_poly_operator(ham.N, ham.poly())
+    nr = np.vdot(psi, psi).real
+    hp = H @ psi
+    return np.vdot(psi, hp).real / nr, np.vdot(hp, hp).real / nr
+
+
+@pytest.mark.parametrize("model,R", [("anderson", 1), ("anderson", 3), ("tck", 2), ("tck", 3)])
+def test_variance_definition_matches_bruteforce(model, R):
+    """Eq. (residual): delta_H^2 = <H^2> - <H>^2 from H^2 multiplied out as
+    Majorana words equals the Fock-space value (Anderson N = 4, two-channel
+    Kondo N = 6, random states)."""
+    ham = si.anderson(1, 1.3, 0.7) if model == "anderson" else si.two_channel_kondo(1, 0.9, U=2.0)
+    g = si.random_states(ham.N, R, seed=5 + R)
+    E, lam, tab = sgs.energy(ham, g)
+    e1, e2, var = ob.hamiltonian_variance(ham, g, lam, tab.G)
+    b1, b2 = _bruteforce_moments(ham, g, lam)
+    assert abs(e1 - E) < 1e-12 * max(1.0, abs(E))
+    assert abs(e1 - b1) < 1e-12 * max(1.0, abs(b1))
+    assert abs(e2 - b2) < 1e-12 * max(1.0, abs(b2))
+    assert abs(var - (b2 - b1 * b1)) < 1e-11 * max(1.0, b2)
+    assert var > 0.0
+
+
+@pytest.mark.parametrize("model", ["anderson", "tck"])
+def test_variance_trace_form_matches_definition(model):
+    """The matrix form (K = 1 + i Delta, <H2 H2>_t = <H2>_t^2 + Tr(alpha K
+    alpha K^T) / 2, Pfaffians of 6 and 8 Majoranas for the quartic words)
+    against the word expansion, n = 16 and 12, R = 3."""
+    ham = si.anderson(3, 1.3, 0.7) if model == "anderson" else si.two_channel_kondo(1, 0.9, U=2.0)
+    g = si.random_states(ham.N, 3, seed=2)
+    E, lam, tab = sgs.energy(ham, g)
+    a = ob.hamiltonian_variance(ham, g, lam, tab.G)
+    b = ob.hamiltonian_variance_trace(ham, g, lam, tab.G)
+    assert abs(a[0] - b[0]) < 1e-12 * max(1.0, abs(a[0]))
+    assert abs(a[1] - b[1]) < 1e-12 * max(1.0, abs(a[1]))
+    assert abs(a[2] - b[2]) < 1e-11 * max(1.0, a[1])
+
+
+def test_variance_vanishes_on_an_eigenstate():
+    """A quadratic H (U = 0) has the Gaussian ground state Gamma = -i sign(iA):
+    delta_H^2 = 0 there (both forms), and > 0 on a random state."""
+    ham = si.anderson(3, 0.0, 0.7)
+    assert ham.quartic_idx.shape[0] == 0 or np.all(ham.quartic_val == 0.0)
+    w, v = np.linalg.eigh(1j * ham.A)
+    gam = (-1j * (v * np.sign(w)) @ v.conj().T).real
+    gam = 0.5 * (gam - gam.T)
+    assert np.abs(gam @ gam + np.eye(ham.n)).max() < 1e-12
+    g = gam[None]
+    lam = np.array([1.0 + 0.0j])
+    G = np.ones((1, 1), dtype=complex)
+    e1, e2, var = ob.hamiltonian_variance(ham, g, lam, G)
+    t1, t2, tvar = ob.hamiltonian_variance_trace(ham, g, lam, G)
+    assert abs(var) < 1e-12 * e2 and abs(tvar) < 1e-12 * t2
+    assert abs(e1 - (ham.e0 - 0.5 * np.abs(2 * w).sum())) < 1e-12 * max(1.0, abs(e1))
+    rnd = si.random_states(ham.N, 1, seed=4)
+    assert ob.hamiltonian_variance(ham, rnd, lam, G)[2] > 1e-3
