@@ -137,6 +137,24 @@ def main(argv=None):
     if ctx.status() != 0:
         raise SystemExit("device status error in sgs_pair_eval")
 
+    # the variance of H (Eq. residual) of the current states: the tables are
+    # current after sgs_pair_eval, so each call times the variance kernels only
+    from paper_2105_01088_amd import SGS_OBS_VARIANCE
+    vout = ctx.observables(SGS_OBS_VARIANCE, [0], [], 3)
+    torch.cuda.synchronize()
+    v0 = torch.cuda.Event(enable_timing=True)
+    v1 = torch.cuda.Event(enable_timing=True)
+    nvar = 5
+    v0.record(stream)
+    for _ in range(nvar):
+        vout = ctx.observables(SGS_OBS_VARIANCE, [0], [], 3)
+    v1.record(stream)
+    torch.cuda.synchronize()
+    ms_var = v0.elapsed_time(v1) / nvar
+    var = vout.cpu().numpy()
+    if ctx.status() != 0:
+        raise SystemExit("device status error in the variance")
+
     ms_step = ms_total / args.steps
     value = P * args.steps / (ms_total / 1e3)
     f_ms, f_n = stages["force"]
@@ -175,6 +193,7 @@ def main(argv=None):
             "force_flops_per_launch": force_flops(n, R),
         },
         "pair_eval": {"ms_per_call": ms_pe, "pair_evals_per_s": P / (ms_pe / 1e3)},
+        "variance": {"ms_per_call": ms_var, "E": float(var[0]), "H2": float(var[1]), "delta_H2": float(var[2])},
         "stages_ms_per_step": {k: v[0] / max(1, args.steps) for k, v in stages.items()},
         "wall_s": wall,
         "host_enqueue_ms_per_step": host_enqueue * 1e3 / args.steps,

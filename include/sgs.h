@@ -83,6 +83,7 @@ extern "C" {
 /* sgs_observables kinds */
 #define SGS_OBS_POLY 1      /* <psi| O |psi> for Majorana polynomials O        */
 #define SGS_OBS_RENYI2 2    /* S_2 = -ln Tr rho_A^2, Eq. (S2_SGS)              */
+#define SGS_OBS_VARIANCE 3  /* <H>, <H^2>, delta_H^2 of Eq. (residual)         */
 
 typedef struct sgs_ctx sgs_ctx; /* opaque */
 
@@ -183,6 +184,13 @@ int sgs_energy(sgs_ctx* ctx, double* E, double* lambda);
  *                   Majoranas 0..nA-1 (2 <= nA <= 32); dargs unused;
  *                   out (device) = 1 double, S_2 = -ln Tr rho_A^2
  *                   (Eq. S2_SGS, App. B; R^4 Pfaffians of order 2 nA).
+ *   SGS_OBS_VARIANCE: iargs = {problem}; dargs unused; out (device) =
+ *                   3 doubles {<H>, <H^2>, delta_H^2 = <H^2> - <H>^2} of the
+ *                   problem's Hamiltonian (Eq. residual, Sec. IV.A), by
+ *                   Wick's theorem on every transition operator: the
+ *                   quadratic part in matrix form (O(n^2 nnz(A)/n) per pair
+ *                   of states), products with quartic words as Pfaffians of
+ *                   6 and 8 Majoranas.  R <= 32.
  * Errors: SGS_EINVAL (kind, sizes, indices), SGS_EHIP. */
 int sgs_observables(sgs_ctx* ctx, int32_t kind, const int32_t* iargs,
                     int32_t niargs, const double* dargs, int32_t ndargs,

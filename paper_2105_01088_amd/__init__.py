@@ -20,4 +20,5 @@ from ._lib import (  # noqa: F401
     SGS_UPD_EXP,
     SGS_OBS_POLY,
     SGS_OBS_RENYI2,
+    SGS_OBS_VARIANCE,
 )

@@ -24,6 +24,7 @@ SGS_UPD_EULER = 0
 SGS_UPD_EXP = 1
 SGS_OBS_POLY = 1
 SGS_OBS_RENYI2 = 2
+SGS_OBS_VARIANCE = 3
 STAGES = ("inverse", "delta", "wick", "phase", "pfaffian", "solve", "force", "purify")
 
 
@@ -220,6 +221,11 @@ class SGS:
         iargs[2] = nterm
         out = self.observables(SGS_OBS_POLY, iargs, dargs, 2 * len(polys)).cpu().numpy()
         return out[0::2] + 1j * out[1::2]
+
+    def variance(self, problem: int = 0):
+        """(<H>, <H^2>, delta_H^2) of the current SGS state (Eq. residual)."""
+        v = self.observables(SGS_OBS_VARIANCE, [int(problem)], [], 3).cpu().numpy()
+        return float(v[0]), float(v[1]), float(v[2])
 
     def renyi2(self, nA: int, problem: int = 0) -> float:
         """S_2 = -ln Tr rho_A^2 of the current state, A = Majoranas 0..nA-1."""

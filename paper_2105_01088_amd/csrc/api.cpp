@@ -182,6 +182,7 @@ struct ObsBuf {
   double* coef = nullptr;
   int* off = nullptr;
   double* part = nullptr;
+  double* vpart = nullptr;  // variance partial sums, R^2 x VAR_CHUNKS x 6 complex
 };
 
 // One stream of independent problems.  Worker 0 runs on the context's
@@ -420,6 +421,7 @@ static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, c
     o.coef = ar.take<double>(2 * (size_t)OBS_MAX_TERMS);
     o.off = ar.take<int>((size_t)OBS_MAX_POLY + 1);
     o.part = ar.take<double>(2 * 32 * 32);
+    o.vpart = ar.take<double>((size_t)32 * 32 * VAR_CHUNKS * 12);
     if (ob) *ob = o;
   }
   pr.assign(nprob, Prob());
@@ -1121,6 +1123,15 @@ int sgs_observables(sgs_ctx* c, int32_t kind, const int32_t* iargs, int32_t niar
     if (launch_obs_poly(s, c->obs.rows, c->obs.coef, c->obs.off, npoly, out, c->s) != hipSuccess) return SGS_EHIP;
     // the host vectors must outlive the copies
     if (hipStreamSynchronize(c->s) != hipSuccess) return SGS_EHIP;
+    return SGS_OK;
+  }
+  if (kind == SGS_OBS_VARIANCE) {
+    if (niargs != 1) return SGS_EINVAL;
+    if (q.R > 32) return SGS_EINVAL;
+    if (ensure_tables(c, p) != hipSuccess) return SGS_EHIP;
+    ObsState s{n, q.R, q.gam, q.W, q.Di, q.lam, q.Gt, q.pidx};
+    VarHam h{q.Adense, q.nnz_up, q.up_k, q.up_l, q.up_v, q.colptr, q.rowidx, q.colval, q.nq, q.q_idx, q.q_val};
+    if (launch_variance(s, h, q.e0, c->obs.vpart, out, c->s) != hipSuccess) return SGS_EHIP;
     return SGS_OK;
   }
   if (kind == SGS_OBS_RENYI2) {

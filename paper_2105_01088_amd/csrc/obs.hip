@@ -12,6 +12,17 @@
 // (Delta^{aa} = Gamma_a), and the trace of a product of two such operators on
 // N_A = nA / 2 modes is 2^{-N_A} Pf([[D_1, i 1], [-i 1, D_2]]).
 //
+// Variance of the Hamiltonian, Eq. (residual): delta_H^2 = <H^2> - <H>^2.
+// On the transition operator of a pair Wick's theorem holds for any product
+// with the two-point matrix K = 1 + i Delta (K_kl = <c_k c_l>_t, K_kk = 1).
+// With H = e0 + H2 + H4, H2 = sum_{k<l} alpha_kl c_k c_l (alpha = 2 i A) and
+// H4 = sum_q u_q c_q0 c_q1 c_q2 c_q3 (Sec. II.A):
+//   <H2>_t = -2 sum_{k<l} A_kl Delta_kl,
+//   <H2 H2>_t = <H2>_t^2 + (1/2) Tr(alpha K alpha K^T)
+//             = <H2>_t^2 + Tr(T alpha) - (1/2) Tr(T T),  T = alpha K
+//   (K^T = 2 - K), and every product with a quartic word is the Pfaffian of
+// the contraction matrix of its 6 or 8 Majoranas (M_ab = K_{i_a i_b}, a < b).
+//
 // Storage: the pair p = (a < b) keeps W = (Gamma_a + Gamma_b)^{-1} and
 // Im Delta^{ba}; Delta^{ba} = -2 W + i Im, Delta^{ab} = its conjugate.
 #include "sgs_internal.h"
@@ -200,6 +211,185 @@ __global__ void k_renyi2_final(const double* __restrict__ part, int count, doubl
   double s = 0.0;
   for (int t = 0; t < count; ++t) s += part[2 * t];
   out[0] = -log(s);
+}
+
+// ---- variance of H ----
+
+__device__ __forceinline__ cd cadd(cd a, cd b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ cd csub(cd a, cd b) { return {a.r - b.r, a.i - b.i}; }
+
+// K_ij = <c_i c_j>_t of the transition matrix Delta^{xy}
+__device__ __forceinline__ cd kval(const ObsState& s, int x, int y, int i, int j) {
+  if (i == j) return {1.0, 0.0};
+  const cd d = delta_at(s, x, y, i, j);
+  return {-d.i, d.r};
+}
+
+// Pfaffians of the contraction matrix M (upper entries M[a][b], a < b) of an
+// ordered product, by expansion along the first index
+__device__ cd pf4p(const cd (&M)[8][8], int a, int b, int c, int d) {
+  return cadd(csub(cmul(M[a][b], M[c][d]), cmul(M[a][c], M[b][d])), cmul(M[a][d], M[b][c]));
+}
+__device__ cd pf6p(const cd (&M)[8][8], const int* p) {
+  cd r{0.0, 0.0};
+#pragma unroll
+  for (int j = 1; j < 6; ++j) {
+    int q[4], t = 0;
+#pragma unroll
+    for (int x = 1; x < 6; ++x)
+      if (x != j) q[t++] = p[x];
+    const cd v = cmul(M[p[0]][p[j]], pf4p(M, q[0], q[1], q[2], q[3]));
+    r = (j & 1) ? cadd(r, v) : csub(r, v);
+  }
+  return r;
+}
+__device__ cd pf8p(const cd (&M)[8][8]) {
+  cd r{0.0, 0.0};
+  for (int j = 1; j < 8; ++j) {
+    int q[6], t = 0;
+    for (int x = 1; x < 8; ++x)
+      if (x != j) q[t++] = x;
+    const cd v = cmul(M[0][j], pf6p(M, q));
+    r = (j & 1) ? cadd(r, v) : csub(r, v);
+  }
+  return r;
+}
+// <c_i0 ... c_i(m-1)>_t, m = 4, 6, 8
+__device__ cd wick_product(const ObsState& s, int x, int y, const int* idx, int m) {
+  cd M[8][8];
+  for (int a = 0; a < m; ++a)
+    for (int b = a + 1; b < m; ++b) M[a][b] = kval(s, x, y, idx[a], idx[b]);
+  if (m == 4) return pf4p(M, 0, 1, 2, 3);
+  if (m == 6) {
+    const int p[6] = {0, 1, 2, 3, 4, 5};
+    return pf6p(M, p);
+  }
+  return pf8p(M);
+}
+
+// grid: (R * R blocks (mu, b), VAR_CHUNKS), 256 threads.  Block (mu, b)
+// works on Delta^{b mu}; its chunk writes six complex partial sums to
+// part[((mu R + b) VAR_CHUNKS + chunk) 12 ..]: Tr(T T), Tr(T alpha), <H2>_t,
+// <H4>_t, <H2 H4 + H4 H2>_t, <H4 H4>_t.
+__global__ __launch_bounds__(256) void k_var_part(ObsState s, VarHam h, double* __restrict__ part) {
+  __shared__ cd red[256];
+  const int n = s.n, R = s.R;
+  const int mb = blockIdx.x, ch = blockIdx.y;
+  const int mu = mb / R, b = mb % R;
+  const int x = b, y = mu;  // Delta^{b mu}
+  const int stride = VAR_CHUNKS * blockDim.x;
+  const int t0 = ch * blockDim.x + threadIdx.x;
+  cd trtt{0.0, 0.0}, trta{0.0, 0.0}, h2{0.0, 0.0}, h4{0.0, 0.0}, hx{0.0, 0.0}, h44{0.0, 0.0};
+  // T_ij = 2 i A_ij - 2 (A Delta)_ij = 2 i A_ij + 2 sum_{k in column i} A_ki Delta_kj (A skew)
+  auto tval = [&](int i, int j) -> cd {
+    cd v{0.0, 2.0 * h.Ad[(long long)i * n + j]};
+    for (int q = h.colptr[i]; q < h.colptr[i + 1]; ++q) {
+      const cd d = delta_at(s, x, y, h.rowidx[q], j);
+      const double a = 2.0 * h.colval[q];
+      v.r += a * d.r;
+      v.i += a * d.i;
+    }
+    return v;
+  };
+  for (long long e = t0; e < (long long)n * n; e += stride) {
+    const int i = (int)(e / n), j = (int)(e - (long long)i * n);
+    if (i > j) continue;
+    const cd tij = tval(i, j);
+    if (i == j) {
+      trtt = cadd(trtt, cmul(tij, tij));
+    } else {
+      const cd tji = tval(j, i);
+      const cd pr = cmul(tij, tji);
+      trtt.r += 2.0 * pr.r;
+      trtt.i += 2.0 * pr.i;
+      // T_ij alpha_ji + T_ji alpha_ij = 2 i A_ij (T_ji - T_ij)
+      trta = cadd(trta, cmul(cd{0.0, 2.0 * h.Ad[(long long)i * n + j]}, csub(tji, tij)));
+    }
+  }
+  // <H2>_t = sum_{k<l} alpha_kl K_kl = -2 sum_{k<l} A_kl Delta_kl
+  for (int u = t0; u < h.nnz_up; u += stride) {
+    const cd d = delta_at(s, x, y, h.up_k[u], h.up_l[u]);
+    h2.r -= 2.0 * h.up_v[u] * d.r;
+    h2.i -= 2.0 * h.up_v[u] * d.i;
+  }
+  for (int q = t0; q < h.nq; q += stride) {
+    const cd v = wick_product(s, x, y, h.q_idx + 4 * q, 4);
+    h4.r += h.q_val[q] * v.r;
+    h4.i += h.q_val[q] * v.i;
+  }
+  // quadratic x quartic, both orders: alpha_kl u_q (<c_k c_l w_q> + <w_q c_k c_l>)
+  for (long long e = t0; e < (long long)h.nnz_up * h.nq; e += stride) {
+    const int u = (int)(e / h.nq), q = (int)(e - (long long)u * h.nq);
+    const int* w = h.q_idx + 4 * q;
+    const int k = h.up_k[u], l = h.up_l[u];
+    const int i1[6] = {k, l, w[0], w[1], w[2], w[3]};
+    const int i2[6] = {w[0], w[1], w[2], w[3], k, l};
+    const cd v = cadd(wick_product(s, x, y, i1, 6), wick_product(s, x, y, i2, 6));
+    const cd c = cmul(cd{0.0, 2.0 * h.up_v[u]}, cd{h.q_val[q], 0.0});
+    hx = cadd(hx, cmul(c, v));
+  }
+  for (int e = t0; e < h.nq * h.nq; e += stride) {
+    const int q1 = e / h.nq, q2 = e - q1 * h.nq;
+    int i8[8];
+    for (int a = 0; a < 4; ++a) { i8[a] = h.q_idx[4 * q1 + a]; i8[4 + a] = h.q_idx[4 * q2 + a]; }
+    const cd v = wick_product(s, x, y, i8, 8);
+    const double c = h.q_val[q1] * h.q_val[q2];
+    h44.r += c * v.r;
+    h44.i += c * v.i;
+  }
+  const cd sums[6] = {block_sum(trtt, red), block_sum(trta, red), block_sum(h2, red),
+                      block_sum(h4, red), block_sum(hx, red), block_sum(h44, red)};
+  if (threadIdx.x == 0) {
+    double* o = part + ((long long)mb * VAR_CHUNKS + ch) * 12;
+    for (int k = 0; k < 6; ++k) { o[2 * k] = sums[k].r; o[2 * k + 1] = sums[k].i; }
+  }
+}
+
+// one workgroup: per block (mu, b) <H'>_t = <H2>_t + <H4>_t and
+// <H'^2>_t = <H2>_t^2 + Tr(T alpha) - Tr(T T) / 2 + <H2 H4 + H4 H2>_t + <H4 H4>_t
+// (H' = H - e0), weighted by lambda_mu^* lambda_b G_{mu b}; out = {<H>, <H^2>,
+// delta_H^2}, normalized by sum lambda_mu^* lambda_b G_{mu b}
+__global__ __launch_bounds__(256) void k_var_final(ObsState s, const double* __restrict__ part, double e0,
+                                                   double* __restrict__ out) {
+  __shared__ cd red[256];
+  const int R = s.R;
+  cd s1{0.0, 0.0}, s2{0.0, 0.0}, nr{0.0, 0.0};
+  for (int mb = threadIdx.x; mb < R * R; mb += blockDim.x) {
+    cd v[6];
+    for (int k = 0; k < 6; ++k) v[k] = {0.0, 0.0};
+    for (int ch = 0; ch < VAR_CHUNKS; ++ch) {
+      const double* o = part + ((long long)mb * VAR_CHUNKS + ch) * 12;
+      for (int k = 0; k < 6; ++k) { v[k].r += o[2 * k]; v[k].i += o[2 * k + 1]; }
+    }
+    const cd X = cadd(v[2], v[3]);
+    cd Y = cmul(v[2], v[2]);
+    Y = cadd(Y, v[1]);
+    Y = csub(Y, cd{0.5 * v[0].r, 0.5 * v[0].i});
+    Y = cadd(cadd(Y, v[4]), v[5]);
+    const int mu = mb / R, b = mb % R;
+    const cd c = cmul(cmul(cconj(lam_at(s, mu)), lam_at(s, b)), g_at(s, mu, b));
+    s1 = cadd(s1, cmul(c, X));
+    s2 = cadd(s2, cmul(c, Y));
+    nr = cadd(nr, c);
+  }
+  const cd S1 = block_sum(s1, red), S2 = block_sum(s2, red), N = block_sum(nr, red);
+  if (threadIdx.x == 0) {
+    const double d = N.r * N.r + N.i * N.i;
+    const cd inv{N.r / d, -N.i / d};
+    const cd x = cmul(S1, inv), yv = cmul(S2, inv);
+    const cd xx = cmul(x, x);
+    out[0] = e0 + x.r;
+    out[1] = e0 * e0 + 2.0 * e0 * x.r + yv.r;
+    out[2] = yv.r - xx.r;
+  }
+}
+
+hipError_t launch_variance(const ObsState& s, const VarHam& h, double e0, double* part, double* out,
+                           hipStream_t st) {
+  if (s.R < 1 || s.R > 32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_var_part, dim3(s.R * s.R, VAR_CHUNKS), dim3(256), 0, st, s, h, part);
+  hipLaunchKernelGGL(k_var_final, dim3(1), dim3(256), 0, st, s, (const double*)part, e0, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_obs_poly(const ObsState& s, const int* rows, const double* coef, const int* off, int npoly,

@@ -197,6 +197,24 @@ struct ObsState {
   const double* Gt;   // R x R complex overlaps
   const int* pidx;    // R x R pair index
 };
+// Hamiltonian tables for the variance of H (obs.hip): dense A, its upper
+// nonzeros, its compressed columns, the quartic words
+struct VarHam {
+  const double* Ad;
+  int nnz_up;
+  const int* up_k;
+  const int* up_l;
+  const double* up_v;
+  const int* colptr;
+  const int* rowidx;
+  const double* colval;
+  int nq;
+  const int* q_idx;
+  const double* q_val;
+};
+constexpr int VAR_CHUNKS = 16;  // workgroups per transition block
+hipError_t launch_variance(const ObsState& s, const VarHam& h, double e0, double* part, double* out,
+                           hipStream_t st);
 constexpr int OBS_MAX_NA = 32;      // Renyi-2 subsystem: at most 32 Majoranas
 constexpr int OBS_MAX_TERMS = 16384;
 constexpr int OBS_MAX_POLY = 4096;
