@@ -196,6 +196,20 @@ int sgs_observables(sgs_ctx* ctx, int32_t kind, const int32_t* iargs,
                     int32_t niargs, const double* dargs, int32_t ndargs,
                     double* out);
 
+/* Rank growing (Sec. III.C): the state added to the ansatz is a random
+ * special orthogonal transformation Q, close to the identity, of a state of
+ * high amplitude.  gamma_out = Q gamma Q^T, made exactly skew.
+ *   Q, gamma  : device, n x n float64, row-major (Q orthogonal, gamma a pure
+ *               covariance matrix; neither is checked)
+ *   work      : device, n*n float64 scratch owned by the caller
+ *   gamma_out : device, n x n; must not overlap gamma or work
+ *   stream    : hipStream_t the work is enqueued on (NULL: the null stream);
+ *               returns without waiting.
+ * Needs no context.  Errors: SGS_EINVAL (null pointer, n odd or outside
+ * 2..8192), SGS_EHIP. */
+int sgs_rotate(const double* Q, const double* gamma, double* work, double* gamma_out, int32_t n,
+               void* stream);
+
 /* Wait for the context's stream and return the device status word:
  * SGS_OK, SGS_ESINGULAR, SGS_ENOCONV or SGS_ERANGE (first failure since the last call;
  * reading it clears it), or SGS_EHIP. */

@@ -21,6 +21,10 @@ covariance-matrix step):
    Alternative (App. A, Eq. ExpStep): the orthogonal update R Gamma R^T with
    R the matrix exponential of a multiple of [Gamma, dGamma] (scipy's expm),
    with the coefficient read so that its first-order term is the Euler step.
+
+Rank growing (Sec. III.C, ``grow``): from one state, run steps, then add a
+random special orthogonal transformation (close to 1) of the state of
+largest amplitude, and repeat.
 """
 
 from __future__ import annotations
@@ -179,3 +183,26 @@ def run(ham, gammas: np.ndarray, dtau: float, nsteps: int, mode: str = "printed"
         if callback is not None:
             callback(k, r)
     return g, np.array(es)
+
+
+def grow(ham, gamma0: np.ndarray, dtau: float, steps_per_rank: int, rotations, mode: str = "printed",
+         update: str = "euler") -> tuple:
+    """Rank-growing protocol of Sec. III.C: steps_per_rank steps from the
+    starting state(s); then, per rotation Q, add Q Gamma_a Q^T for the state a
+    of largest |lambda_a| and run steps_per_rank more steps.  Returns
+    (final gammas, energies of the states entering every step, rank of every
+    step)."""
+    g = gamma0[None] if gamma0.ndim == 2 else gamma0
+    es: List[float] = []
+    ranks: List[int] = []
+    for r in range(len(rotations) + 1):
+        g, e = run(ham, g, dtau, steps_per_rank, mode, update=update)
+        es.extend(e)
+        ranks.extend([g.shape[0]] * steps_per_rank)
+        if r == len(rotations):
+            break
+        _, lam, _ = energy(ham, g)
+        a = int(np.argmax(np.abs(lam)))
+        new = rotations[r] @ g[a] @ rotations[r].T
+        g = np.concatenate([g, (0.5 * (new - new.T))[None]])
+    return g, np.array(es), ranks

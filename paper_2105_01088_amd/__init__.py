@@ -21,4 +21,6 @@ from ._lib import (  # noqa: F401
     SGS_OBS_POLY,
     SGS_OBS_RENYI2,
     SGS_OBS_VARIANCE,
+    rotate_state,
 )
+from .protocol import grow  # noqa: F401

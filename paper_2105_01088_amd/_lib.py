@@ -73,6 +73,8 @@ def load_library(path: str = LIB_PATH):
     lib.sgs_destroy.restype = None
     lib.sgs_strerror.argtypes = [c_int32]
     lib.sgs_strerror.restype = ctypes.c_char_p
+    lib.sgs_rotate.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
+    lib.sgs_rotate.restype = c_int32
     for f in ("sgs_workspace_bytes", "sgs_init", "sgs_pair_eval", "sgs_step", "sgs_energy",
               "sgs_observables", "sgs_status", "sgs_set_timing", "sgs_stage_times"):
         getattr(lib, f).restype = c_int32
@@ -93,6 +95,23 @@ def default_options(**kw) -> sgs_options:
     for k, v in kw.items():
         setattr(o, k, v)
     return o
+
+
+def rotate_state(Q, gamma, stream=None):
+    """Q gamma Q^T (device tensors, n x n float64) by sgs_rotate, on the given
+    torch stream (default: the current one); returns a new device tensor."""
+    import torch
+
+    lib = load_library()
+    n = int(gamma.shape[-1])
+    Q = Q.to(device=gamma.device, dtype=torch.float64).contiguous()
+    g = gamma.contiguous()
+    work = torch.empty(n * n, dtype=torch.float64, device=gamma.device)
+    out = torch.empty(n, n, dtype=torch.float64, device=gamma.device)
+    st = stream if stream is not None else torch.cuda.current_stream(gamma.device)
+    _check(lib.sgs_rotate(Q.data_ptr(), g.data_ptr(), work.data_ptr(), out.data_ptr(), n, st.cuda_stream),
+           "sgs_rotate")
+    return out
 
 
 def _check(rc: int, what: str):

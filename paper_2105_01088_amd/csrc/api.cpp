@@ -1146,6 +1146,11 @@ int sgs_observables(sgs_ctx* c, int32_t kind, const int32_t* iargs, int32_t niar
   return SGS_EINVAL;
 }
 
+int sgs_rotate(const double* Q, const double* gamma, double* work, double* gamma_out, int32_t n, void* stream) {
+  if (!Q || !gamma || !work || !gamma_out || n < 2 || n > 8192 || (n & 1)) return SGS_EINVAL;
+  return launch_rotate(Q, gamma, work, gamma_out, n, (hipStream_t)stream) == hipSuccess ? SGS_OK : SGS_EHIP;
+}
+
 int sgs_status(sgs_ctx* c) {
   if (!c) return SGS_EINVAL;
   int st = 0;

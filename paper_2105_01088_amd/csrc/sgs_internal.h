@@ -197,6 +197,9 @@ struct ObsState {
   const double* Gt;   // R x R complex overlaps
   const int* pidx;    // R x R pair index
 };
+// Gamma' = Q Gamma Q^T, exactly skew (rotate.hip); work: n*n doubles
+hipError_t launch_rotate(const double* Q, const double* G, double* work, double* out, int n, hipStream_t s);
+
 // Hamiltonian tables for the variance of H (obs.hip): dense A, its upper
 // nonzeros, its compressed columns, the quartic words
 struct VarHam {

@@ -43,3 +43,19 @@ def random_states(N: int, R: int, seed: int = 0,
         g = q @ g0 @ q.T
         out[mu] = 0.5 * (g - g.T)
     return out
+
+
+def small_rotations(n: int, count: int, eps: float, seed: int = 0) -> list:
+    """count seeded special orthogonal n x n matrices Q = exp(eps K / |K|_F)
+    with K a Gaussian random skew matrix, so |Q - 1|_F ~ eps: the
+    transformations that create new states in the rank-growing protocol
+    (Sec. III.C), passed to both the oracle and the GPU driver."""
+    import scipy.linalg
+
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        z = rng.standard_normal((n, n))
+        k = z - z.T
+        out.append(scipy.linalg.expm(eps * k / np.linalg.norm(k)))
+    return out

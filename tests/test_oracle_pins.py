@@ -435,3 +435,39 @@ def test_variance_vanishes_on_an_eigenstate():
     assert abs(e1 - (ham.e0 - 0.5 * np.abs(2 * w).sum())) < 1e-12 * max(1.0, abs(e1))
     rnd = si.random_states(ham.N, 1, seed=4)
     assert ob.hamiltonian_variance(ham, rnd, lam, G)[2] > 1e-3
+
+
+# ------------------------------------------------------------ rank growing
+
+def test_small_rotations_are_special_orthogonal_near_one():
+    for Q in si.small_rotations(12, 3, 0.3, seed=1):
+        assert np.abs(Q @ Q.T - np.eye(12)).max() < 1e-14
+        assert abs(np.linalg.det(Q) - 1.0) < 1e-13
+        assert 0.25 < np.linalg.norm(Q - np.eye(12)) < 0.31
+
+
+def test_grow_reaches_the_exact_ground_state():
+    """Sec. III.C: from one random state (converging to GHF), rank 1 -> 3 by
+    rotated copies of the largest-amplitude state; N = 4 Anderson reaches the
+    exact even-sector ground energy, and never goes below it."""
+    N, terms = si.anderson_terms(1, 1.3, 0.7)
+    ham = si.MajoranaHamiltonian.from_poly(N, si.fermion_terms_to_majorana(terms))
+    g0 = si.random_states(ham.N, 1, seed=3)[0]
+    g, es, ranks = sgs.grow(ham, g0, 0.05, 40, si.small_rotations(ham.n, 2, 0.3, seed=1), mode="unit")
+    ex = ed.even_sector_ground_energy(N, terms)
+    assert g.shape[0] == 3 and ranks == [1] * 40 + [2] * 40 + [3] * 40
+    assert abs(es[-1] - ex) < 1e-6
+    assert es.min() > ex - 1e-10
+
+
+def test_grow_additions_lower_the_energy():
+    """N = 6: every added state lowers the energy at once (the variational
+    space grows), the trajectory decreases, and stays above the exact value."""
+    N, terms = si.anderson_terms(2, 1.3, 0.7)
+    ham = si.MajoranaHamiltonian.from_poly(N, si.fermion_terms_to_majorana(terms))
+    g0 = si.random_states(ham.N, 1, seed=3)[0]
+    g, es, ranks = sgs.grow(ham, g0, 0.05, 40, si.small_rotations(ham.n, 2, 0.3, seed=1), mode="unit")
+    assert np.all(np.diff(es) <= 1e-12)
+    for r in (1, 2):
+        assert es[40 * r] < es[40 * r - 1]
+    assert es[-1] > ed.even_sector_ground_energy(N, terms)
