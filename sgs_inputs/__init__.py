@@ -19,6 +19,7 @@ from .models import (  # noqa: F401
     spin_dot_terms,
     spin_dot_poly,
     siam_mode,
+    wilson_hoppings,
 )
 from .states import vacuum_cm, haar_so, random_states, small_rotations  # noqa: F401
 from .configs import CONFIGS, config_problem, batched_problems  # noqa: F401

@@ -223,6 +223,12 @@ def anderson_terms(L: int, U: float, V: float, t: float = 1.0,
     return N, terms
 
 
+def wilson_hoppings(L_W: int = 20, Lambda: float = 1.2, t: float = 1.0) -> List[float]:
+    """Hoppings t_n = Lambda^-n t, n = 1..L_W, of the tail appended to the bath
+    to reduce finite-size effects (Fig. 4 caption: L_W = 20, Lambda = 1.2)."""
+    return [t * Lambda ** (-k) for k in range(1, L_W + 1)]
+
+
 def anderson(L: int, U: float, V: float, t: float = 1.0, eps_d: float | None = None,
              mu: float = 0.0, wilson_tail: Sequence[float] = ()) -> MajoranaHamiltonian:
     N, terms = anderson_terms(L, U, V, t, eps_d, mu, wilson_tail)

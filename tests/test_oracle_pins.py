@@ -471,3 +471,17 @@ def test_grow_additions_lower_the_energy():
     for r in (1, 2):
         assert es[40 * r] < es[40 * r - 1]
     assert es[-1] > ed.even_sector_ground_energy(N, terms)
+
+
+def test_wilson_tail_hoppings_enter_the_chain():
+    """Fig. 4 caption: L_W = 20 extra sites with t_n = Lambda^-n t, Lambda = 1.2.
+    The last bath bond of the tail couples the last two sites with t_20."""
+    tail = si.wilson_hoppings(20, 1.2)
+    assert len(tail) == 20 and abs(tail[0] - 1 / 1.2) < 1e-15 and abs(tail[-1] - 1.2 ** -20) < 1e-15
+    N, terms = si.anderson_terms(3, 1.0, 0.5, wilson_tail=tail)
+    assert N == 2 * (1 + 3 + 20)
+    hops = {}
+    for c, ops in terms:
+        if len(ops) == 2 and ops[0][1] and not ops[1][1] and ops[0][0] != ops[1][0]:
+            hops[(ops[0][0], ops[1][0])] = c
+    assert abs(hops[(si.siam_mode(22, 0), si.siam_mode(23, 0))] + 1.2 ** -20) < 1e-15
