@@ -46,6 +46,7 @@ struct Prob {
   int gj_nb = 16;
   int worker = 0;  // stream (and scratch region) this problem runs on
   bool expmap = false;  // exponential-map update instead of Euler + purification
+  bool denseA = false;  // A has many nonzeros per column: Y = Delta A by GEMM
   double e0 = 0.0;
   double* gam = nullptr;
   // dense work
@@ -60,6 +61,7 @@ struct Prob {
   int* nsctl;
   ForceTerm* terms;
   JobTable jdi, jt1, jxr, jnsq[2], jnsx[2], jval;
+  JobTable jya;  // dense A: Y_r = -2 W A, Y_i = Im Delta A per pair, Yd = Gamma A per state
   // exponential map: P = Gamma dGamma, Y = K^2, Z = Y^2, the three
   // Paterson-Stockmeyer steps, R = C + K S, squarings, R Gamma, (R Gamma) R^T
   double *ex0 = nullptr, *ex1 = nullptr, *ex2 = nullptr, *ex3 = nullptr, *exrow = nullptr, *expar = nullptr;
@@ -378,6 +380,7 @@ static void carve_jobs(Prob& q, Arena& ar) {
   q.jpf.assign(npf, JobTable());
   for (auto& t : q.jpf) table(t, q.Q);
   table(q.jdi, q.P);
+  table(q.jya, q.denseA ? 2 * q.P + q.R : 0);
   table(q.jt1, q.R - 1);
   table(q.jxr, q.R - 1);
   for (int k = 0; k < 2; ++k) {
@@ -410,6 +413,9 @@ static int device_lds_max() {
 }
 
 constexpr int MAX_WORKERS = 4;  // concurrent streams for independent problems
+// more nonzeros of A per column than this: Y = Delta A by grouped GEMMs
+// instead of the compressed-column product
+constexpr int DENSE_A_PER_COLUMN = 16;
 
 static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, char* base, int lds_max,
                    int max_workers, bool expmap, ObsBuf* ob = nullptr, int* nworkers = nullptr) {
@@ -434,6 +440,7 @@ static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, c
     q.nq = sp.nq; q.e0 = sp.e0;
     q.M = sp.nq > 0 ? impurity_count(sp) : 0;
     q.nnz = nnz_count(sp, &q.nnz_up);
+    q.denseA = q.nnz > DENSE_A_PER_COLUMN * q.n;
     q.gj_nb = pick_gj_nb(q.n, lds_max);
     q.expmap = expmap;
     carve(q, ar);
@@ -633,6 +640,18 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
     add_job(q.jdi, j);
   }
   HIPCHK(upload_jobs(q.jdi));
+  // dense A: the products with A on the matrix cores
+  q.jya.host.clear(); q.jya.ntiles = 0;
+  if (q.denseA) {
+    for (int pp = 0; pp < P; ++pp) {
+      add_job(q.jya, job(q.W + pp * nn, n, 0, q.Adense, n, 0, nullptr, n, q.Y + 2 * pp * nn, n, n, n, n, -2.0, 0.0));
+      add_job(q.jya, job(q.Di + pp * nn, n, 0, q.Adense, n, 0, nullptr, n, q.Y + (2 * pp + 1) * nn, n, n, n, n,
+                         1.0, 0.0));
+    }
+    for (int mu = 0; mu < R; ++mu)
+      add_job(q.jya, job(q.gam + mu * nn, n, 0, q.Adense, n, 0, nullptr, n, q.Yd + mu * nn, n, n, n, n, 1.0, 0.0));
+  }
+  HIPCHK(upload_jobs(q.jya));
   // phase matrices: T_a = Gamma_0 W_0a ; Re X_a = T_a Gamma_0 + W_0a
   q.jt1.host.clear(); q.jt1.ntiles = 0; q.jxr.host.clear(); q.jxr.ntiles = 0;
   for (int a = 1; a < R; ++a) {
@@ -808,7 +827,12 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
   HamDev h{n, q.nnz_up, q.nq, q.M, q.up_k, q.up_l, q.up_v, q.q_idx, q.q_loc, q.q_val, q.e0};
   HCHK(launch_eps_fock(h, P, R, q.W, q.Di, q.gam, q.pa, q.pb, q.eps, q.Fc, s));
   SparseA sa{q.colptr, q.rowidx, q.colval, q.imp, q.impos, q.M};
-  HCHK(launch_apply_fock(sa, n, P, R, q.W, q.Di, q.gam, q.Fc, q.Y, q.Yd, s));
+  if (q.denseA) {
+    HCHK(run_gemm(q.jya, s));
+    HCHK(launch_fock_imp(sa, n, P, R, q.W, q.Di, q.gam, q.Fc, q.Y, q.Yd, s));
+  } else {
+    HCHK(launch_apply_fock(sa, n, P, R, q.W, q.Di, q.gam, q.Fc, q.Y, q.Yd, s));
+  }
   tm.end(SGS_STAGE_WICK, s);
   if (P > 0 && fork) HCHK(hipStreamWaitEvent(s, wk.ev_join, 0));
   SolveArgs a;

@@ -172,6 +172,56 @@ __global__ __launch_bounds__(256) void k_apply_fock(SparseA sa, int n, int P, co
   }
 }
 
+// Dense A: Y = Delta A and Yd = Gamma A come from grouped GEMMs; this adds
+// the impurity-block Fock correction Delta[:, imp] Fc (Gamma[:, imp] Fc_r for
+// the states) on the M impurity columns.  grid: (ceil(n M / 256), P + R)
+__global__ __launch_bounds__(256) void k_fock_imp(SparseA sa, int n, int P, const double* __restrict__ W,
+                                                  const double* __restrict__ Di,
+                                                  const double* __restrict__ gam,
+                                                  const double* __restrict__ Fc,
+                                                  double* __restrict__ Y, double* __restrict__ Yd) {
+  const int blk = blockIdx.y;
+  const int M = sa.M;
+  const long long nn = (long long)n * n;
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= (long long)n * M) return;
+  const int i = (int)(e / M), jl = (int)(e - (long long)i * M);
+  const int j = sa.imp[jl];
+  const double* fr = Fc + (long long)blk * 2 * M * M;
+  const double* fi = fr + M * M;
+  const long long o = (long long)i * n + j;
+  if (blk < P) {
+    const double* w = W + blk * nn + (long long)i * n;
+    const double* di = Di + blk * nn + (long long)i * n;
+    double yr = 0.0, yi = 0.0;
+    for (int kl = 0; kl < M; ++kl) {
+      const int k = sa.imp[kl];
+      const double xr = -2.0 * w[k], xi = di[k];
+      const double cr = fr[kl * M + jl], ci = fi[kl * M + jl];
+      yr += xr * cr - xi * ci;
+      yi += xr * ci + xi * cr;
+    }
+    double* y = Y + (long long)blk * 2 * nn;
+    y[o] += yr;
+    y[o + nn] += yi;
+  } else {
+    const int mu = blk - P;
+    const double* g = gam + mu * nn + (long long)i * n;
+    double y = 0.0;
+    for (int kl = 0; kl < M; ++kl) y += g[sa.imp[kl]] * fr[kl * M + jl];
+    Yd[mu * nn + o] += y;
+  }
+}
+
+hipError_t launch_fock_imp(const SparseA& sa, int n, int P, int R, const double* W, const double* Di,
+                           const double* gam, const double* Fc, double* Y, double* Yd, hipStream_t s) {
+  if (sa.M <= 0) return hipSuccess;
+  const long long cnt = (long long)n * sa.M;
+  hipLaunchKernelGGL(k_fock_imp, dim3((unsigned)((cnt + 255) / 256), P + R), dim3(256), 0, s, sa, n, P, W, Di,
+                     gam, Fc, Y, Yd);
+  return hipGetLastError();
+}
+
 // C_ab = i (Gamma_b + Gamma_0) - i X_a for 1 <= a < b, planar:
 //   Re C = Im X_a = T_a^T - T_a  (T_a = Gamma_0 W_0a),
 //   Im C = Gamma_b + Gamma_0 - Re X_a.

@@ -182,6 +182,9 @@ hipError_t launch_eps_fock(const HamDev& h, int P, int R, const double* W, const
                            hipStream_t s);
 hipError_t launch_apply_fock(const SparseA& sa, int n, int P, int R, const double* W, const double* Di,
                              const double* gam, const double* Fc, double* Y, double* Yd, hipStream_t s);
+// dense A: adds the impurity-block Fock correction into Y = Delta A, Yd = Gamma A
+hipError_t launch_fock_imp(const SparseA& sa, int n, int P, int R, const double* W, const double* Di,
+                           const double* gam, const double* Fc, double* Y, double* Yd, hipStream_t s);
 hipError_t launch_build_c(int n, const double* gam, const double* T, const double* Xr, const int* qa,
                           const int* qb, int Q, double* Cm, hipStream_t s);
 size_t solve_lds_bytes(int R);
