@@ -48,6 +48,7 @@ struct Prob {
   bool expmap = false;  // exponential-map update instead of Euler + purification
   bool denseA = false;  // A has many nonzeros per column: Y = Delta A by GEMM
   double e0 = 0.0;
+  double a2 = 0.0;  // |A|_F^2
   double* gam = nullptr;
   // dense work
   double *W, *Di, *Y, *Yd, *T1, *Xr, *Cm, *Cm2, *UV, *RM, *gjE, *gjB, *dG, *dP, *dE, *nsX0, *nsX1, *nsQ, *Adense;
@@ -184,7 +185,7 @@ struct ObsBuf {
   double* coef = nullptr;
   int* off = nullptr;
   double* part = nullptr;
-  double* vpart = nullptr;  // variance partial sums, R^2 x VAR_CHUNKS x 6 complex
+  double* vpart = nullptr;  // variance partial sums, R (R + 1) / 2 x VAR_CHUNKS x 5 complex
 };
 
 // One stream of independent problems.  Worker 0 runs on the context's
@@ -427,7 +428,7 @@ static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, c
     o.coef = ar.take<double>(2 * (size_t)OBS_MAX_TERMS);
     o.off = ar.take<int>((size_t)OBS_MAX_POLY + 1);
     o.part = ar.take<double>(2 * 32 * 32);
-    o.vpart = ar.take<double>((size_t)32 * 32 * VAR_CHUNKS * 12);
+    o.vpart = ar.take<double>((size_t)32 * 32 * VAR_CHUNKS * 10);
     if (ob) *ob = o;
   }
   pr.assign(nprob, Prob());
@@ -594,6 +595,8 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
   for (int i = 0; i < n; ++i)
     for (int j = i + 1; j < n; ++j)
       if (Ad[(size_t)i * n + j] != 0.0) { uk.push_back(i); ul.push_back(j); uv.push_back(Ad[(size_t)i * n + j]); }
+  q.a2 = 0.0;
+  for (double v : uv) q.a2 += 2.0 * v * v;
   for (int j = 0; j < n; ++j) {
     colptr[j] = (int)rowidx.size();
     for (int i = 0; i < n; ++i)
@@ -1155,7 +1158,7 @@ int sgs_observables(sgs_ctx* c, int32_t kind, const int32_t* iargs, int32_t niar
     if (ensure_tables(c, p) != hipSuccess) return SGS_EHIP;
     ObsState s{n, q.R, q.gam, q.W, q.Di, q.lam, q.Gt, q.pidx};
     VarHam h{q.Adense, q.nnz_up, q.up_k, q.up_l, q.up_v, q.colptr, q.rowidx, q.colval, q.nq, q.q_idx, q.q_val};
-    if (launch_variance(s, h, q.e0, c->obs.vpart, out, c->s) != hipSuccess) return SGS_EHIP;
+    if (launch_variance(s, h, q.e0, q.a2, c->obs.vpart, out, c->s) != hipSuccess) return SGS_EHIP;
     return SGS_OK;
   }
   if (kind == SGS_OBS_RENYI2) {

@@ -19,9 +19,12 @@
 // H4 = sum_q u_q c_q0 c_q1 c_q2 c_q3 (Sec. II.A):
 //   <H2>_t = -2 sum_{k<l} A_kl Delta_kl,
 //   <H2 H2>_t = <H2>_t^2 + (1/2) Tr(alpha K alpha K^T)
-//             = <H2>_t^2 + Tr(T alpha) - (1/2) Tr(T T),  T = alpha K
-//   (K^T = 2 - K), and every product with a quartic word is the Pfaffian of
-// the contraction matrix of its 6 or 8 Majoranas (M_ab = K_{i_a i_b}, a < b).
+//             = <H2>_t^2 + 2 |A|_F^2 - 2 Tr(U U),  U = A Delta
+// (K^T = 2 - K; with A and Delta skew the terms linear in U cancel and
+// U_ji = (Delta A)_ij, so Tr(U U) = sum_ij (A Delta)_ij (Delta A)_ij: both
+// factors combine rows of Delta), and every product with a quartic word is
+// the Pfaffian of the contraction matrix of its 6 or 8 Majoranas
+// (M_ab = K_{i_a i_b}, a < b).
 //
 // Storage: the pair p = (a < b) keeps W = (Gamma_a + Gamma_b)^{-1} and
 // Im Delta^{ba}; Delta^{ba} = -2 W + i Im, Delta^{ab} = its conjugate.
@@ -52,7 +55,8 @@ __device__ __forceinline__ cd g_at(const ObsState& s, int i, int j) {
   return {s.Gt[2 * (i * s.R + j)], s.Gt[2 * (i * s.R + j) + 1]};
 }
 
-// block-wide complex sum in a fixed order (deterministic); blockDim.x <= 256
+// block-wide complex sum in a fixed order (deterministic); red holds blockDim.x
+// entries, blockDim.x a power of two
 __device__ cd block_sum(cd v, cd* red) {
   const int t = threadIdx.x;
   red[t] = v;
@@ -267,45 +271,111 @@ __device__ cd wick_product(const ObsState& s, int x, int y, const int* idx, int 
   return pf8p(M);
 }
 
-// grid: (R * R blocks (mu, b), VAR_CHUNKS), 256 threads.  Block (mu, b)
-// works on Delta^{b mu}; its chunk writes six complex partial sums to
-// part[((mu R + b) VAR_CHUNKS + chunk) 12 ..]: Tr(T T), Tr(T alpha), <H2>_t,
-// <H4>_t, <H2 H4 + H4 H2>_t, <H4 H4>_t.
+// Blocks (mu, b) with b <= mu, m = mu (mu + 1) / 2 + b: block (mu, b) works on
+// Delta^{b mu}; the block (b, mu) is its complex conjugate (H and H^2 are
+// Hermitian) and is not computed.  Chunk `chunk` of block m writes five
+// complex partial sums to part[(m VAR_CHUNKS + chunk) 10 ..]: Tr(U U) (by
+// k_var_uu), <H2>_t, <H4>_t, <H2 H4 + H4 H2>_t, <H4 H4>_t (by k_var_part).
+__device__ __forceinline__ int tri_row(int m) {
+  int r = 0;
+  while ((r + 1) * (r + 2) / 2 <= m) ++r;
+  return r;
+}
+
+// grid: (R (R + 1) / 2, VAR_CHUNKS), 512 threads.  Tr(U U) = sum_ij U_ij U_ji
+// by 64 x 64 tiles: for tiles I >= J the block stores U[I, J] in LDS, then
+// forms U[J, I] and multiplies entrywise with the transposed tile
+// (off-diagonal tile pairs count twice).  Row i of U is
+// -sum_{k in column i} A_ki Delta_k,: (A skew), so a wave walks one column of
+// A for all 64 lanes and reads 64 consecutive entries of a row of Delta.
+constexpr int VAR_T = 64;
+constexpr int VAR_NW = 8;                // waves per block
+constexpr int VAR_RPW = VAR_T / VAR_NW;  // tile rows per wave
+
+// U_{r_k, c} = -sum_{q in column r_k} A_{row q, r_k} Delta_{row q, c} for the
+// rows r_k = r0 + VAR_NW k of one wave (zero for r_k >= n or c >= n).  The
+// rows advance together, one nonzero each per step, with clamped indices and
+// zero weights past a column's end, so each step has VAR_RPW independent loads.
+__device__ __forceinline__ void u_rows(const ObsState& s, const VarHam& h, int x, int y, int r0, int c,
+                                       double (&er)[VAR_RPW], double (&ei)[VAR_RPW]) {
+  const int n = s.n;
+  int beg[VAR_RPW], len[VAR_RPW], mx = 0;
+#pragma unroll
+  for (int k = 0; k < VAR_RPW; ++k) {
+    const int i = r0 + VAR_NW * k;
+    beg[k] = i < n ? h.colptr[i] : 0;
+    len[k] = i < n ? h.colptr[i + 1] - beg[k] : 0;
+    mx = max(mx, len[k]);
+    er[k] = 0.0;
+    ei[k] = 0.0;
+  }
+  const bool cin = c < n;
+  const int cc = cin ? c : n - 1;
+  for (int t = 0; t < mx; ++t) {  // mx > 0 only if A has nonzeros
+#pragma unroll
+    for (int k = 0; k < VAR_RPW; ++k) {
+      const bool v = t < len[k];
+      const int q = v ? beg[k] + t : 0;
+      const double a = v && cin ? h.colval[q] : 0.0;
+      const cd d = delta_at(s, x, y, h.rowidx[q], cc);
+      er[k] -= a * d.r;
+      ei[k] -= a * d.i;
+    }
+  }
+}
+
+__global__ __launch_bounds__(VAR_NW * 64) void k_var_uu(ObsState s, VarHam h, double* __restrict__ part) {
+  __shared__ double ur[VAR_T][VAR_T + 1], ui[VAR_T][VAR_T + 1];
+  __shared__ cd red[VAR_NW * 64];
+  const int n = s.n;
+  const int m = blockIdx.x, ch = blockIdx.y;
+  const int mu = tri_row(m), b = m - mu * (mu + 1) / 2;
+  const int x = b, y = mu;  // Delta^{b mu}
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  cd tuu{0.0, 0.0};
+  const int nt = (n + VAR_T - 1) / VAR_T;
+  for (int tp = ch; tp < nt * (nt + 1) / 2; tp += VAR_CHUNKS) {
+    const int I = tri_row(tp);
+    const int J = tp - I * (I + 1) / 2;  // J <= I
+    const int i0 = I * VAR_T, j0 = J * VAR_T;
+    double er[VAR_RPW], ei[VAR_RPW];
+    u_rows(s, h, x, y, i0 + wv, j0 + lane, er, ei);  // U[i0 + r, j0 + lane]
+#pragma unroll
+    for (int k = 0; k < VAR_RPW; ++k) {
+      ur[wv + VAR_NW * k][lane] = er[k];
+      ui[wv + VAR_NW * k][lane] = ei[k];
+    }
+    __syncthreads();
+    u_rows(s, h, x, y, j0 + wv, i0 + lane, er, ei);  // U[j0 + r, i0 + lane]
+    cd acc{0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < VAR_RPW; ++k) {
+      const int r = wv + VAR_NW * k;
+      acc = cadd(acc, cmul(cd{er[k], ei[k]}, cd{ur[lane][r], ui[lane][r]}));
+    }
+    __syncthreads();
+    const double f = I == J ? 1.0 : 2.0;
+    tuu.r += f * acc.r;
+    tuu.i += f * acc.i;
+  }
+  const cd sum = block_sum(tuu, red);
+  if (threadIdx.x == 0) {
+    double* o = part + ((long long)m * VAR_CHUNKS + ch) * 10;
+    o[0] = sum.r;
+    o[1] = sum.i;
+  }
+}
+
+// grid: (R (R + 1) / 2, VAR_CHUNKS), 256 threads: the sums over the sparse
+// quadratic part and the quartic words
 __global__ __launch_bounds__(256) void k_var_part(ObsState s, VarHam h, double* __restrict__ part) {
   __shared__ cd red[256];
-  const int n = s.n, R = s.R;
-  const int mb = blockIdx.x, ch = blockIdx.y;
-  const int mu = mb / R, b = mb % R;
+  const int m = blockIdx.x, ch = blockIdx.y;
+  const int mu = tri_row(m), b = m - mu * (mu + 1) / 2;
   const int x = b, y = mu;  // Delta^{b mu}
   const int stride = VAR_CHUNKS * blockDim.x;
   const int t0 = ch * blockDim.x + threadIdx.x;
-  cd trtt{0.0, 0.0}, trta{0.0, 0.0}, h2{0.0, 0.0}, h4{0.0, 0.0}, hx{0.0, 0.0}, h44{0.0, 0.0};
-  // T_ij = 2 i A_ij - 2 (A Delta)_ij = 2 i A_ij + 2 sum_{k in column i} A_ki Delta_kj (A skew)
-  auto tval = [&](int i, int j) -> cd {
-    cd v{0.0, 2.0 * h.Ad[(long long)i * n + j]};
-    for (int q = h.colptr[i]; q < h.colptr[i + 1]; ++q) {
-      const cd d = delta_at(s, x, y, h.rowidx[q], j);
-      const double a = 2.0 * h.colval[q];
-      v.r += a * d.r;
-      v.i += a * d.i;
-    }
-    return v;
-  };
-  for (long long e = t0; e < (long long)n * n; e += stride) {
-    const int i = (int)(e / n), j = (int)(e - (long long)i * n);
-    if (i > j) continue;
-    const cd tij = tval(i, j);
-    if (i == j) {
-      trtt = cadd(trtt, cmul(tij, tij));
-    } else {
-      const cd tji = tval(j, i);
-      const cd pr = cmul(tij, tji);
-      trtt.r += 2.0 * pr.r;
-      trtt.i += 2.0 * pr.i;
-      // T_ij alpha_ji + T_ji alpha_ij = 2 i A_ij (T_ji - T_ij)
-      trta = cadd(trta, cmul(cd{0.0, 2.0 * h.Ad[(long long)i * n + j]}, csub(tji, tij)));
-    }
-  }
+  cd h2{0.0, 0.0}, h4{0.0, 0.0}, hx{0.0, 0.0}, h44{0.0, 0.0};
   // <H2>_t = sum_{k<l} alpha_kl K_kl = -2 sum_{k<l} A_kl Delta_kl
   for (int u = t0; u < h.nnz_up; u += stride) {
     const cd d = delta_at(s, x, y, h.up_k[u], h.up_l[u]);
@@ -337,40 +407,46 @@ __global__ __launch_bounds__(256) void k_var_part(ObsState s, VarHam h, double* 
     h44.r += c * v.r;
     h44.i += c * v.i;
   }
-  const cd sums[6] = {block_sum(trtt, red), block_sum(trta, red), block_sum(h2, red),
-                      block_sum(h4, red), block_sum(hx, red), block_sum(h44, red)};
+  const cd sums[4] = {block_sum(h2, red), block_sum(h4, red), block_sum(hx, red), block_sum(h44, red)};
   if (threadIdx.x == 0) {
-    double* o = part + ((long long)mb * VAR_CHUNKS + ch) * 12;
-    for (int k = 0; k < 6; ++k) { o[2 * k] = sums[k].r; o[2 * k + 1] = sums[k].i; }
+    double* o = part + ((long long)m * VAR_CHUNKS + ch) * 10;
+    for (int k = 0; k < 4; ++k) { o[2 + 2 * k] = sums[k].r; o[3 + 2 * k] = sums[k].i; }
   }
 }
 
 // one workgroup: per block (mu, b) <H'>_t = <H2>_t + <H4>_t and
-// <H'^2>_t = <H2>_t^2 + Tr(T alpha) - Tr(T T) / 2 + <H2 H4 + H4 H2>_t + <H4 H4>_t
-// (H' = H - e0), weighted by lambda_mu^* lambda_b G_{mu b}; out = {<H>, <H^2>,
-// delta_H^2}, normalized by sum lambda_mu^* lambda_b G_{mu b}
+// <H'^2>_t = <H2>_t^2 + 2 |A|_F^2 - 2 Tr(U U) + <H2 H4 + H4 H2>_t + <H4 H4>_t
+// (H' = H - e0), weighted by lambda_mu^* lambda_b G_{mu b}, the block (b, mu)
+// taking the conjugate values; out = {<H>, <H^2>, delta_H^2}, normalized by
+// sum lambda_mu^* lambda_b G_{mu b}
 __global__ __launch_bounds__(256) void k_var_final(ObsState s, const double* __restrict__ part, double e0,
-                                                   double* __restrict__ out) {
+                                                   double a2, double* __restrict__ out) {
   __shared__ cd red[256];
   const int R = s.R;
   cd s1{0.0, 0.0}, s2{0.0, 0.0}, nr{0.0, 0.0};
-  for (int mb = threadIdx.x; mb < R * R; mb += blockDim.x) {
-    cd v[6];
-    for (int k = 0; k < 6; ++k) v[k] = {0.0, 0.0};
+  for (int m = threadIdx.x; m < R * (R + 1) / 2; m += blockDim.x) {
+    cd v[5];
+    for (int k = 0; k < 5; ++k) v[k] = {0.0, 0.0};
     for (int ch = 0; ch < VAR_CHUNKS; ++ch) {
-      const double* o = part + ((long long)mb * VAR_CHUNKS + ch) * 12;
-      for (int k = 0; k < 6; ++k) { v[k].r += o[2 * k]; v[k].i += o[2 * k + 1]; }
+      const double* o = part + ((long long)m * VAR_CHUNKS + ch) * 10;
+      for (int k = 0; k < 5; ++k) { v[k].r += o[2 * k]; v[k].i += o[2 * k + 1]; }
     }
-    const cd X = cadd(v[2], v[3]);
-    cd Y = cmul(v[2], v[2]);
-    Y = cadd(Y, v[1]);
-    Y = csub(Y, cd{0.5 * v[0].r, 0.5 * v[0].i});
-    Y = cadd(cadd(Y, v[4]), v[5]);
-    const int mu = mb / R, b = mb % R;
+    const cd X = cadd(v[1], v[2]);
+    cd Y = cmul(v[1], v[1]);
+    Y.r += 2.0 * a2 - 2.0 * v[0].r;
+    Y.i -= 2.0 * v[0].i;
+    Y = cadd(cadd(Y, v[3]), v[4]);
+    const int mu = tri_row(m), b = m - mu * (mu + 1) / 2;
     const cd c = cmul(cmul(cconj(lam_at(s, mu)), lam_at(s, b)), g_at(s, mu, b));
     s1 = cadd(s1, cmul(c, X));
     s2 = cadd(s2, cmul(c, Y));
     nr = cadd(nr, c);
+    if (b != mu) {
+      const cd ct = cmul(cmul(cconj(lam_at(s, b)), lam_at(s, mu)), g_at(s, b, mu));
+      s1 = cadd(s1, cmul(ct, cconj(X)));
+      s2 = cadd(s2, cmul(ct, cconj(Y)));
+      nr = cadd(nr, ct);
+    }
   }
   const cd S1 = block_sum(s1, red), S2 = block_sum(s2, red), N = block_sum(nr, red);
   if (threadIdx.x == 0) {
@@ -384,11 +460,12 @@ __global__ __launch_bounds__(256) void k_var_final(ObsState s, const double* __r
   }
 }
 
-hipError_t launch_variance(const ObsState& s, const VarHam& h, double e0, double* part, double* out,
+hipError_t launch_variance(const ObsState& s, const VarHam& h, double e0, double a2, double* part, double* out,
                            hipStream_t st) {
   if (s.R < 1 || s.R > 32) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_var_part, dim3(s.R * s.R, VAR_CHUNKS), dim3(256), 0, st, s, h, part);
-  hipLaunchKernelGGL(k_var_final, dim3(1), dim3(256), 0, st, s, (const double*)part, e0, out);
+  hipLaunchKernelGGL(k_var_uu, dim3(s.R * (s.R + 1) / 2, VAR_CHUNKS), dim3(VAR_NW * 64), 0, st, s, h, part);
+  hipLaunchKernelGGL(k_var_part, dim3(s.R * (s.R + 1) / 2, VAR_CHUNKS), dim3(256), 0, st, s, h, part);
+  hipLaunchKernelGGL(k_var_final, dim3(1), dim3(256), 0, st, s, (const double*)part, e0, a2, out);
   return hipGetLastError();
 }
 

@@ -219,7 +219,8 @@ struct VarHam {
   const double* q_val;
 };
 constexpr int VAR_CHUNKS = 16;  // workgroups per transition block
-hipError_t launch_variance(const ObsState& s, const VarHam& h, double e0, double* part, double* out,
+// a2 = |A|_F^2
+hipError_t launch_variance(const ObsState& s, const VarHam& h, double e0, double a2, double* part, double* out,
                            hipStream_t st);
 constexpr int OBS_MAX_NA = 32;      // Renyi-2 subsystem: at most 32 Majoranas
 constexpr int OBS_MAX_TERMS = 16384;
