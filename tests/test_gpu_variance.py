@@ -4,10 +4,10 @@ through the C ABI (SGS_OBS_VARIANCE) against the oracle.
 Small systems against the word expansion of H^2 (``hamiltonian_variance``):
 Anderson n = 16 with R = 1 and 3, the two-channel Kondo model (several
 quartic words: 6- and 8-Majorana Pfaffians) with R = 3, a ragged n = 132
-over several tiles, and the exact Gaussian ground state of a quadratic H
-(delta_H^2 = 0).  Full size (n = 400, R = 16) against the matrix form
-(``hamiltonian_variance_trace``, itself pinned to the word expansion), before
-and after 5 steps.
+over several tiles, the exact Gaussian ground state of a quadratic H
+(delta_H^2 = 0), and a dense A with odd R.  R = 32 (the largest) and full
+size (n = 400, R = 16) against the matrix form (``hamiltonian_variance_trace``,
+itself pinned to the word expansion), the latter before and after 5 steps.
 
 Tolerance: <H> and <H^2> are sums of lambda_mu^* lambda_b G_mb <.>_t, so
 they inherit the tables' relative accuracy (1e-9, as the other
@@ -64,6 +64,40 @@ def test_variance_matches_oracle(model, L, R, seed):
     _check(got, ref)
     Eg, _ = ctx.energy()
     assert abs(got[0] - Eg.cpu().item()) < TOL * max(1.0, abs(got[0]))
+    ctx.close()
+
+
+def test_variance_largest_R():
+    """R = 32 (the most the variance takes): 528 blocks b <= mu, the others
+    taken as their conjugates."""
+    ham = si.anderson(3, 1.3, 0.7)
+    gam = si.random_states(ham.N, 32, 11)
+    _say(f"[variance] anderson n={ham.n} R=32")
+    ctx = _ctx(ham, gam)
+    got = ctx.variance()
+    assert ctx.status() == 0
+    E, lam, tab = osgs.energy(ham, gam)
+    _check(got, ob.hamiltonian_variance_trace(ham, gam, lam, tab.G))
+    ctx.close()
+
+
+def test_variance_dense_A():
+    """Every column of A full (the longest column walks), two quartic words,
+    odd R; against the word expansion."""
+    rng = np.random.default_rng(3)
+    N = 12
+    n = 2 * N
+    z = rng.standard_normal((n, n)) / np.sqrt(n)
+    words = np.array([np.sort(rng.choice(n, size=4, replace=False)) for _ in range(2)], dtype=np.int32)
+    ham = si.MajoranaHamiltonian(N=N, A=0.5 * (z - z.T), quartic_idx=words,
+                                 quartic_val=rng.uniform(0.2, 0.8, size=2), e0=0.3)
+    gam = si.random_states(ham.N, 5, 2)
+    _say(f"[variance] dense A n={ham.n} R=5")
+    ctx = _ctx(ham, gam)
+    got = ctx.variance()
+    assert ctx.status() == 0
+    E, lam, tab = osgs.energy(ham, gam)
+    _check(got, ob.hamiltonian_variance(ham, gam, lam, tab.G))
     ctx.close()
 
 
