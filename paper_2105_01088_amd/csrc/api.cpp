@@ -867,7 +867,7 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
   // joined before the solve), concurrent with the dense products
   HCHK(hipEventRecord(wk.ev_f, s));
   HCHK(hipStreamWaitEvent(wk.s2, wk.ev_f, 0));
-  HCHK(launch_force_elem(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, q.dE, wk.s2));
+  HCHK(launch_force_elem(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, fmode == FORCE_FP32, q.dE, wk.s2));
   HCHK(hipEventRecord(wk.ev_fe, wk.s2));
   HCHK(launch_force(n, R, q.terms, q.coef, q.dG, q.dP, q.dgnorm, fmode, s));
   tm.end(SGS_STAGE_FORCE, s);

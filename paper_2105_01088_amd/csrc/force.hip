@@ -60,7 +60,7 @@ constexpr size_t force_lds_bytes(size_t elem) {
 // b % 8, so all tiles of a state share that XCD's L2 (every tile of state mu
 // streams the same Y and Delta panels).  terms: R*R descriptors (mu-major);
 // coef: c1 then c2 tables, complex interleaved, R*R each.
-template <typename TT>
+template <typename TT, bool IY>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_force(int n, int R, int T, const ForceTerm* __restrict__ terms,
                                                const double* __restrict__ coef,
                                                double* __restrict__ dG, double* __restrict__ dP,
@@ -146,7 +146,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double dr = ds * rd[0][r], di = sgi * rd[1][r];
+        // IY: B = c1 (D + i 1), so the product also carries Re(c1 i Y)
+        const double dr = ds * rd[0][r],
+                     di = sgi * rd[1][r] + (IY && kc + b_k + r == col0 + b_j && col0 + b_j < n ? 1.0 : 0.0);
         // A: Y_r, sg Y_i; B: Re(c1 D), -Im(c1 D)
         As[0][a_k + r][a_i] = (TT)ra[0][r];
         As[1][a_k + r][a_i] = (TT)(sgi * ra[1][r]);
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(FS_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
 __global__ __launch_bounds__(512) void k_force_elem(int n, int R, int T, const ForceTerm* __restrict__ terms,
                                                     const double* __restrict__ coef,
                                                     const double* __restrict__ Adense,
-                                                    const int* __restrict__ impos, int M,
+                                                    const int* __restrict__ impos, int M, int direct_y,
                                                     double* __restrict__ dE) {
   __shared__ double Tt[64][64 + 1];
   const int mu = blockIdx.y;
@@ -413,7 +415,8 @@ __global__ __launch_bounds__(512) void k_force_elem(int n, int R, int T, const F
       const int gi = row0 + li;
       const bool ok = gi < n && gj < n;
       const long long o = ok ? (long long)gi * n + gj : 0;
-      double v = -y1 * Yr[o] + x2 * ds * Dr[o] + im * (-x1 * sg * Yi[o] - y2 * sg * Di[o]);
+      double v = x2 * ds * Dr[o] - im * y2 * sg * Di[o];
+      if (direct_y) v += -y1 * Yr[o] - im * x1 * sg * Yi[o];
       if (M > 0 && ok) {
         const int pi = impos[gi], pj = impos[gj];
         if (pi >= 0 && pj >= 0) {
@@ -512,17 +515,17 @@ hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef
   const int ntri = T * (T + 1) / 2;
   const dim3 grid(8 * per_xcd * ntri * FORCE_SPLIT), block(256);
   if (mode == FORCE_FP64)
-    hipLaunchKernelGGL((k_force<double>), grid, block, 0, s, n, R, T, terms, coef, dG, dP, nrm);
+    hipLaunchKernelGGL((k_force<double, true>), grid, block, 0, s, n, R, T, terms, coef, dG, dP, nrm);
   else
-    hipLaunchKernelGGL((k_force<float>), grid, block, 0, s, n, R, T, terms, coef, dG, dP, nrm);
+    hipLaunchKernelGGL((k_force<float, false>), grid, block, 0, s, n, R, T, terms, coef, dG, dP, nrm);
   return hipGetLastError();
 }
 
 hipError_t launch_force_elem(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
-                             const int* impos, int M, double* dE, hipStream_t s) {
+                             const int* impos, int M, int direct_y, double* dE, hipStream_t s) {
   const int T = (n + 63) / 64;
   hipLaunchKernelGGL(k_force_elem, dim3(T * (T + 1) / 2, R), dim3(512), 0, s, n, R, T, terms, coef, A, impos, M,
-                     dE);
+                     direct_y, dE);
   return hipGetLastError();
 }
 

@@ -241,8 +241,10 @@ enum : int { FORCE_FP64 = 0, FORCE_FP32 = 1 };
 constexpr int FORCE_SPLIT = 2;
 hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, double* dG, double* dP,
                         unsigned long long* nrm, int mode, hipStream_t s);
+// direct_y = 0: the products carry Re(c1 i Y) (FP64: B = c1 (D + i 1)) and
+// k_force_elem leaves it out
 hipError_t launch_force_elem(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
-                             const int* impos, int M, double* dE, hipStream_t s);
+                             const int* impos, int M, int direct_y, double* dE, hipStream_t s);
 hipError_t launch_force_join(double* dG, const double* dP, const double* dE, int n, int R, unsigned long long* nrm,
                              hipStream_t s);
 hipError_t launch_euler(const double* gam, const double* dG, double dtau, int n, int R, double* X,
