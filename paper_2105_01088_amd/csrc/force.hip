@@ -9,11 +9,16 @@
 // depth 2n per term; in k_force the workgroup for an output tile streams
 // every term b through the matrix cores, forming the B operand Re(c1 D) /
 // -Im(c1 D) on the fly from W (D_r = -2 W) and D_i, and writes the tile and
-// its skew mirror (the force is skew: only tiles I <= J run).  The remaining
-// terms, Re{c1 (F + i (Y - Y^T)) + c2 D}, are elementwise and memory-bound:
-// k_force_elem sums them into a second buffer on another stream while the
-// matrix cores run (few registers, many waves to hide the loads), and
-// k_force_join adds the two and takes the 1-norm the Euler step needs.
+// its skew mirror (the force is skew: only tiles I <= J run).  In float64
+// the B operand is c1 (D + i 1) (a 1 on the diagonal while staging), so
+// the product also carries Re(c1 i Y).  The remaining terms,
+// Re{c1 (F - i Y^T) + c2 D} (float32 products: also Re(c1 i Y), kept in
+// float64), are elementwise and memory-bound: k_force_elem sums them into a
+// second buffer on another stream while the matrix cores run (few
+// registers, many waves to hide the loads), and k_force_join adds the two
+// and takes the 1-norm the Euler step needs.  Each part is skew-completed
+// the same way (strict upper triangle mirrored, diagonal tiles
+// antisymmetrized), which is exact for their sum, the skew force.
 // The pair (a < b) stores Delta^{ba}; the term for mu = b uses its complex
 // conjugate (sgn = -1 on every imaginary part).
 //
