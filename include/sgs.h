@@ -59,6 +59,7 @@ extern "C" {
 #define SGS_EWORKSPACE (-9)/* workspace smaller than sgs_workspace_bytes        */
 #define SGS_ERANGE (-10)   /* exponential map: |c dtau [Gamma, dGamma]|_1 above */
                            /* 2^12 (or not finite) for some state             */
+#define SGS_ESCRATCH (-11) /* sgs_rotate_noalloc: n above its fixed scratch    */
 
 /* sgs_options.precision */
 #define SGS_FP64 0          /* every stage in float64                          */
@@ -209,6 +210,18 @@ int sgs_observables(sgs_ctx* ctx, int32_t kind, const int32_t* iargs,
  * 2..8192), SGS_EHIP. */
 int sgs_rotate(const double* Q, const double* gamma, double* work, double* gamma_out, int32_t n,
                void* stream);
+
+/* sgs_rotate without a work buffer, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and result as sgs_rotate; the n x n intermediate
+ * lives in a fixed scratch array of the library (18 MiB per device, held from
+ * the first call on a device until the process ends), so n <= 1536.  No
+ * allocation of any kind is made.  Every call on one device shares that
+ * scratch: calls that overlap on a device (different streams, or threads
+ * without ordering) race and must be serialized by the caller.
+ * Errors: SGS_EINVAL (null pointer, n odd or < 2), SGS_ESCRATCH (n > 1536),
+ * SGS_EHIP. */
+int sgs_rotate_noalloc(const double* Q, const double* gamma, double* gamma_out, int32_t n, void* stream);
 
 /* Wait for the context's stream and return the device status word:
  * SGS_OK, SGS_ESINGULAR, SGS_ENOCONV or SGS_ERANGE (first failure since the last call;

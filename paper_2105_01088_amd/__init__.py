@@ -22,5 +22,6 @@ from ._lib import (  # noqa: F401
     SGS_OBS_RENYI2,
     SGS_OBS_VARIANCE,
     rotate_state,
+    rotate_state_noalloc,
 )
 from .protocol import grow  # noqa: F401

@@ -75,6 +75,8 @@ def load_library(path: str = LIB_PATH):
     lib.sgs_strerror.restype = ctypes.c_char_p
     lib.sgs_rotate.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
     lib.sgs_rotate.restype = c_int32
+    lib.sgs_rotate_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
+    lib.sgs_rotate_noalloc.restype = c_int32
     for f in ("sgs_workspace_bytes", "sgs_init", "sgs_pair_eval", "sgs_step", "sgs_energy",
               "sgs_observables", "sgs_status", "sgs_set_timing", "sgs_stage_times"):
         getattr(lib, f).restype = c_int32
@@ -111,6 +113,24 @@ def rotate_state(Q, gamma, stream=None):
     st = stream if stream is not None else torch.cuda.current_stream(gamma.device)
     _check(lib.sgs_rotate(Q.data_ptr(), g.data_ptr(), work.data_ptr(), out.data_ptr(), n, st.cuda_stream),
            "sgs_rotate")
+    return out
+
+
+def rotate_state_noalloc(Q, gamma, out=None, stream=None):
+    """Q gamma Q^T by sgs_rotate_noalloc (no work buffer: the library's fixed
+    scratch, n <= 1536); out (device, n x n float64) is allocated here when
+    not given."""
+    import torch
+
+    lib = load_library()
+    n = int(gamma.shape[-1])
+    Q = Q.to(device=gamma.device, dtype=torch.float64).contiguous()
+    g = gamma.contiguous()
+    if out is None:
+        out = torch.empty(n, n, dtype=torch.float64, device=gamma.device)
+    st = stream if stream is not None else torch.cuda.current_stream(gamma.device)
+    _check(lib.sgs_rotate_noalloc(Q.data_ptr(), g.data_ptr(), out.data_ptr(), n, st.cuda_stream),
+           "sgs_rotate_noalloc")
     return out
 
 

@@ -1178,6 +1178,14 @@ int sgs_rotate(const double* Q, const double* gamma, double* work, double* gamma
   return launch_rotate(Q, gamma, work, gamma_out, n, (hipStream_t)stream) == hipSuccess ? SGS_OK : SGS_EHIP;
 }
 
+int sgs_rotate_noalloc(const double* Q, const double* gamma, double* gamma_out, int32_t n, void* stream) {
+  if (!Q || !gamma || !gamma_out || n < 2 || (n & 1)) return SGS_EINVAL;
+  if (n > ROTATE_SCRATCH_N) return SGS_ESCRATCH;
+  double* work = nullptr;
+  if (rotate_scratch(&work) != hipSuccess) return SGS_EHIP;
+  return launch_rotate(Q, gamma, work, gamma_out, n, (hipStream_t)stream) == hipSuccess ? SGS_OK : SGS_EHIP;
+}
+
 int sgs_status(sgs_ctx* c) {
   if (!c) return SGS_EINVAL;
   int st = 0;
@@ -1223,6 +1231,7 @@ const char* sgs_strerror(int code) {
     case SGS_ESTATE: return "call out of order";
     case SGS_EWORKSPACE: return "workspace too small";
     case SGS_ERANGE: return "exponential-map generator too large (or not finite)";
+    case SGS_ESCRATCH: return "size above the allocation-free entry point's fixed scratch";
     default: return "unknown error";
   }
 }

@@ -2,6 +2,8 @@
 // special orthogonal transformation Q, close to the identity, applied to a
 // state of high amplitude: Gamma' = Q Gamma Q^T.  It runs once per added
 // state, so the two products are plain LDS-tiled ones on the vector units.
+#include <mutex>
+
 #include "sgs_internal.h"
 
 namespace sgs {
@@ -45,6 +47,34 @@ __global__ __launch_bounds__(256) void k_rot_skew(double* __restrict__ C, int n)
     C[e] = v;
     C[t] = -v;
   }
+}
+
+// Scratch of the allocation-free variant: the intermediate Q Gamma for
+// n <= ROTATE_SCRATCH_N.  Each device holds its own copy for the life of the
+// process; host code reaches it only through the address hipGetSymbolAddress
+// returns on that device (the array's name is not a device address on the host).
+__device__ __align__(256) double scratch[ROTATE_SCRATCH_N * ROTATE_SCRATCH_N];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t rotate_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[dev] = (double*)p;
+  }
+  *out = scratch_ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_rotate(const double* Q, const double* G, double* work, double* out, int n, hipStream_t s) {

@@ -202,6 +202,10 @@ struct ObsState {
 };
 // Gamma' = Q Gamma Q^T, exactly skew (rotate.hip); work: n*n doubles
 hipError_t launch_rotate(const double* Q, const double* G, double* work, double* out, int n, hipStream_t s);
+// the allocation-free variant's scratch (rotate.hip): n <= ROTATE_SCRATCH_N,
+// address on the current device (looked up once per device)
+constexpr int ROTATE_SCRATCH_N = 1536;
+hipError_t rotate_scratch(double** out);
 
 // Hamiltonian tables for the variance of H (obs.hip): dense A, its upper
 // nonzeros, its compressed columns, the quartic words
