@@ -15,7 +15,8 @@ using namespace sgs;
 
 namespace {
 
-constexpr int GJ_NB_MAX = 32;
+constexpr int GJ_NB_MAX = 32;   // Gauss-Jordan panel width
+constexpr int GJ_SUPER = 128;   // Gauss-Jordan super-panel width (rank of the trailing updates)
 constexpr int PF_NBH_MAX = 16;
 
 struct Arena {
@@ -68,10 +69,15 @@ struct Prob {
   double *ex0 = nullptr, *ex1 = nullptr, *ex2 = nullptr, *ex3 = nullptr, *exrow = nullptr, *expar = nullptr;
   JobTable jexp_p, jexp_y, jexp_z, jexp_h[3], jexp_r, jexp_sq[2], jexp_q, jexp_g;
   ExpCoef excf{};
-  std::vector<JobTable> jgj0, jgj1, jpf;  // GJ updates: pairs (0, a), then the rest
-  std::vector<int> gj_k, gj_b, pf_m;
+  // Gauss-Jordan: inner updates per panel and trailing updates per
+  // super-panel, for the pairs (0, a) (jgj0, jgs0) and the rest (jgj1, jgs1)
+  std::vector<JobTable> jgj0, jgj1, jgs0, jgs1, jpf;
+  std::vector<int> gj_k, gj_b, gj_s, gs_k, gs_nb, pf_m;
   long long uvstride = 0, uv_im = 0;
 };
+
+// per pair: the panel's Brow (b x super-panel) or a super-panel's pivot rows (nb x n)
+long long gj_brow_stride(int n) { return std::max((long long)GJ_NB_MAX * GJ_SUPER, (long long)GJ_SUPER * n); }
 
 int gemm_tiles(int M, int N, int mirror = 0) {
   const int tm = (M + 63) / 64, tn = (N + 63) / 64;
@@ -299,7 +305,7 @@ static void carve_scratch(Prob& q, Arena& ar) {
   q.UV = ar.take<double>(std::max(1LL, Q * q.uvstride));
   q.RM = ar.take<double>(std::max(1LL, Q * q.uvstride));
   q.gjE = ar.take<double>(std::max(1LL, (long long)P * n * GJ_NB_MAX));
-  q.gjB = ar.take<double>(std::max(1LL, (long long)P * n * GJ_NB_MAX));
+  q.gjB = ar.take<double>(std::max(1LL, (long long)P * gj_brow_stride(n)));
   q.dG = ar.take<double>(R * nn);
   q.dP = ar.take<double>(std::max(1LL, (FORCE_SPLIT - 1) * R * nn));  // partial force products, added into dG
   q.dE = ar.take<double>(R * nn);  // elementwise force terms, added into dG
@@ -371,11 +377,27 @@ static void carve_jobs(Prob& q, Arena& ar) {
     t.map_cap = 8 * jobs * T * T;
     t.dmap = ar.take<int>((size_t)t.map_cap);
   };
-  const int ngj = (n + q.gj_nb - 1) / q.gj_nb;
-  q.jgj0.assign(ngj, JobTable());
-  q.jgj1.assign(ngj, JobTable());
-  for (auto& t : q.jgj0) table(t, q.R - 1);
-  for (auto& t : q.jgj1) table(t, q.P - (q.R - 1));
+  // panels and super-panels of the Gauss-Jordan inverse
+  q.gj_k.clear(); q.gj_b.clear(); q.gj_s.clear(); q.gs_k.clear(); q.gs_nb.clear();
+  for (int k0 = 0; k0 < n; k0 += GJ_SUPER) {
+    const int nbs = std::min(GJ_SUPER, n - k0);
+    for (int k = k0; k < k0 + nbs; k += q.gj_nb) {
+      q.gj_k.push_back(k);
+      q.gj_b.push_back(std::min(q.gj_nb, k0 + nbs - k));
+      q.gj_s.push_back((int)q.gs_k.size());
+    }
+    q.gs_k.push_back(k0);
+    q.gs_nb.push_back(nbs);
+  }
+  const int P0 = std::min(q.P, q.R - 1);
+  q.jgj0.assign(q.gj_k.size(), JobTable());
+  q.jgj1.assign(q.gj_k.size(), JobTable());
+  q.jgs0.assign(q.gs_k.size(), JobTable());
+  q.jgs1.assign(q.gs_k.size(), JobTable());
+  for (auto& t : q.jgj0) table(t, P0);
+  for (auto& t : q.jgj1) table(t, q.P - P0);
+  for (auto& t : q.jgs0) table(t, 2 * P0);
+  for (auto& t : q.jgs1) table(t, 2 * (q.P - P0));
   int npf = 0;
   for (int m = n; m > 0; m -= 2 * pf_panel_shape(m).ns) ++npf;
   q.jpf.assign(npf, JobTable());
@@ -617,19 +639,40 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
   HIPCHK(up(q.q_idx, qidxv)); HIPCHK(up(q.q_val, qv));
 
   // --- GEMM job tables ---
-  // Gauss-Jordan updates: M <- M - E Brow per panel
-  q.gj_k.clear(); q.gj_b.clear();
-  for (int k = 0, t = 0; k < n; k += q.gj_nb, ++t) {
-    const int b = std::min(q.gj_nb, n - k);
-    q.gj_k.push_back(k); q.gj_b.push_back(b);
-    // pairs are ordered (0,1) .. (0,R-1), (1,2), ...: the first R - 1 feed the phases
+  // Gauss-Jordan.  Pairs are ordered (0,1) .. (0,R-1), (1,2), ...: the first
+  // R - 1 feed the phases and form their own batch.  Inner update of panel t
+  // (columns [k, k + b) of super-panel [k0, k0 + nbs)):
+  //   M[:, k0:k0+nbs] -= E Brow   (E: n x b, Brow: b x nbs)
+  // trailing update of super-panel s, the columns left and right of it:
+  //   M[:, c] += M[:, k0:k0+nbs] Brow[:, c]   (Brow: nbs x n)
+  const long long bstr = gj_brow_stride(n);
+  for (size_t t = 0; t < q.gj_k.size(); ++t) {
+    const int b = q.gj_b[t], s = q.gj_s[t], k0 = q.gs_k[s], nbs = q.gs_nb[s];
     for (int half = 0; half < 2; ++half) {
       JobTable& jt = half == 0 ? q.jgj0[t] : q.jgj1[t];
       jt.host.clear(); jt.ntiles = 0; jt.late_c = true;
       const int p0 = half == 0 ? 0 : std::min(P, R - 1), p1 = half == 0 ? std::min(P, R - 1) : P;
-      for (int pp = p0; pp < p1; ++pp)
-        add_job(jt, job(q.gjE + (long long)pp * n * GJ_NB_MAX, b, 0, q.gjB + (long long)pp * n * GJ_NB_MAX, n, 0,
-                        q.Di + pp * nn, n, q.Di + pp * nn, n, n, n, b, -1.0, 1.0));
+      if (nbs > b)  // a super-panel of one panel has nothing else to update
+        for (int pp = p0; pp < p1; ++pp)
+          add_job(jt, job(q.gjE + (long long)pp * n * GJ_NB_MAX, b, 0, q.gjB + pp * bstr, nbs, 0,
+                          q.Di + pp * nn + k0, n, q.Di + pp * nn + k0, n, n, nbs, b, -1.0, 1.0));
+      HIPCHK(upload_jobs(jt));
+    }
+  }
+  for (size_t s = 0; s < q.gs_k.size(); ++s) {
+    const int k0 = q.gs_k[s], nbs = q.gs_nb[s];
+    for (int half = 0; half < 2; ++half) {
+      JobTable& jt = half == 0 ? q.jgs0[s] : q.jgs1[s];
+      jt.host.clear(); jt.ntiles = 0; jt.late_c = true;
+      const int p0 = half == 0 ? 0 : std::min(P, R - 1), p1 = half == 0 ? std::min(P, R - 1) : P;
+      for (int pp = p0; pp < p1; ++pp) {
+        double* M = q.Di + pp * nn;
+        const double* Br = q.gjB + pp * bstr;
+        if (k0 > 0) add_job(jt, job(M + k0, n, 0, Br, n, 0, M, n, M, n, n, k0, nbs, 1.0, 1.0));
+        if (k0 + nbs < n)
+          add_job(jt, job(M + k0, n, 0, Br + k0 + nbs, n, 0, M + k0 + nbs, n, M + k0 + nbs, n, n, n - k0 - nbs, nbs,
+                          1.0, 1.0));
+      }
       HIPCHK(upload_jobs(jt));
     }
   }
@@ -773,13 +816,20 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
     // one batch of inverses: panels, grouped updates, unscramble
     auto inverses = [&](int half, hipStream_t st) -> hipError_t {
       const int off = half == 0 ? 0 : P0, cnt = half == 0 ? P0 : P - P0;
+      const long long bstr = gj_brow_stride(n);
       for (size_t t = 0; t < q.gj_k.size(); ++t) {
+        const int s = q.gj_s[t], k0 = q.gs_k[s], nbs = q.gs_nb[s];
         HCHK(launch_gj_panel(q.Di + off * nn, nn, cnt, n, q.gj_k[t], q.gj_b[t],
                              q.gjE + (long long)off * n * GJ_NB_MAX, (long long)n * GJ_NB_MAX,
-                             q.gjB + (long long)off * n * GJ_NB_MAX, (long long)n * GJ_NB_MAX,
+                             q.gjB + off * bstr, bstr, k0, k0 + nbs,
                              q.piv + (long long)off * n, q.piv + (long long)(P + off) * n, q.logdet + off,
                              c->status, st));
         HCHK(run_gemm(half == 0 ? q.jgj0[t] : q.jgj1[t], st));
+        if (t + 1 == q.gj_k.size() || q.gj_s[t + 1] != s) {  // the super-panel's last panel
+          HCHK(launch_gj_gather(q.Di + off * nn, nn, cnt, n, k0, nbs, q.piv + (long long)off * n,
+                                q.gjB + off * bstr, bstr, st));
+          HCHK(run_gemm(half == 0 ? q.jgs0[s] : q.jgs1[s], st));
+        }
       }
       return launch_gj_unscramble(q.Di + off * nn, q.W + off * nn, nn, cnt, n, q.piv + (long long)off * n,
                                   q.piv + (long long)(P + off) * n, st);

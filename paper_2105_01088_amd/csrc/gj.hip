@@ -4,14 +4,26 @@
 // overlap magnitude |<a|b>|^2 = 2^{-N} |det S_ab|^{1/2} (Sec. II.B).
 //
 // Pivoting is virtual: rows never move.  Logical row r of the elimination is
-// physical row piv[r], the row chosen as pivot for column r.  For each column
-// panel J = [k, k+b):
+// physical row piv[r], the row chosen as pivot for column r.  Two levels of
+// column panels: super-panels Js = [k0, k0+nb) of up to 128 columns, each
+// swept by panels J = [k, k+b) of up to 32:
 //   1. k_gj_panel (one workgroup per matrix) sweeps the n x b panel with
 //      partial pivoting over the free rows; with D = (pivot block)^-1 it
 //      writes the multipliers E = M[:, J] D for every row (E_i = e_l - D_l on
 //      the pivot row of position l), the final panel columns (-E_i; D_l on
-//      the pivot rows) and Brow = the pivot rows, zero on J.
-//   2. grouped GEMM: M <- M - E Brow over every row and column.
+//      the pivot rows) and Brow = the pivot rows on Js, zero on J.
+//   2. grouped GEMM: M[:, Js] <- M[:, Js] - E Brow (the other columns of the
+//      super-panel, earlier panels included, take the exchange of J).
+// After its last panel the super-panel holds the exchange of the whole block
+// (exchanges of column blocks compose): with P the pivot rows of Js,
+// M[P, Js] = (M_old[P, Js])^-1 and M[i, Js] = -M_old[i, Js] M_old[P, Js]^-1
+// elsewhere, and the rest of the matrix takes one rank-nb update:
+//   3. k_gj_gather copies Brow = M[P, :] (zero on Js) and clears M[P, :]
+//      outside Js;
+//   4. grouped GEMM: M[:, c] <- M[:, c] + M[:, Js] Brow[:, c] for c outside Js
+//      (on the cleared pivot rows this leaves M[P, Js] Brow, elsewhere the
+//      exchange update), one read and write of the matrix per super-panel
+//      instead of one per panel.
 // Afterwards M[piv[r]][c] = W[r][pi(c)] with pi = piv, and k_gj_unscramble
 // writes W[r][c] = M[piv[r]][piv^-1[c]] into a separate buffer.
 #include "sgs_internal.h"
@@ -44,6 +56,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                                                   int n, int k, int b,
                                                   double* __restrict__ Eall, long long estride,
                                                   double* __restrict__ Ball, long long bstride,
+                                                  int bc0, int bc1,
                                                   int* __restrict__ pivall, int* __restrict__ srcall,
                                                   double* __restrict__ logdet,
                                                   int* __restrict__ status) {
@@ -251,9 +264,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     if (sing) atomicCAS(status, ST_OK, ST_SINGULAR);
   }
   __syncthreads();  // pivl complete
-  // Brow: the pivot rows outside J (zero on J); 16 rows in flight per thread
+  // Brow: the pivot rows on columns [bc0, bc1) (leading dimension
+  // bc1 - bc0), zero on J; 16 rows in flight per thread
+  const int ldbr = bc1 - bc0;
   for (int l0 = 0; l0 < b; l0 += 16) {
-    for (int c = tid; c < n; c += nt) {
+    for (int c = bc0 + tid; c < bc1; c += nt) {
       const bool inj = c >= k && c < k + b;
       double v[16];
 #pragma unroll
@@ -261,7 +276,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         v[u] = (l0 + u < b && !inj) ? M[(long long)pivl[l0 + u] * n + c] : 0.0;
 #pragma unroll
       for (int u = 0; u < 16; ++u)
-        if (l0 + u < b) Br[(long long)(l0 + u) * n + c] = v[u];
+        if (l0 + u < b) Br[(long long)(l0 + u) * ldbr + (c - bc0)] = v[u];
     }
   }
   // panel outputs (pivot rows M[i, J] = D_l, E_i = e_l - D_l; others
@@ -313,6 +328,30 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 }
 
+// Super-panel [k0, k0 + nb) done: Br[l][c] = M[piv[k0 + l]][c] (zero for c in
+// the super-panel), then M[piv[k0 + l]][c] = 0 outside it.  grid (matrices,
+// chunks); each element is read and cleared by the same thread.
+__global__ __launch_bounds__(256) void k_gj_gather(double* __restrict__ Mall, long long mstride, int n, int k0,
+                                                   int nb, const int* __restrict__ pivall, double* __restrict__ Ball,
+                                                   long long bstride) {
+  const int mat = blockIdx.x;
+  double* __restrict__ M = Mall + (long long)mat * mstride;
+  double* __restrict__ Br = Ball + (long long)mat * bstride;
+  const int* __restrict__ piv = pivall + (long long)mat * n + k0;
+  const long long total = (long long)nb * n;
+  for (long long e = (long long)blockIdx.y * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.y * blockDim.x) {
+    const int l = (int)(e / n), c = (int)(e - (long long)l * n);
+    const bool ins = c >= k0 && c < k0 + nb;
+    // (pivot index clamped: a singular matrix, flagged in the status word,
+    // may leave the pivot list short of a permutation)
+    const long long o = (long long)min(max(piv[l], 0), n - 1) * n + c;
+    const double v = ins ? 0.0 : M[o];
+    Br[e] = v;
+    if (!ins) M[o] = 0.0;
+  }
+}
+
 // grid (matrices, row chunks of rpb): W[r][c] = M[piv[r]][src[c]]
 __global__ __launch_bounds__(256) void k_gj_unscramble(const double* __restrict__ Mall, double* __restrict__ Wall,
                                                        long long mstride, int n, const int* __restrict__ pivall,
@@ -337,12 +376,14 @@ __global__ __launch_bounds__(256) void k_gj_unscramble(const double* __restrict_
 }
 
 // Register budget: the panel (n x B doubles) lives in the registers of one
-// workgroup of at most 512 threads, RPT x B doubles per thread.
+// workgroup of at most 512 threads, RPT x B doubles per thread.  Every shape
+// used up to n = 2048 compiles without spilling (32 x 3 spilled 377 VGPRs
+// and took ~1 ms per panel at n = 1204).
 GjPanelShape gj_panel_shape(int n) {
   GjPanelShape sh;
   if (n <= 512) { sh.B = 32; sh.rpt = 1; }
   else if (n <= 1024) { sh.B = 32; sh.rpt = 2; }
-  else if (n <= 1536) { sh.B = 32; sh.rpt = 3; }
+  else if (n <= 1536) { sh.B = 24; sh.rpt = 3; }
   else if (n <= 2048) { sh.B = 16; sh.rpt = 4; }
   else if (n <= 4096) { sh.B = 8; sh.rpt = 8; }
   else { sh.B = 4; sh.rpt = 16; }
@@ -363,21 +404,32 @@ size_t gj_panel_lds_bytes(int n, int k, int b) {
 }
 
 hipError_t launch_gj_panel(double* M, long long mstride, int nmat, int n, int k, int b,
-                           double* E, long long estride, double* Br, long long bstride,
+                           double* E, long long estride, double* Br, long long bstride, int bc0, int bc1,
                            int* piv, int* src, double* logdet, int* status, hipStream_t s) {
   const GjPanelShape sh = gj_panel_shape(n);
   if (b < 1 || b > sh.B || k < 0 || k + b > n || (long long)sh.nt * sh.rpt < n) return hipErrorInvalidValue;
+  if (bc0 < 0 || bc1 > n || bc0 > k || bc1 < k + b || (long long)b * (bc1 - bc0) > bstride)
+    return hipErrorInvalidValue;
   const size_t lds = gj_panel_lds_bytes(n, k, sh.B);
 #define GJ_LAUNCH(BB, RP)                                                                                    \
   hipLaunchKernelGGL((k_gj_panel<BB, RP>), dim3(nmat), dim3(sh.nt), lds, s, M, mstride, n, k, b, E, estride, \
-                     Br, bstride, piv, src, logdet, status)
+                     Br, bstride, bc0, bc1, piv, src, logdet, status)
   if (sh.rpt == 1) GJ_LAUNCH(32, 1);
   else if (sh.rpt == 2) GJ_LAUNCH(32, 2);
-  else if (sh.rpt == 3) GJ_LAUNCH(32, 3);
+  else if (sh.rpt == 3) GJ_LAUNCH(24, 3);
   else if (sh.rpt == 4) GJ_LAUNCH(16, 4);
   else if (sh.rpt == 8) GJ_LAUNCH(8, 8);
   else GJ_LAUNCH(4, 16);
 #undef GJ_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_gj_gather(double* M, long long mstride, int nmat, int n, int k0, int nb, const int* piv,
+                            double* Br, long long bstride, hipStream_t s) {
+  if (nb < 1 || k0 < 0 || k0 + nb > n || (long long)nb * n > bstride) return hipErrorInvalidValue;
+  int chunks = (int)(((long long)nb * n + 255) / 256);
+  if (chunks > 32) chunks = 32;
+  hipLaunchKernelGGL(k_gj_gather, dim3(nmat, chunks), dim3(256), 0, s, M, mstride, n, k0, nb, piv, Br, bstride);
   return hipGetLastError();
 }
 
@@ -396,7 +448,7 @@ hipError_t set_gj_lds_limit(size_t bytes) {
   hipError_t e;
   if ((e = hipFuncSetAttribute((const void*)k_gj_panel<32, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)k_gj_panel<32, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_gj_panel<32, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_gj_panel<24, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)k_gj_panel<16, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)k_gj_panel<8, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_gj_panel<4, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

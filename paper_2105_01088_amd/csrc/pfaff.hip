@@ -307,9 +307,12 @@ size_t pf_panel_lds_bytes(int m, int nbh) {
 
 PfPanelShape pf_panel_shape(int m) {
   PfPanelShape sh;
-  // at most 512 threads (256 VGPRs each): register rows x panel depth fixed
+  // at most 512 threads (256 VGPRs each): register rows x panel depth fixed;
+  // the shapes up to m = 1536 compile without spilling (8 x 2 and 4 x 4
+  // spill 18 and 58 VGPRs: 4 x 4 took ~100 us per step at m = 1204)
   if (m <= 512) { sh.nbh = 16; sh.rpt = 1; }
-  else if (m <= 1024) { sh.nbh = 8; sh.rpt = 2; }
+  else if (m <= 1024) { sh.nbh = 7; sh.rpt = 2; }
+  else if (m <= 1536) { sh.nbh = 4; sh.rpt = 3; }
   else if (m <= 2048) { sh.nbh = 4; sh.rpt = 4; }
   else if (m <= 4096) { sh.nbh = 2; sh.rpt = 8; }
   else { sh.nbh = 1; sh.rpt = 16; }
@@ -330,7 +333,8 @@ hipError_t launch_pf_panel(const double* A, long long astride, long long plane, 
   hipLaunchKernelGGL((k_pf_panel<NB, RP>), dim3(nmat), dim3(sh.nt), lds, s, A, astride, plane, ld, m, L, \
                      RM, lstride, l_im, perm, pstride, acc, first, status)
   if (sh.nbh == 16) PF_LAUNCH(16, 1);
-  else if (sh.nbh == 8) PF_LAUNCH(8, 2);
+  else if (sh.nbh == 7) PF_LAUNCH(7, 2);
+  else if (sh.nbh == 4 && sh.rpt == 3) PF_LAUNCH(4, 3);
   else if (sh.nbh == 4) PF_LAUNCH(4, 4);
   else if (sh.nbh == 2) PF_LAUNCH(2, 8);
   else PF_LAUNCH(1, 16);

@@ -161,9 +161,14 @@ struct GjPanelShape {
 };
 GjPanelShape gj_panel_shape(int n);
 size_t gj_panel_lds_bytes(int n, int k, int b);
+// Brow of the panel covers columns [bc0, bc1) (leading dimension bc1 - bc0)
 hipError_t launch_gj_panel(double* M, long long mstride, int nmat, int n, int k, int b, double* E,
-                           long long estride, double* Br, long long bstride, int* piv, int* src, double* logdet,
-                           int* status, hipStream_t s);
+                           long long estride, double* Br, long long bstride, int bc0, int bc1, int* piv, int* src,
+                           double* logdet, int* status, hipStream_t s);
+// super-panel [k0, k0 + nb) done: Br = its pivot rows (nb x n, zero on the
+// super-panel), which are then cleared outside it
+hipError_t launch_gj_gather(double* M, long long mstride, int nmat, int n, int k0, int nb, const int* piv,
+                            double* Br, long long bstride, hipStream_t s);
 hipError_t launch_gj_unscramble(const double* M, double* W, long long mstride, int nmat, int n, const int* piv,
                                 const int* src, hipStream_t s);
 hipError_t set_gj_lds_limit(size_t bytes);
