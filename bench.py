@@ -40,6 +40,14 @@ def force_flops(n: int, R: int) -> float:
     return R * (R - 1) * 2.0 * n ** 3 + R * 1.0 * n ** 3
 
 
+def _tune_arg(t):
+    if t is None:
+        return None
+    if t.lstrip().startswith("["):
+        return json.loads(t)
+    return t
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +61,9 @@ def main(argv=None):
                     help="exp: the orthogonal exponential-map update instead of Euler + purification")
     ap.add_argument("--dtau", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune", default=None,
+                    help="tuning table: a JSON file written by paper_2105_01088_amd/autotune.py, or an "
+                         "inline JSON list of rows")
     ap.add_argument("--grow", type=int, default=0, metavar="STEPS",
                     help="run the rank-growing protocol (Sec. III.C) on the workload: STEPS steps at "
                          "each rank from 1 to R, one rotated copy of the largest-amplitude state added "
@@ -96,7 +107,8 @@ def main(argv=None):
 
     prec = 1 if args.precision == "fp32" else 0
     upd = 1 if args.update == "exp" else 0
-    ctx = SGS([ham], [gam], options=default_options(weight=weight, precision=prec, update=upd))
+    ctx = SGS([ham], [gam], options=default_options(weight=weight, precision=prec, update=upd,
+                                                    tune=_tune_arg(args.tune)))
     stream = ctx.stream
     # warmup
     e_first = ctx.step(dtau, 1)

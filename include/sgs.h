@@ -99,6 +99,24 @@ typedef struct {
   double e0;             /* constant energy offset                             */
 } sgs_problem;
 
+/* One row of a tuning table (written by the project autotuner,
+ * paper_2105_01088_amd/autotune.py, from measured step times): the row with
+ * the smallest n_max >= n applies to a problem of n Majoranas.  A field <= 0
+ * keeps the library's built-in choice for that n.  Choices change only
+ * scheduling and blocking, never the arithmetic of a result beyond rounding
+ * order. */
+typedef struct {
+  int32_t n_max;     /* largest n the row applies to                          */
+  int32_t gj_super;  /* Gauss-Jordan super-panel width, a multiple of the     */
+                     /* panel width, <= 256 (rank of the trailing updates)    */
+  int32_t gj_first;  /* 1: the pairs (0, a), which feed the overlap phases,   */
+                     /* are inverted before the other pairs start; 2: both    */
+                     /* batches start together                                */
+  int32_t pf_super;  /* Pfaffian: elimination steps per trailing update       */
+                     /* (rank 2 pf_super), 1..64                              */
+  int32_t reserved[4];
+} sgs_tune;
+
 typedef struct {
   int32_t precision;       /* SGS_FP64 (default) or SGS_FP32_REFINE            */
   int32_t weight;          /* SGS_W_PRINTED (default) or SGS_W_UNIT            */
@@ -118,6 +136,9 @@ typedef struct {
                            /* 4 dGamma, so 1/4 makes the first-order term the */
                            /* Euler step; the value printed in App. A, 1/2,   */
                            /* takes a step of 2 dtau)                         */
+  const sgs_tune* tune;    /* host, ntune rows sorted by n_max, read by        */
+  int32_t ntune;           /* sgs_workspace_bytes / sgs_init; NULL / 0: the    */
+                           /* built-in choices (default)                      */
 } sgs_options;
 
 /* Fill *opt with the defaults listed above. */

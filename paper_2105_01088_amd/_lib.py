@@ -39,10 +39,16 @@ class sgs_problem(ctypes.Structure):
                 ("q_idx", POINTER(c_int32)), ("q_val", POINTER(c_double)), ("e0", c_double)]
 
 
+class sgs_tune(ctypes.Structure):
+    _fields_ = [("n_max", c_int32), ("gj_super", c_int32), ("gj_first", c_int32), ("pf_super", c_int32),
+                ("reserved", c_int32 * 4)]
+
+
 class sgs_options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("weight", c_int32), ("g_rel_threshold", c_double),
                 ("purify_tol", c_double), ("purify_iters", c_int32),
-                ("streams", c_int32), ("update", c_int32), ("exp_coef", c_double)]
+                ("streams", c_int32), ("update", c_int32), ("exp_coef", c_double),
+                ("tune", POINTER(sgs_tune)), ("ntune", c_int32)]
 
 
 _lib = None
@@ -91,11 +97,34 @@ def _strerror(code: int) -> str:
         return "?"
 
 
-def default_options(**kw) -> sgs_options:
+def tuning_table(rows) -> ctypes.Array:
+    """sgs_tune rows from dicts {n_max, gj_super, gj_first, pf_super} (missing
+    fields: 0, the library's built-in choice), sorted by n_max."""
+    rows = sorted(rows, key=lambda r: int(r["n_max"]))
+    arr = (sgs_tune * max(1, len(rows)))()
+    for i, r in enumerate(rows):
+        for f in ("n_max", "gj_super", "gj_first", "pf_super"):
+            setattr(arr[i], f, int(r.get(f, 0)))
+    return arr
+
+
+def default_options(tune=None, **kw) -> sgs_options:
+    """Library defaults with the given fields replaced.  tune: a list of
+    tuning rows (dicts, see tuning_table), or a path to the JSON file the
+    autotuner writes."""
     o = sgs_options()
     load_library().sgs_default_options(ctypes.byref(o))
     for k, v in kw.items():
         setattr(o, k, v)
+    if tune is not None:
+        if isinstance(tune, str):
+            import json
+            with open(tune) as f:
+                tune = json.load(f)["rows"]
+        arr = tuning_table(tune)
+        o._tune_rows = arr  # kept alive with the options
+        o.tune = ctypes.cast(arr, POINTER(sgs_tune))
+        o.ntune = len(tune)
     return o
 
 

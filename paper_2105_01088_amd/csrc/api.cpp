@@ -16,7 +16,7 @@ using namespace sgs;
 namespace {
 
 constexpr int GJ_NB_MAX = 32;   // Gauss-Jordan panel width
-constexpr int GJ_SUPER = 128;   // Gauss-Jordan super-panel width (rank of the trailing updates)
+constexpr int GJ_SUPER_MAX = 256;  // Gauss-Jordan super-panel width (rank of the trailing updates), at most
 constexpr int PF_NBH_MAX = 16;
 
 struct Arena {
@@ -45,6 +45,8 @@ struct JobTable {
 struct Prob {
   int N = 0, n = 0, R = 0, P = 0, Q = 0, M = 0, nq = 0, nnz_up = 0, nnz = 0;
   int gj_nb = 16;
+  int gj_super = 128;  // super-panel width (a multiple of gj_nb)
+  bool gj_first = false;  // pairs (0, a) inverted before the others start
   int worker = 0;  // stream (and scratch region) this problem runs on
   bool expmap = false;  // exponential-map update instead of Euler + purification
   bool denseA = false;  // A has many nonzeros per column: Y = Delta A by GEMM
@@ -77,7 +79,7 @@ struct Prob {
 };
 
 // per pair: the panel's Brow (b x super-panel) or a super-panel's pivot rows (nb x n)
-long long gj_brow_stride(int n) { return std::max((long long)GJ_NB_MAX * GJ_SUPER, (long long)GJ_SUPER * n); }
+long long gj_brow_stride(int n) { return std::max((long long)GJ_NB_MAX * GJ_SUPER_MAX, (long long)GJ_SUPER_MAX * n); }
 
 int gemm_tiles(int M, int N, int mirror = 0) {
   const int tm = (M + 63) / 64, tn = (N + 63) / 64;
@@ -379,8 +381,8 @@ static void carve_jobs(Prob& q, Arena& ar) {
   };
   // panels and super-panels of the Gauss-Jordan inverse
   q.gj_k.clear(); q.gj_b.clear(); q.gj_s.clear(); q.gs_k.clear(); q.gs_nb.clear();
-  for (int k0 = 0; k0 < n; k0 += GJ_SUPER) {
-    const int nbs = std::min(GJ_SUPER, n - k0);
+  for (int k0 = 0; k0 < n; k0 += q.gj_super) {
+    const int nbs = std::min(q.gj_super, n - k0);
     for (int k = k0; k < k0 + nbs; k += q.gj_nb) {
       q.gj_k.push_back(k);
       q.gj_b.push_back(std::min(q.gj_nb, k0 + nbs - k));
@@ -440,8 +442,28 @@ constexpr int MAX_WORKERS = 4;  // concurrent streams for independent problems
 // instead of the compressed-column product
 constexpr int DENSE_A_PER_COLUMN = 16;
 
+// Built-in scheduling choices by size, then the caller's tuning row (if any).
+static void pick_tuning(Prob& q, const sgs_options& o) {
+  q.gj_nb = pick_gj_nb(q.n, 0);
+  q.gj_super = 128;
+  // measured at n = 400, 800, 1204: both batches of inverses start together
+  // (with the pairs (0, a) first the phase chain then shares the GPU with the
+  // other inverses for its whole length: 256 instead of 253 ms per step at
+  // n = 1204); super-panels of 128 beat 64 and 256 at all three sizes
+  q.gj_first = false;
+  for (int i = 0; i < o.ntune; ++i) {
+    const sgs_tune& t = o.tune[i];
+    if (q.n > t.n_max) continue;
+    if (t.gj_super > 0) q.gj_super = t.gj_super;
+    if (t.gj_first > 0) q.gj_first = t.gj_first == 1;
+    break;
+  }
+  q.gj_super = std::max(q.gj_nb, std::min(GJ_SUPER_MAX, q.gj_super / q.gj_nb * q.gj_nb));
+}
+
 static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, char* base, int lds_max,
-                   int max_workers, bool expmap, ObsBuf* ob = nullptr, int* nworkers = nullptr) {
+                   int max_workers, bool expmap, const sgs_options& opt, ObsBuf* ob = nullptr,
+                   int* nworkers = nullptr) {
   Arena ar{base, 0};
   ar.take<int>(64);  // status word and spare
   {
@@ -464,7 +486,8 @@ static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, c
     q.M = sp.nq > 0 ? impurity_count(sp) : 0;
     q.nnz = nnz_count(sp, &q.nnz_up);
     q.denseA = q.nnz > DENSE_A_PER_COLUMN * q.n;
-    q.gj_nb = pick_gj_nb(q.n, lds_max);
+    (void)lds_max;
+    pick_tuning(q, opt);
     q.expmap = expmap;
     carve(q, ar);
     carve_jobs(q, ar);
@@ -836,18 +859,22 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
     };
     // the pairs (a, b), 1 <= a < b, on the third stream from the start; the
     // pairs (0, a) on the main stream, then the phase chain forks from it
+    // (with gj_first the third stream starts after the pairs (0, a),
+    // together with the phase chain)
     const bool rest = P - P0 > 0;
-    if (rest) {
+    auto rest_inverses = [&]() -> hipError_t {
       HCHK(hipEventRecord(wk.ev_gj, s));
       HCHK(hipStreamWaitEvent(wk.s3, wk.ev_gj, 0));
       HCHK(launch_pair_sum(q.gam, n, q.pa + P0, q.pb + P0, P - P0, q.Di + P0 * nn, q.logdet + P0, wk.s3));
       HCHK(inverses(1, wk.s3));
-      HCHK(hipEventRecord(wk.ev_gj_done, wk.s3));
-    }
+      return hipEventRecord(wk.ev_gj_done, wk.s3);
+    };
+    if (rest && !q.gj_first) HCHK(rest_inverses());
     if (P0 > 0) {
       HCHK(launch_pair_sum(q.gam, n, q.pa, q.pb, P0, q.Di, q.logdet, s));
       HCHK(inverses(0, s));
     }
+    if (rest && q.gj_first) HCHK(rest_inverses());
     if (fork) {
       // phases on the second stream, concurrent with the other inverses
       HCHK(hipEventRecord(wk.ev_fork, s));
@@ -976,6 +1003,8 @@ void sgs_default_options(sgs_options* o) {
   o->streams = MAX_WORKERS;
   o->update = SGS_UPD_EULER;
   o->exp_coef = 0.25;
+  o->tune = nullptr;
+  o->ntune = 0;
 }
 
 static int check_options(const sgs_options& o) {
@@ -986,6 +1015,12 @@ static int check_options(const sgs_options& o) {
   if (o.streams < 1 || o.streams > MAX_WORKERS) return SGS_EINVAL;
   if (o.update != SGS_UPD_EULER && o.update != SGS_UPD_EXP) return SGS_EINVAL;
   if (!(o.exp_coef > 0.0 && o.exp_coef <= 1e6)) return SGS_EINVAL;
+  if (o.ntune < 0 || o.ntune > 64 || (o.ntune > 0 && !o.tune)) return SGS_EINVAL;
+  for (int i = 0; i < o.ntune; ++i) {
+    const sgs_tune& t = o.tune[i];
+    if (t.n_max < 2 || (i > 0 && t.n_max <= o.tune[i - 1].n_max)) return SGS_EINVAL;
+    if (t.gj_super > GJ_SUPER_MAX || t.gj_first > 2 || t.pf_super > 64) return SGS_EINVAL;
+  }
   return SGS_OK;
 }
 
@@ -999,7 +1034,7 @@ int sgs_workspace_bytes(const sgs_problem* probs, int32_t nprob, const sgs_optio
   for (int p = 0; p < nprob; ++p)
     if ((rc = check_problem(probs[p]))) return rc;
   std::vector<Prob> pr;
-  *bytes = plan(pr, probs, nprob, nullptr, device_lds_max(), o.streams, o.update == SGS_UPD_EXP);
+  *bytes = plan(pr, probs, nprob, nullptr, device_lds_max(), o.streams, o.update == SGS_UPD_EXP, o);
   return SGS_OK;
 }
 
@@ -1021,7 +1056,9 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
   c->lds_max = device_lds_max();
   int nworkers = 1;
   const size_t need = plan(c->pr, probs, nprob, (char*)workspace, c->lds_max, c->opt.streams,
-                           c->opt.update == SGS_UPD_EXP, &c->obs, &nworkers);
+                           c->opt.update == SGS_UPD_EXP, c->opt, &c->obs, &nworkers);
+  c->opt.tune = nullptr;  // read above; the caller's table need not outlive init
+  c->opt.ntune = 0;
   if (ws_bytes < need) { delete c; return SGS_EWORKSPACE; }
   c->status = (int*)workspace;
   double* g = gamma;
