@@ -76,13 +76,51 @@ def solve_amplitudes(G: np.ndarray, h: np.ndarray, rel_threshold: float = 1e-12)
     return float(e[0]), lam
 
 
+# Vanishing amplitudes (Sec. III.A notes that the printed choice diverges as
+# some lambda_mu -> 0; the paper fixes no rule).  Readings used here and by
+# the GPU path:
+#  * printed: the force on mu carries lambda_b / lambda_mu.  The self term
+#    (b = mu) is exactly 1; when |lambda_mu| <= LAMBDA_FLOOR max|lambda| the
+#    cross terms (b != mu) are dropped: lambda_mu is then at the rounding floor
+#    of any float64 eigen-solver (LAPACK's tridiagonal solvers return exact
+#    zeros there) and the ratio carries no information.
+#  * unit: w_mu lambda_b = |lambda~_mu| (lambda_mu^* / |lambda_mu|) lambda_b with
+#    the phase lambda_mu^* / |lambda_mu| read as 1 when lambda_mu = 0.
+LAMBDA_FLOOR = 1e-13
+
+
 def weights(lam: np.ndarray, lamt: np.ndarray, mode: str = "printed") -> np.ndarray:
-    """c_mu of Eq. (Bmu)."""
+    """c_mu of Eq. (Bmu): printed 1 / (lambda_mu lambda~_mu^*), or the
+    unit-modulus lambda~_mu lambda_mu^* / |lambda~_mu lambda_mu| (phase of a
+    vanishing product read as the phase of lambda~_mu, i.e. lambda_mu's as 1)."""
     if mode == "printed":
-        return 1.0 / (lam * lamt.conj())
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return 1.0 / (lam * lamt.conj())
     if mode == "unit":
-        return lamt * lam.conj() / np.abs(lamt * lam)
+        ph_lam = np.ones(lam.shape, dtype=complex)
+        nz = np.abs(lam) > 0
+        ph_lam[nz] = lam[nz].conj() / np.abs(lam[nz])
+        ph_lt = np.ones(lam.shape, dtype=complex)
+        nzt = np.abs(lamt) > 0
+        ph_lt[nzt] = lamt[nzt] / np.abs(lamt[nzt])
+        return ph_lt * ph_lam
     raise ValueError(mode)
+
+
+def term_weights(lam: np.ndarray, lamt: np.ndarray, mode: str = "printed") -> np.ndarray:
+    """K[mu, b] = c_mu lambda~_mu^* lambda_b, the factor of the (mu, b) term of
+    Eq. (EOM-Gamma3), with the readings for vanishing amplitudes above."""
+    R = lam.shape[0]
+    if mode == "printed":
+        K = np.zeros((R, R), dtype=complex)
+        lmax = np.abs(lam).max()
+        for mu in range(R):
+            if np.abs(lam[mu]) > LAMBDA_FLOOR * lmax:
+                K[mu] = lam / lam[mu]
+            K[mu, mu] = 1.0
+        return K
+    c = weights(lam, lamt, mode)
+    return (c * lamt.conj())[:, None] * lam[None, :]
 
 
 def forces(ham, gammas: np.ndarray, tab: PairTables, E: float, lam: np.ndarray,
@@ -91,7 +129,7 @@ def forces(ham, gammas: np.ndarray, tab: PairTables, E: float, lam: np.ndarray,
     R, n, _ = gammas.shape
     G, h = tab.G, tab.h
     lamt = G @ lam
-    c = weights(lam, lamt, mode)
+    Kw = term_weights(lam, lamt, mode)
     Ginv_h = np.linalg.solve(G, h)
     qt = quartic_tensor(ham)
     out = np.zeros((R, n, n))
@@ -110,7 +148,7 @@ def forces(ham, gammas: np.ndarray, tab: PairTables, E: float, lam: np.ndarray,
                     + 2.0 * G[mu, b] * (DF @ D[b] + F.toarray())
                     - h[mu, b] * D[b]
                     + norm_terms[b])
-            acc += lam[b] * np.conj(lamt[mu]) * c[mu] * term
+            acc += Kw[mu, b] * term
         out[mu] = (acc + acc.conj()).real
     return out
 

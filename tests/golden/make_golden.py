@@ -1,13 +1,23 @@
 """Write the stored expected values under tests/golden/ from the oracle only.
 
-Run from the repository root:  python tests/golden/make_golden.py
+Run from the repository root:
+
+    python tests/golden/make_golden.py small        # anderson_L7.json (seconds)
+    python tests/golden/make_golden.py traj400      # anderson_L99_R16_traj500.json (hours)
+    python tests/golden/make_golden.py step800      # anderson_L199_R32_U1_step.json (minutes)
+    python tests/golden/make_golden.py step1204     # tck_L150_R24_J0.3_step.json (minutes)
+
 Each value records the oracle routine that produced it and the passage of
-Boutin & Bauer (arXiv:2105.01088) it follows.
+Boutin & Bauer (arXiv:2105.01088) it follows.  Inputs come from sgs_inputs
+(seeded states and model Hamiltonians); every number is computed by oracle/.
 """
 
 import json
 import os
 import sys
+import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
@@ -15,8 +25,11 @@ sys.path.insert(0, ROOT)
 import sgs_inputs as si  # noqa: E402
 from oracle import ed, sgs  # noqa: E402
 
+HERE = os.path.join(ROOT, "tests", "golden")
+STEP_CITE = "Eqs. (eigLambda), (EOM-Gamma3), (RKstep), (CM-normal-form)"
 
-def main():
+
+def small():
     out = {}
     # Anderson impurity, L = 7 bath sites per spin (N = 16 modes): even-sector ED
     # bound for the variational energies (Sec. III.C: energy descent; Sec. II.C).
@@ -24,15 +37,75 @@ def main():
     out["anderson_L7_U1_V0.5_ed_even"] = dict(
         value=ed.even_sector_ground_energy(N, terms),
         source="oracle.ed.even_sector_ground_energy", cite="Sec. IV model, even parity sector")
-    # first 10 step energies of the seeded R = 4 trajectory (printed weights, dtau = 0.05)
+    # the seeded R = 4 trajectory (printed weights, dtau = 0.05): the first 10
+    # step energies, and all 200 of the configured run
     ham, gam, cfg = si.config_problem("anderson_L7_R4")
-    _, es = sgs.run(ham, gam, 0.05, 10)
+    _, es = sgs.run(ham, gam, 0.05, 200)
     out["anderson_L7_R4_seed0_first10_E"] = dict(
-        value=[float(x) for x in es], source="oracle.sgs.run",
-        cite="Eqs. (eigLambda), (EOM-Gamma3), (RKstep), (CM-normal-form)")
-    with open(os.path.join(ROOT, "tests", "golden", "anderson_L7.json"), "w") as f:
+        value=[float(x) for x in es[:10]], source="oracle.sgs.run", cite=STEP_CITE)
+    out["anderson_L7_R4_seed0_200_E"] = dict(
+        value=[float(x) for x in es], source="oracle.sgs.run (200 steps, printed weights)", cite=STEP_CITE)
+    with open(os.path.join(HERE, "anderson_L7.json"), "w") as f:
         json.dump(out, f, indent=1)
 
 
+def traj400(steps=500):
+    """Energies of the 500-step benchmark trajectory (n = 400, R = 16, unit
+    weights), with the final states' sampled entries."""
+    ham, gam, cfg = si.config_problem("anderson_L99_R16")
+    hp = ham.poly()
+    es = []
+    g = gam
+    t0 = time.time()
+    for k in range(steps):
+        r = sgs.step(ham, g, 0.05, mode="unit", hpoly=hp)
+        es.append(float(r.E))
+        g = r.gammas
+        print(f"step {k} E={r.E:.15f} t={time.time() - t0:.0f}s", flush=True)
+    E_end, _, _ = sgs.energy(ham, g, hpoly=hp)
+    out = dict(workload="anderson_L99_R16", weights="unit", dtau=0.05, steps=steps,
+               source="oracle.sgs.step (unit weights), oracle.sgs.energy", cite=STEP_CITE,
+               energies=es, E_end=float(E_end))
+    out.update(_samples(g, seed=400))
+    with open(os.path.join(HERE, "anderson_L99_R16_traj500.json"), "w") as f:
+        json.dump(out, f)
+
+
+def _samples(g, seed, count=4096):
+    R, n, _ = g.shape
+    rng = np.random.default_rng(seed)
+    idx = np.stack([rng.integers(0, R, count), rng.integers(0, n, count), rng.integers(0, n, count)], axis=1)
+    return dict(sample_idx=idx.tolist(), sample_val=[float(g[m, i, j]) for m, i, j in idx])
+
+
+def one_step(name, seed):
+    """Tables, energy and the new states (sampled entries, per-state norms of
+    the change) of one step from the seeded states of a full-size workload."""
+    ham, gam, cfg = si.config_problem(name)
+    t0 = time.time()
+    r = sgs.step(ham, gam, 0.05, mode="unit")
+    print(f"{name}: one step in {time.time() - t0:.0f} s, E = {r.E}", flush=True)
+    tab = r.tables
+    out = dict(workload=name, weights="unit", dtau=0.05,
+               source="oracle.sgs.step (unit weights)", cite=STEP_CITE,
+               E=float(r.E), logabs=tab.logabs.tolist(), arg=tab.arg.tolist(),
+               eps_re=tab.eps.real.tolist(), eps_im=tab.eps.imag.tolist(),
+               dgamma_max=float(np.abs(r.dgamma).max()),
+               change_norm=[float(np.linalg.norm(r.gammas[m] - gam[m])) for m in range(gam.shape[0])])
+    out.update(_samples(r.gammas, seed=seed))
+    with open(os.path.join(HERE, f"{name}_step.json"), "w") as f:
+        json.dump(out, f)
+
+
 if __name__ == "__main__":
-    main()
+    what = sys.argv[1] if len(sys.argv) > 1 else "small"
+    if what == "small":
+        small()
+    elif what == "traj400":
+        traj400()
+    elif what == "step800":
+        one_step("anderson_L199_R32_U1", seed=800)
+    elif what == "step1204":
+        one_step("tck_L150_R24_J0.3", seed=1204)
+    else:
+        raise SystemExit(f"unknown golden: {what}")
