@@ -62,14 +62,22 @@ def pair_tables(ham, gammas: np.ndarray, use_direct: bool = False, hpoly=None) -
     return PairTables(G=G, h=h, logabs=la, arg=ar, eps=eps)
 
 
+def canonical_basis(G: np.ndarray, rel_threshold: float = 1e-12) -> np.ndarray:
+    """X = U_kept diag(s_kept)^(-1/2) of canonical orthogonalization: the
+    eigenvectors of (the Hermitian part of) G whose eigenvalue exceeds
+    rel_threshold * the largest; X^dag G X = 1, and X X^dag is the inverse of G
+    on the kept subspace (G^-1 itself when nothing is dropped)."""
+    Gh = 0.5 * (G + G.conj().T)
+    s, U = np.linalg.eigh(Gh)
+    keep = s > rel_threshold * s.max()
+    return U[:, keep] / np.sqrt(s[keep])[None, :]
+
+
 def solve_amplitudes(G: np.ndarray, h: np.ndarray, rel_threshold: float = 1e-12):
     """Lowest (E, lambda) of h lambda = E G lambda after canonical orthogonalization
     (eigenvectors of G below rel_threshold * max eigenvalue are dropped)."""
-    Gh = 0.5 * (G + G.conj().T)
     hh = 0.5 * (h + h.conj().T)
-    s, U = np.linalg.eigh(Gh)
-    keep = s > rel_threshold * s.max()
-    X = U[:, keep] / np.sqrt(s[keep])[None, :]
+    X = canonical_basis(G, rel_threshold)
     hp = X.conj().T @ hh @ X
     e, y = np.linalg.eigh(0.5 * (hp + hp.conj().T))
     lam = X @ y[:, 0]
@@ -79,11 +87,11 @@ def solve_amplitudes(G: np.ndarray, h: np.ndarray, rel_threshold: float = 1e-12)
 # Vanishing amplitudes (Sec. III.A notes that the printed choice diverges as
 # some lambda_mu -> 0; the paper fixes no rule).  Readings used here and by
 # the GPU path:
-#  * printed: the force on mu carries lambda_b / lambda_mu.  The self term
-#    (b = mu) is exactly 1; when |lambda_mu| <= LAMBDA_FLOOR max|lambda| the
-#    cross terms (b != mu) are dropped: lambda_mu is then at the rounding floor
-#    of any float64 eigen-solver (LAPACK's tridiagonal solvers return exact
-#    zeros there) and the ratio carries no information.
+#  * printed: the force on mu carries lambda_b / lambda_mu (exactly 1 for
+#    b = mu).  When |lambda_mu| <= LAMBDA_FLOOR max|lambda|, lambda_mu is at
+#    the rounding floor of any float64 eigen-solver (LAPACK's tridiagonal
+#    solvers return exact zeros there), the ratio carries no information, and
+#    the state is left unchanged by the step (its weight is 0).
 #  * unit: w_mu lambda_b = |lambda~_mu| (lambda_mu^* / |lambda_mu|) lambda_b with
 #    the phase lambda_mu^* / |lambda_mu| read as 1 when lambda_mu = 0.
 LAMBDA_FLOOR = 1e-13
@@ -117,20 +125,26 @@ def term_weights(lam: np.ndarray, lamt: np.ndarray, mode: str = "printed") -> np
         for mu in range(R):
             if np.abs(lam[mu]) > LAMBDA_FLOOR * lmax:
                 K[mu] = lam / lam[mu]
-            K[mu, mu] = 1.0
+                K[mu, mu] = 1.0
         return K
     c = weights(lam, lamt, mode)
     return (c * lamt.conj())[:, None] * lam[None, :]
 
 
 def forces(ham, gammas: np.ndarray, tab: PairTables, E: float, lam: np.ndarray,
-           mode: str = "printed") -> np.ndarray:
-    """dGamma_mu / ds for every state, Eq. (EOM-Gamma3) in its printed long form."""
+           mode: str = "printed", rel_threshold: float = 1e-12) -> np.ndarray:
+    """dGamma_mu / ds for every state, Eq. (EOM-Gamma3) in its printed long form.
+
+    G^-1 in the projector of Eq. (projImEvol) is read, like the amplitude
+    solve, through canonical orthogonalization: X X^dag, the inverse of G on
+    the kept subspace (G^-1 when nothing is dropped).  Then V X X^dag V^dag is
+    the orthogonal projector onto the span of the kept combinations of states."""
     R, n, _ = gammas.shape
     G, h = tab.G, tab.h
     lamt = G @ lam
     Kw = term_weights(lam, lamt, mode)
-    Ginv_h = np.linalg.solve(G, h)
+    X = canonical_basis(G, rel_threshold)
+    Ginv_h = X @ (X.conj().T @ h)
     qt = quartic_tensor(ham)
     out = np.zeros((R, n, n))
     for mu in range(R):
@@ -194,7 +208,7 @@ def step(ham, gammas: np.ndarray, dtau: float, mode: str = "printed",
     (Eq. ExpStep), update = "euler" | "exp"."""
     tab = pair_tables(ham, gammas, hpoly=hpoly)
     E, lam = solve_amplitudes(tab.G, tab.h, rel_threshold)
-    dg = forces(ham, gammas, tab, E, lam, mode)
+    dg = forces(ham, gammas, tab, E, lam, mode, rel_threshold)
     if update == "exp":
         new = np.stack([exp_update(gammas[m], dg[m], dtau) for m in range(gammas.shape[0])])
     else:

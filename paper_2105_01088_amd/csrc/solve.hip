@@ -300,11 +300,15 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     const double lm2 = lr[mu] * lr[mu] + li[mu] * li[mu];
     if (a.weight == 0) {
       // c_mu = 1 / (lambda_mu lambda~_mu^*):  w_mu lambda_b = lambda_b / lambda_mu
-      if (b == mu) { rr = 1.0; ri = 0.0; }
-      else if (sqrt(lm2) > 1e-13 * lmax) {
+      // (exactly 1 for b = mu).  The printed weight diverges as lambda_mu -> 0
+      // (Sec. III.A); a state at the float64 floor (|lambda_mu| <= 1e-13
+      // max|lambda|, where the ratio carries no information) is left unchanged.
+      if (!(sqrt(lm2) > 1e-13 * lmax)) { rr = 0.0; ri = 0.0; }
+      else if (b == mu) { rr = 1.0; ri = 0.0; }
+      else {
         rr = (lr[b] * lr[mu] + li[b] * li[mu]) / lm2;
         ri = (li[b] * lr[mu] - lr[b] * li[mu]) / lm2;
-      } else { rr = 0.0; ri = 0.0; }
+      }
     } else {
       // c_mu = lambda~_mu lambda_mu^* / |lambda~_mu lambda_mu|:
       // w_mu lambda_b = |lambda~_mu| (lambda_mu^* / |lambda_mu|) lambda_b

@@ -21,5 +21,5 @@ from .models import (  # noqa: F401
     siam_mode,
     wilson_hoppings,
 )
-from .states import vacuum_cm, haar_so, random_states, small_rotations  # noqa: F401
+from .states import vacuum_cm, haar_so, random_states, small_rotations, near_copy_states  # noqa: F401
 from .configs import CONFIGS, config_problem, batched_problems  # noqa: F401

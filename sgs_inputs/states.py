@@ -59,3 +59,18 @@ def small_rotations(n: int, count: int, eps: float, seed: int = 0) -> list:
         k = z - z.T
         out.append(scipy.linalg.expm(eps * k / np.linalg.norm(k)))
     return out
+
+
+def near_copy_states(N: int, R: int, eps: float, seed: int = 0) -> np.ndarray:
+    """(R, 2N, 2N) chain of states, each a small seeded special orthogonal
+    rotation (|Q - 1|_F ~ eps, as in small_rotations) of the previous one,
+    starting from a Haar-random state: the near-linearly-dependent ansatz that
+    rank growing (Sec. III.C) produces, with an ill-conditioned Gram matrix."""
+    n = 2 * N
+    out = np.empty((R, n, n))
+    out[0] = random_states(N, 1, seed=seed)[0]
+    rots = small_rotations(n, R - 1, eps, seed=seed + 1)
+    for mu in range(1, R):
+        g = rots[mu - 1] @ out[mu - 1] @ rots[mu - 1].T
+        out[mu] = 0.5 * (g - g.T)
+    return out

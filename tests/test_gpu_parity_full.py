@@ -1,0 +1,261 @@
+"""Parity of the HIP path with the CPU oracle at the workloads' full sizes,
+over whole trajectories, and on ill-conditioned Gram matrices.
+
+Expected values at n = 800 and n = 1204 (one oracle step takes minutes) and
+of the 500-step n = 400 trajectory (hours) come from tests/golden/, written by
+tests/golden/make_golden.py, which calls only oracle/.  The smaller cases run
+the oracle in the test.
+
+Tolerances (float64 path): tables at 1e-9 relative, energies at 1e-10
+relative, covariance matrices at 1e-10 absolute (the inverse and Pfaffian
+lose about cond(Gamma_a + Gamma_b) n eps, a few hundred to a few thousand
+here).  With printed weights the force on state mu carries lambda_b /
+lambda_mu; its tolerance is derived from the eigen-solver's backward error
+(tests/parity_tol.py) and printed next to the error found.
+"""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import sgs_inputs as si
+from oracle import sgs as osgs
+from parity_tol import energy_tol, printed_tol
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_TAB = 1e-9
+TOL_GAMMA = 1e-10
+TOL_E = 1e-10
+EPS = np.finfo(float).eps
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _ctx(ham, gam, weight=0, **kw):
+    from paper_2105_01088_amd import SGS, default_options
+    return SGS([ham], [gam], options=default_options(weight=weight, **kw))
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated (python tests/golden/make_golden.py)")
+    with open(path) as f:
+        return json.load(f)
+
+
+def _samples(g, gold):
+    idx = np.array(gold["sample_idx"])
+    return g[idx[:, 0], idx[:, 1], idx[:, 2]], np.array(gold["sample_val"])
+
+
+# ------------------------------------------------------- full-size one step
+
+@pytest.mark.parametrize("name", ["anderson_L199_R32_U1", "tck_L150_R24_J0.3"])
+def test_full_size_one_step_fp64(name):
+    """One FP64 step at n = 800 (R = 32) and n = 1204 (R = 24), unit weights,
+    in bench.py's launch configuration: every table entry, the energy, 4096
+    sampled entries of the new states and each state's |Gamma' - Gamma|_F."""
+    gold = _golden(f"{name}_step.json")
+    ham, gam, cfg = si.config_problem(name)
+    R, n = gam.shape[0], gam.shape[1]
+    _say(f"[step] {name} (n={n}, R={R}) fp64 against the oracle golden")
+    ctx = _ctx(ham, gam, weight=1)
+    la, ar, ep = ctx.pair_eval()
+    la = la.cpu().numpy().reshape(R, R)
+    ar = ar.cpu().numpy().reshape(R, R)
+    ep = ep.cpu().numpy().reshape(R, R, 2)
+    ep = ep[..., 0] + 1j * ep[..., 1]
+    off = ~np.eye(R, dtype=bool)
+    rla = np.array(gold["logabs"])
+    reps = np.array(gold["eps_re"]) + 1j * np.array(gold["eps_im"])
+    e_la = np.abs(la - rla)[off].max() / np.abs(rla).max()
+    e_ph = np.abs(np.exp(1j * ar) - np.exp(1j * np.array(gold["arg"]))).max()
+    e_ep = np.abs(ep - reps).max() / max(1.0, np.abs(reps).max())
+    _say(f"  tables: log|G| {e_la:.2e}  phase {e_ph:.2e}  eps {e_ep:.2e}")
+    assert e_la < TOL_TAB and e_ep < TOL_TAB
+    # the phase accumulates n / 2 pivots of Pf(C_ab), each within about
+    # kappa eps of its exact value; these random states are nearly orthogonal
+    # (|G_ab| ~ e^-100 .. e^-200) and kappa reaches ~1e5: n 1e-11 here
+    assert e_ph < 1e-11 * n
+    e = ctx.step(0.05, 1)
+    assert ctx.status() == 0
+    e = e.cpu().item()
+    g_new = ctx.gammas(0).cpu().numpy()
+    got, want = _samples(g_new, gold)
+    err = np.abs(got - want).max()
+    _say(f"  E err {abs(e - gold['E']) / abs(gold['E']):.2e}  Gamma sample err {err:.2e}")
+    assert abs(e - gold["E"]) < TOL_E * abs(gold["E"])
+    assert err < TOL_GAMMA
+    cn = np.array([np.linalg.norm(g_new[m] - gam[m]) for m in range(R)])
+    assert np.abs(cn - np.array(gold["change_norm"])).max() < TOL_GAMMA * n
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["anderson_L199_R32_U1", "tck_L150_R24_J0.3"])
+def test_full_size_one_step_fp32(name):
+    """The FP32 path against the same FP64 oracle step: the energy entering
+    the step does not see the force (1e-10), the new states differ by the
+    float32 rounding of the force product, bounded by 1e-5 dtau max|dGamma|
+    (float epsilon 6e-8 times a product depth 2 n R with cancellation)."""
+    gold = _golden(f"{name}_step.json")
+    ham, gam, cfg = si.config_problem(name)
+    _say(f"[fp32] {name} one step against the oracle golden")
+    ctx = _ctx(ham, gam, weight=1, precision=1)
+    e = ctx.step(0.05, 1)
+    assert ctx.status() == 0
+    e = e.cpu().item()
+    got, want = _samples(ctx.gammas(0).cpu().numpy(), gold)
+    err = np.abs(got - want).max()
+    bound = 1e-5 * 0.05 * gold["dgamma_max"]
+    _say(f"  E err {abs(e - gold['E']) / abs(gold['E']):.2e}  Gamma sample err {err:.2e} (bound {bound:.2e})")
+    assert abs(e - gold["E"]) < TOL_E * abs(gold["E"])
+    assert err < bound
+    ctx.close()
+
+
+# ------------------------------------------------------------ trajectories
+
+def test_anderson_L7_full_trajectory():
+    """The configured n = 32, R = 4 run: 200 steps (printed weights) against
+    the oracle's energies at 1e-10, monotone descent (Sec. III.A) and the
+    even-sector exact-diagonalization bound (Sec. II.C)."""
+    gold = _golden("anderson_L7.json")
+    ham, gam, cfg = si.config_problem("anderson_L7_R4")
+    _say("[trajectory] anderson L=7 R=4, 200 steps")
+    ctx = _ctx(ham, gam)
+    e = ctx.step(0.05, 200).cpu().numpy()
+    assert ctx.status() == 0
+    ref = np.array(gold["anderson_L7_R4_seed0_200_E"]["value"])
+    err = np.abs(e - ref) / np.abs(ref)
+    _say(f"  max rel err over 200 steps {err.max():.2e}, final {err[-1]:.2e}")
+    assert err.max() < TOL_E
+    e_ed = gold["anderson_L7_U1_V0.5_ed_even"]["value"]
+    assert np.all(e >= e_ed - 1e-12)
+    assert np.all(np.diff(e) <= 1e-12 * np.abs(e).max())
+    for x in ctx.gammas(0).cpu().numpy():
+        assert np.abs(x + x.T).max() == 0.0
+        assert np.abs(x @ x + np.eye(x.shape[0])).max() < 1e-12
+    ctx.close()
+
+
+def test_anderson_L99_R16_500_steps():
+    """The benchmark workload over its configured 500 steps (unit weights)
+    against the oracle's trajectory: every step's energy at 1e-10 relative,
+    and the end state's sampled entries."""
+    gold = _golden("anderson_L99_R16_traj500.json")
+    ham, gam, cfg = si.config_problem("anderson_L99_R16")
+    _say("[trajectory] anderson_L99_R16, 500 steps")
+    ctx = _ctx(ham, gam, weight=1)
+    e = ctx.step(0.05, gold["steps"]).cpu().numpy()
+    assert ctx.status() == 0
+    E_end, _ = ctx.energy()
+    ref = np.array(gold["energies"])
+    err = np.abs(e - ref) / np.abs(ref)
+    got, want = _samples(ctx.gammas(0).cpu().numpy(), gold)
+    end_err = abs(E_end.cpu().item() - gold["E_end"]) / abs(gold["E_end"])
+    _say(f"  max rel err over {len(ref)} steps {err.max():.2e}, end {end_err:.2e}, "
+         f"state sample err {np.abs(got - want).max():.2e}")
+    assert err.max() < TOL_E and end_err < TOL_E
+    assert np.abs(got - want).max() < 1e-8
+    ctx.close()
+
+
+def test_anderson_L99_R16_fp32_energy_error():
+    """Precision path over the benchmark trajectory: after 20 and 100 steps the
+    FP32-force energies stay within 1e-8 relative of the FP64 oracle's."""
+    gold = _golden("anderson_L99_R16_traj500.json")
+    ham, gam, cfg = si.config_problem("anderson_L99_R16")
+    _say("[fp32] anderson_L99_R16, 100 steps against the oracle trajectory")
+    ctx = _ctx(ham, gam, weight=1, precision=1)
+    e = ctx.step(0.05, 100).cpu().numpy()
+    assert ctx.status() == 0
+    ref = np.array(gold["energies"][:100])
+    err = np.abs(e - ref) / np.abs(ref)
+    _say(f"  rel err at step 20 {err[19]:.2e}, max over 100 steps {err.max():.2e}")
+    assert err.max() < 1e-8
+    ctx.close()
+
+
+# -------------------------------------------------- ill-conditioned G, weights
+
+def _step_against_oracle(ham, gam, weight, tag):
+    _say(f"[step] {tag} n={gam.shape[1]} R={gam.shape[0]} weight={'printed' if weight == 0 else 'unit'}")
+    ctx = _ctx(ham, gam, weight=weight)
+    e = ctx.step(0.05, 1)
+    assert ctx.status() == 0
+    g_new = ctx.gammas(0).cpu().numpy()
+    ctx.close()
+    ref = osgs.step(ham, gam, 0.05, mode="printed" if weight == 0 else "unit")
+    return e.cpu().item(), g_new, ref
+
+
+@pytest.mark.parametrize("eps_rot", [0.03, 0.01])
+@pytest.mark.parametrize("weight", [0, 1])
+def test_near_copy_states_n400(weight, eps_rot):
+    """Six states, each a rotation |Q - 1|_F = eps of the previous one (the
+    ansatz rank growing builds): cond(G) ~ 2e5 (0.03) and 2e6 (0.01) at
+    n = 400, all amplitudes of the same order.  Printed and unit weights, one
+    step at 1e-10 plus the eigen-solver's backward-error terms (which reach a
+    few 1e-10 at cond(G) = 2e6, where no float64 solver does better): this
+    pins the compact force form (the GPU's) against the printed long form
+    (the oracle's) where G is far from the identity."""
+    gam = si.near_copy_states(200, 6, eps_rot, seed=5)
+    ham = si.anderson(99, 1.0, 0.5)
+    e, g_new, ref = _step_against_oracle(ham, gam, weight, f"near copies eps={eps_rot}")
+    s = np.linalg.eigvalsh(0.5 * (ref.tables.G + ref.tables.G.conj().T))
+    err = np.abs(g_new - ref.gammas).reshape(6, -1).max(axis=1)
+    tol = printed_tol(ref, 0.05)[0]
+    _say(f"  cond(G) {s.max() / s.min():.1e}, |lambda| {np.round(np.abs(ref.lam), 2)}, "
+         f"err {err.max():.2e}, tol {tol.min():.2e}..{tol.max():.2e}; "
+         f"E err {abs(e - ref.E) / abs(ref.E):.2e}, tol {energy_tol(ref):.2e}")
+    assert s.max() / s.min() > 1e5
+    assert abs(e - ref.E) < energy_tol(ref) * abs(ref.E)
+    assert np.all(err < tol)
+
+
+@pytest.mark.parametrize("weight", [0, 1])
+def test_dropped_combination(weight):
+    """A state that is a rotation |Q - 1|_F = 1e-7 of another: G has an
+    eigenvalue below 1e-12 of its largest, canonical orthogonalization keeps
+    R - 1 combinations, and the force uses the inverse of G on them (both
+    paths).  The near-duplicate pair magnifies float64 rounding by ~1e7, so
+    the covariance tolerance is 1e7 eps dtau max|dGamma| on top of 1e-10."""
+    ham = si.anderson(15, 1.2, 0.5)
+    g0 = si.random_states(ham.N, 3, seed=8)
+    q = si.small_rotations(ham.n, 1, 1e-7, seed=9)[0]
+    g3 = q @ g0[2] @ q.T
+    gam = np.concatenate([g0, (0.5 * (g3 - g3.T))[None]])
+    e, g_new, ref = _step_against_oracle(ham, gam, weight, "dropped combination")
+    assert osgs.canonical_basis(ref.tables.G).shape[1] == 3
+    err = np.abs(g_new - ref.gammas).max()
+    tol = TOL_GAMMA + 1e7 * EPS * 0.05 * np.abs(ref.dgamma).max()
+    _say(f"  err {err:.2e}, tol {tol:.2e}")
+    assert abs(e - ref.E) < TOL_E * abs(ref.E)
+    assert err < tol
+
+
+def test_printed_weights_n400_random_states():
+    """Printed weights on the benchmark's seeded random states (n = 400,
+    R = 16), which are nearly orthogonal: amplitudes range over many orders
+    of magnitude, so each state's tolerance follows its own amplification
+    (parity_tol.printed_tol).  States at the 1e-13 amplitude floor are left
+    unchanged by both paths; every other one is held to 1e-10 plus its
+    eigen-solver term."""
+    ham, gam, cfg = si.config_problem("anderson_L99_R16")
+    e, g_new, ref = _step_against_oracle(ham, gam, 0, "anderson_L99_R16 printed")
+    tol, amp = printed_tol(ref, 0.05)
+    err = np.abs(g_new - ref.gammas).reshape(gam.shape[0], -1).max(axis=1)
+    for mu in range(gam.shape[0]):
+        _say(f"  state {mu:2d} |lambda| {abs(ref.lam[mu]):.2e} amp {amp[mu]:.1e} err {err[mu]:.2e} tol {tol[mu]:.2e}")
+    assert abs(e - ref.E) < TOL_E * abs(ref.E)
+    assert np.all(err < tol)

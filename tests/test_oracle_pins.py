@@ -237,6 +237,86 @@ def test_force_matches_bruteforce_derivative(mode, model):
         assert np.abs(dg[mu] @ g[mu] + g[mu] @ dg[mu]).max() < 1e-12
 
 
+def _fock_setup(ham, g):
+    N = ham.N
+    vecs = fock.fix_gauge([fock.gaussian_state(x) for x in g], fock.gaussian_state(g[0]))
+    vecs = fock.fix_gauge(vecs, vecs[0])
+    V = np.stack(vecs, 1)
+    H = fock.majorana_poly_operator(N, ham.poly())
+    return vecs, V, H
+
+
+@pytest.mark.parametrize("mode", ["printed", "unit"])
+def test_weights_satisfy_the_descent_condition(mode):
+    """Sec. III.A: the weight makes every state descend, c_mu lambda~_mu^*
+    lambda_mu real and positive; the unit-modulus choice has |c_mu| = 1; with
+    the printed choice the states move together as Eq. (projImEvol2) asks,
+    sum_mu lambda_mu |dphi_mu> = -R Pi_perp H |psi> (R times the printed
+    right-hand side: each of the R states carries the full projected step).
+    Checked in Fock space, independently of how sgs.weights is written."""
+    ham = si.anderson(1, 1.1, 0.6)
+    g = si.random_states(ham.N, 3, seed=21)
+    vecs, V, H = _fock_setup(ham, g)
+    Gb, hb = V.conj().T @ V, V.conj().T @ H @ V
+    E, lam = sgs.solve_amplitudes(Gb, hb)
+    lamt = Gb @ lam
+    c = sgs.weights(lam, lamt, mode)
+    d = c * lamt.conj() * lam
+    assert np.all(d.real > 0) and np.abs(d.imag).max() < 1e-12 * np.abs(d).max()
+    if mode == "unit":
+        assert np.allclose(np.abs(c), 1.0, atol=1e-14, rtol=0)
+    else:
+        psi = V @ lam
+        pperp = np.eye(V.shape[0]) - V @ np.linalg.inv(Gb) @ V.conj().T
+        target = -3 * (pperp @ H @ psi)
+        tot = np.zeros_like(psi)
+        for mu in range(3):
+            B = c[mu] * np.outer(pperp @ H @ psi, psi.conj())   # Eq. (Bmu)
+            B = B + B.conj().T
+            tot += lam[mu] * (-B @ vecs[mu])                      # Eq. (PhiMu)
+        assert np.abs(tot - target).max() < 1e-12 * np.abs(target).max()
+
+
+def test_force_with_dropped_combination_matches_bruteforce():
+    """Two states differ by a rotation of |Q - 1|_F = 1e-7: G has an eigenvalue
+    below 1e-12 of its largest, which canonical orthogonalization drops.  The
+    long form of Eq. (EOM-Gamma3) with G^-1 read as the inverse on the kept
+    subspace equals the brute-force derivative with the projector onto the
+    complement of the kept combinations (and differs from it at O(1) with the
+    plain G^-1, so a dropped term or the wrong inverse fails here)."""
+    ham = si.anderson(1, 1.2, 0.5)
+    g0 = si.random_states(ham.N, 2, seed=8)
+    q = si.small_rotations(ham.n, 1, 1e-7, seed=9)[0]
+    g2 = q @ g0[1] @ q.T
+    g = np.stack([g0[0], g0[1], 0.5 * (g2 - g2.T)])
+    tab = sgs.pair_tables(ham, g)
+    X = sgs.canonical_basis(tab.G)
+    assert X.shape[1] == 2  # one combination dropped
+    E, lam = sgs.solve_amplitudes(tab.G, tab.h)
+    for mode in ("printed", "unit"):
+        dg = sgs.forces(ham, g, tab, E, lam, mode)
+        vecs, V, H = _fock_setup(ham, g)
+        Gb = V.conj().T @ V
+        lamt = Gb @ lam
+        c = sgs.weights(lam, lamt, mode)
+        VX = V @ X
+        pperp = np.eye(V.shape[0]) - VX @ VX.conj().T
+        psi = V @ lam
+        cm = fock.majoranas(ham.N)
+        for mu in range(3):
+            B = c[mu] * np.outer(pperp @ H @ psi, psi.conj())
+            B = B + B.conj().T
+            dphi = -B @ vecs[mu]
+            ref = np.zeros((ham.n, ham.n))
+            for k in range(ham.n):
+                for l in range(ham.n):
+                    if k != l:
+                        ref[k, l] = 2 * (-1j * np.vdot(vecs[mu], cm[k] @ cm[l] @ dphi)).real
+            # the kept combinations mix two vectors that differ by 1e-7, so
+            # float64 rounding (1e-16) in either side is magnified ~1e7
+            assert np.abs(dg[mu] - ref).max() < 1e-7 * max(1.0, np.abs(ref).max())
+
+
 def test_rank_one_is_ghf_imaginary_time():
     # R = 1: the normalization line cancels and dGamma = 4 (F + Gamma F Gamma)
     ham = si.anderson(2, 1.5, 0.6)
