@@ -90,7 +90,7 @@ typedef struct sgs_ctx sgs_ctx; /* opaque */
 
 /* One impurity problem (Sec. II.A).  Host pointers, read by sgs_init only. */
 typedef struct {
-  int32_t N;             /* fermionic modes, n = 2N Majoranas, 2 <= N <= 4096  */
+  int32_t N;             /* fermionic modes, n = 2N Majoranas, 1 <= N <= 2048  */
   int32_t R;             /* rank of the ansatz, 1 <= R <= 32                   */
   const double* A;       /* n*n row-major, real skew (checked)                 */
   int32_t nq;            /* number of quartic words, 0 <= nq <= 256            */
@@ -113,8 +113,12 @@ typedef struct {
                      /* are inverted before the other pairs start; 2: both    */
                      /* batches start together                                */
   int32_t pf_super;  /* Pfaffian: elimination steps per trailing update       */
-                     /* (rank 2 pf_super), 1..64                              */
-  int32_t reserved[4];
+                     /* (rank 2 pf_super), 1..32                              */
+  int32_t force_split;  /* force products: workgroups per output tile, each */
+                        /* summing a range of the terms, 1..4                */
+  int32_t force_elem;   /* elementwise force terms: 1 beside the products on */
+                        /* a second stream, 2 after them on the same stream  */
+  int32_t reserved[2];
 } sgs_tune;
 
 typedef struct {

@@ -41,7 +41,10 @@ class sgs_problem(ctypes.Structure):
 
 class sgs_tune(ctypes.Structure):
     _fields_ = [("n_max", c_int32), ("gj_super", c_int32), ("gj_first", c_int32), ("pf_super", c_int32),
-                ("reserved", c_int32 * 4)]
+                ("force_split", c_int32), ("force_elem", c_int32), ("reserved", c_int32 * 2)]
+
+
+TUNE_FIELDS = ("n_max", "gj_super", "gj_first", "pf_super", "force_split", "force_elem")
 
 
 class sgs_options(ctypes.Structure):
@@ -98,12 +101,13 @@ def _strerror(code: int) -> str:
 
 
 def tuning_table(rows) -> ctypes.Array:
-    """sgs_tune rows from dicts {n_max, gj_super, gj_first, pf_super} (missing
-    fields: 0, the library's built-in choice), sorted by n_max."""
+    """sgs_tune rows from dicts {n_max, gj_super, gj_first, pf_super,
+    force_split, force_elem} (missing fields: 0, the library's built-in
+    choice), sorted by n_max."""
     rows = sorted(rows, key=lambda r: int(r["n_max"]))
     arr = (sgs_tune * max(1, len(rows)))()
     for i, r in enumerate(rows):
-        for f in ("n_max", "gj_super", "gj_first", "pf_super"):
+        for f in TUNE_FIELDS:
             setattr(arr[i], f, int(r.get(f, 0)))
     return arr
 

@@ -17,7 +17,7 @@ namespace {
 
 constexpr int GJ_NB_MAX = 32;   // Gauss-Jordan panel width
 constexpr int GJ_SUPER_MAX = 256;  // Gauss-Jordan super-panel width (rank of the trailing updates), at most
-constexpr int PF_NBH_MAX = 16;
+constexpr int PF_SUPER_MAX = 32;  // Pfaffian steps per trailing update (rank 2 x this), at most
 
 struct Arena {
   char* base;
@@ -47,6 +47,8 @@ struct Prob {
   int gj_nb = 16;
   int gj_super = 128;  // super-panel width (a multiple of gj_nb)
   bool gj_first = false;  // pairs (0, a) inverted before the others start
+  int force_split = 2;    // workgroups per force output tile (term ranges)
+  bool force_seq = false;  // elementwise force terms after the products, same stream
   int worker = 0;  // stream (and scratch region) this problem runs on
   bool expmap = false;  // exponential-map update instead of Euler + purification
   bool denseA = false;  // A has many nonzeros per column: Y = Delta A by GEMM
@@ -54,7 +56,7 @@ struct Prob {
   double a2 = 0.0;  // |A|_F^2
   double* gam = nullptr;
   // dense work
-  double *W, *Di, *Y, *Yd, *T1, *Xr, *Cm, *Cm2, *UV, *RM, *gjE, *gjB, *dG, *dP, *dE, *nsX0, *nsX1, *nsQ, *Adense;
+  double *W, *Di, *Y, *Yd, *T1, *Xr, *Cm, *Cm2, *UV, *RM, *PD, *gjE, *gjB, *dG, *dP, *dE, *nsX0, *nsX1, *nsQ, *Adense;
   // small
   double *pfacc, *logdet, *eps, *Fc, *coef, *Gt, *ht, *lam, *lamt, *E, *tab_la, *tab_arg, *tab_eps;
   double *up_v, *colval, *q_val;
@@ -74,8 +76,13 @@ struct Prob {
   // Gauss-Jordan: inner updates per panel and trailing updates per
   // super-panel, for the pairs (0, a) (jgj0, jgs0) and the rest (jgj1, jgs1)
   std::vector<JobTable> jgj0, jgj1, jgs0, jgs1, jpf;
-  std::vector<int> gj_k, gj_b, gj_s, gs_k, gs_nb, pf_m;
-  long long uvstride = 0, uv_im = 0;
+  std::vector<int> gj_k, gj_b, gj_s, gs_k, gs_nb;
+  // Pfaffian: super-panels (stored size, steps) and their register panels
+  int pf_super = PF_SUPER_MAX;
+  struct PfPanel { int sp, p0, ns, kd; };
+  std::vector<int> ps_m, ps_k;
+  std::vector<PfPanel> pf_pan;
+  long long uvstride = 0, uv_im = 0, pdstride = 0;
 };
 
 // per pair: the panel's Brow (b x super-panel) or a super-panel's pivot rows (nb x n)
@@ -257,7 +264,7 @@ struct sgs_ctx {
 // layout
 // ---------------------------------------------------------------------------
 static int check_problem(const sgs_problem& p) {
-  if (p.N < 1 || p.N > 4096 || p.R < 1 || p.R > 32 || !p.A || p.nq < 0 || p.nq > 256) return SGS_EINVAL;
+  if (p.N < 1 || p.N > 2048 || p.R < 1 || p.R > 32 || !p.A || p.nq < 0 || p.nq > 256) return SGS_EINVAL;
   if (p.nq > 0 && (!p.q_idx || !p.q_val)) return SGS_EINVAL;
   const int n = 2 * p.N;
   for (int q = 0; q < p.nq; ++q) {
@@ -301,15 +308,17 @@ static void carve_scratch(Prob& q, Arena& ar) {
   q.Xr = ar.take<double>(std::max(1LL, (R - 1) * nn));
   q.Cm = ar.take<double>(std::max(1LL, 2 * Q * nn));
   q.Cm2 = ar.take<double>(std::max(1LL, 2 * Q * nn));
-  q.uvstride = 2LL * n * 2 * PF_NBH_MAX;  // planar: re block then im block
-  q.uv_im = (long long)n * 2 * PF_NBH_MAX;
+  q.uvstride = 2LL * n * 2 * PF_SUPER_MAX;  // planar: re block then im block
+  q.uv_im = (long long)n * 2 * PF_SUPER_MAX;
+  q.pdstride = 4LL * n * PF_SUPER_MAX;  // deferred columns: [row][step][U re, U im, V re, V im]
   q.pfperm = ar.take<int>(std::max(1LL, (long long)Q * n));
   q.UV = ar.take<double>(std::max(1LL, Q * q.uvstride));
   q.RM = ar.take<double>(std::max(1LL, Q * q.uvstride));
+  q.PD = ar.take<double>(std::max(1LL, Q * q.pdstride));
   q.gjE = ar.take<double>(std::max(1LL, (long long)P * n * GJ_NB_MAX));
   q.gjB = ar.take<double>(std::max(1LL, (long long)P * gj_brow_stride(n)));
   q.dG = ar.take<double>(R * nn);
-  q.dP = ar.take<double>(std::max(1LL, (FORCE_SPLIT - 1) * R * nn));  // partial force products, added into dG
+  q.dP = ar.take<double>(std::max(1LL, (FORCE_SPLIT_MAX - 1) * R * nn));  // partial force products, added into dG
   q.dE = ar.take<double>(R * nn);  // elementwise force terms, added into dG
   q.nsX0 = ar.take<double>(R * nn);
   q.nsX1 = ar.take<double>(R * nn);
@@ -400,9 +409,23 @@ static void carve_jobs(Prob& q, Arena& ar) {
   for (auto& t : q.jgj1) table(t, q.P - P0);
   for (auto& t : q.jgs0) table(t, 2 * P0);
   for (auto& t : q.jgs1) table(t, 2 * (q.P - P0));
-  int npf = 0;
-  for (int m = n; m > 0; m -= 2 * pf_panel_shape(m).ns) ++npf;
-  q.jpf.assign(npf, JobTable());
+  // Pfaffian schedule: super-panels of pf_super steps (fewer at the end),
+  // each swept by register panels sized for the rows they hold
+  q.ps_m.clear(); q.ps_k.clear(); q.pf_pan.clear();
+  for (int m = n; m > 0;) {
+    const int k = std::min(q.pf_super, m / 2);
+    const int sp = (int)q.ps_m.size();
+    q.ps_m.push_back(m);
+    q.ps_k.push_back(k);
+    for (int done = 0; done < k;) {
+      const int p0 = 2 * done;
+      const int ns = std::min(pf_panel_shape(m - p0).nbh, k - done);
+      q.pf_pan.push_back({sp, p0, ns, done});
+      done += ns;
+    }
+    m -= 2 * k;
+  }
+  q.jpf.assign(q.ps_m.size(), JobTable());
   for (auto& t : q.jpf) table(t, q.Q);
   table(q.jdi, q.P);
   table(q.jya, q.denseA ? 2 * q.P + q.R : 0);
@@ -446,6 +469,11 @@ constexpr int DENSE_A_PER_COLUMN = 16;
 static void pick_tuning(Prob& q, const sgs_options& o) {
   q.gj_nb = pick_gj_nb(q.n, 0);
   q.gj_super = 128;
+  // Pfaffian super-panels of 32 steps (rank-64 trailing updates) beat 16 and
+  // 24 at n = 800 and 1204 (92.5 / 95.0 / 93.3 and 190 / 200 / 193 ms per
+  // step); at n = 400 one register panel of 16 steps per update is best (the
+  // chain is bound by the panels' latency there, not by the updates)
+  q.pf_super = q.n <= 512 ? 16 : PF_SUPER_MAX;
   // measured at n = 400, 800, 1204: both batches of inverses start together
   // (with the pairs (0, a) first the phase chain then shares the GPU with the
   // other inverses for its whole length: 256 instead of 253 ms per step at
@@ -456,9 +484,14 @@ static void pick_tuning(Prob& q, const sgs_options& o) {
     if (q.n > t.n_max) continue;
     if (t.gj_super > 0) q.gj_super = t.gj_super;
     if (t.gj_first > 0) q.gj_first = t.gj_first == 1;
+    if (t.pf_super > 0) q.pf_super = t.pf_super;
+    if (t.force_split > 0) q.force_split = t.force_split;
+    if (t.force_elem > 0) q.force_seq = t.force_elem == 2;
     break;
   }
   q.gj_super = std::max(q.gj_nb, std::min(GJ_SUPER_MAX, q.gj_super / q.gj_nb * q.gj_nb));
+  q.pf_super = std::max(1, std::min(PF_SUPER_MAX, q.pf_super));
+  q.force_split = std::max(1, std::min(std::min(FORCE_SPLIT_MAX, q.R), q.force_split));
 }
 
 static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, char* base, int lds_max,
@@ -730,33 +763,28 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
                        1.0, 1.0));
   }
   HIPCHK(upload_jobs(q.jt1)); HIPCHK(upload_jobs(q.jxr));
-  // Pfaffian panels: panel t reads the compact trailing matrix from buffer
-  // t % 2 and its GEMM writes the next one, read through the panel's
-  // permutation, into the other buffer:  A' = A[perm, perm] + [U V] [V -U]^T
-  q.pf_m.clear();
-  {
-    int t = 0;
-    for (int m = n; m > 0; ++t) {
-      const PfPanelShape sh = pf_panel_shape(m);
-      const int mp = m - 2 * sh.ns, K = 2 * sh.nbh;
-      q.pf_m.push_back(m);
-      JobTable& jt = q.jpf[t];
-      jt.host.clear(); jt.ntiles = 0; jt.cplx = true;
-      double* cin = (t & 1) ? q.Cm2 : q.Cm;
-      double* cout = (t & 1) ? q.Cm : q.Cm2;
-      if (mp > 0)
-        for (int qq = 0; qq < q.Q; ++qq) {
-          // the panel stores [U V] and [V -U] transposed (K x mp)
-          GemmJob j = job(q.UV + qq * q.uvstride, mp, 1, q.RM + qq * q.uvstride, mp, 0, cin + qq * 2 * nn, n,
-                          cout + qq * 2 * nn, n, mp, mp, K, 1.0, 1.0);
-          j.a_im = q.uv_im; j.b_im = q.uv_im; j.c_im = nn; j.d_im = nn;
-          j.cperm = q.pfperm + (long long)qq * n;
-          j.mirror = -1;  // the trailing matrix stays skew
-          add_job(jt, j);
-        }
-      HIPCHK(upload_jobs(jt));
-      m = mp;
-    }
+  // Pfaffian super-panels: super-panel t reads the compact trailing matrix
+  // from buffer t % 2 and its GEMM writes the next one, read through the
+  // super-panel's permutation, into the other buffer:
+  //   A' = A[perm, perm] + [U V] [V -U]^T   (depth 2 k)
+  for (size_t t = 0; t < q.ps_m.size(); ++t) {
+    const int m = q.ps_m[t], k = q.ps_k[t];
+    const int mp = m - 2 * k, K = 2 * k;
+    JobTable& jt = q.jpf[t];
+    jt.host.clear(); jt.ntiles = 0; jt.cplx = true;
+    double* cin = (t & 1) ? q.Cm2 : q.Cm;
+    double* cout = (t & 1) ? q.Cm : q.Cm2;
+    if (mp > 0)
+      for (int qq = 0; qq < q.Q; ++qq) {
+        // the last panel stores [U V] and [V -U] transposed (K x mp)
+        GemmJob j = job(q.UV + qq * q.uvstride, mp, 1, q.RM + qq * q.uvstride, mp, 0, cin + qq * 2 * nn, n,
+                        cout + qq * 2 * nn, n, mp, mp, K, 1.0, 1.0);
+        j.a_im = q.uv_im; j.b_im = q.uv_im; j.c_im = nn; j.d_im = nn;
+        j.cperm = q.pfperm + (long long)qq * n + 2 * k;
+        j.mirror = -1;  // the trailing matrix stays skew
+        add_job(jt, j);
+      }
+    HIPCHK(upload_jobs(jt));
   }
   // Newton-Schulz: Q = X X ; X' = 0.5 X Q + 1.5 X (ping-pong)
   for (int par = 0; par < 2; ++par) {
@@ -886,11 +914,15 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
       HCHK(launch_build_c(n, q.gam, q.T1, q.Xr, q.qa, q.qb, q.Q, q.Cm, s2));
       tm.end(SGS_STAGE_PHASE, s2);
       tm.begin(SGS_STAGE_PFAFFIAN, s2);
-      for (size_t t = 0; t < q.pf_m.size(); ++t) {
-        const double* cin = (t & 1) ? q.Cm2 : q.Cm;
-        HCHK(launch_pf_panel(cin, 2 * nn, nn, n, q.pf_m[t], q.Q, q.UV, q.RM, q.uvstride, q.uv_im, q.pfperm, n,
-                             q.pfacc, t == 0, c->status, s2));
-        HCHK(run_gemm(q.jpf[t], s2));
+      for (size_t i = 0; i < q.pf_pan.size(); ++i) {
+        const Prob::PfPanel& pp = q.pf_pan[i];
+        const int sp = pp.sp, k = q.ps_k[sp];
+        const bool last = pp.kd + pp.ns == k;
+        const double* cin = (sp & 1) ? q.Cm2 : q.Cm;
+        HCHK(launch_pf_panel(cin, 2 * nn, nn, n, q.ps_m[sp], pp.p0, pp.ns, pp.kd, k, pp.kd == 0, last, q.Q, q.PD,
+                             q.pdstride, q.UV, q.RM, q.uvstride, q.uv_im, q.pfperm, n, q.pfacc, i == 0, c->status,
+                             s2));
+        if (last) HCHK(run_gemm(q.jpf[sp], s2));
       }
       tm.end(SGS_STAGE_PFAFFIAN, s2);
       HCHK(hipEventRecord(wk.ev_join, s2));
@@ -940,16 +972,23 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
   StageTimer& tm = q.worker == 0 ? c->timer : c->mute;
   tm.begin(SGS_STAGE_FORCE, s);
   const int fmode = c->opt.precision == SGS_FP64 ? FORCE_FP64 : FORCE_FP32;
-  // the elementwise terms on the second stream (idle here: the phase chain
-  // joined before the solve), concurrent with the dense products
-  HCHK(hipEventRecord(wk.ev_f, s));
-  HCHK(hipStreamWaitEvent(wk.s2, wk.ev_f, 0));
-  HCHK(launch_force_elem(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, fmode == FORCE_FP32, q.dE, wk.s2));
-  HCHK(hipEventRecord(wk.ev_fe, wk.s2));
-  HCHK(launch_force(n, R, q.terms, q.coef, q.dG, q.dP, q.dgnorm, fmode, s));
-  tm.end(SGS_STAGE_FORCE, s);
-  HCHK(hipStreamWaitEvent(s, wk.ev_fe, 0));
-  HCHK(launch_force_join(q.dG, q.dP, q.dE, n, R, q.dgnorm, s));
+  if (q.force_seq) {
+    // the elementwise terms after the dense products, on the same stream
+    HCHK(launch_force(n, R, q.terms, q.coef, q.dG, q.dP, q.dgnorm, fmode, q.force_split, s));
+    HCHK(launch_force_elem(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, fmode == FORCE_FP32, q.dE, s));
+    tm.end(SGS_STAGE_FORCE, s);
+  } else {
+    // the elementwise terms on the second stream (idle here: the phase chain
+    // joined before the solve), concurrent with the dense products
+    HCHK(hipEventRecord(wk.ev_f, s));
+    HCHK(hipStreamWaitEvent(wk.s2, wk.ev_f, 0));
+    HCHK(launch_force_elem(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, fmode == FORCE_FP32, q.dE, wk.s2));
+    HCHK(hipEventRecord(wk.ev_fe, wk.s2));
+    HCHK(launch_force(n, R, q.terms, q.coef, q.dG, q.dP, q.dgnorm, fmode, q.force_split, s));
+    tm.end(SGS_STAGE_FORCE, s);
+    HCHK(hipStreamWaitEvent(s, wk.ev_fe, 0));
+  }
+  HCHK(launch_force_join(q.dG, q.dP, q.dE, n, R, q.force_split, q.dgnorm, s));
   (void)nn;
   tm.begin(SGS_STAGE_PURIFY, s);
   if (q.expmap) {
@@ -1019,7 +1058,9 @@ static int check_options(const sgs_options& o) {
   for (int i = 0; i < o.ntune; ++i) {
     const sgs_tune& t = o.tune[i];
     if (t.n_max < 2 || (i > 0 && t.n_max <= o.tune[i - 1].n_max)) return SGS_EINVAL;
-    if (t.gj_super > GJ_SUPER_MAX || t.gj_first > 2 || t.pf_super > 64) return SGS_EINVAL;
+    if (t.gj_super > GJ_SUPER_MAX || t.gj_first > 2 || t.pf_super > PF_SUPER_MAX ||
+        t.force_split > FORCE_SPLIT_MAX || t.force_elem > 2)
+      return SGS_EINVAL;
   }
   return SGS_OK;
 }

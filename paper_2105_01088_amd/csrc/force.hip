@@ -66,7 +66,7 @@ constexpr size_t force_lds_bytes(size_t elem) {
 // streams the same Y and Delta panels).  terms: R*R descriptors (mu-major);
 // coef: c1 then c2 tables, complex interleaved, R*R each.
 template <typename TT, bool IY>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_force(int n, int R, int T, const ForceTerm* __restrict__ terms,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_force(int n, int R, int T, int nsplit, const ForceTerm* __restrict__ terms,
                                                const double* __restrict__ coef,
                                                double* __restrict__ dG, double* __restrict__ dP,
                                                unsigned long long* __restrict__ nrm) {
@@ -81,13 +81,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 
   const int ntri = T * (T + 1) / 2;
   const int xcd = blockIdx.x & 7, loc2 = blockIdx.x >> 3;
-  // each tile's terms are split over FORCE_SPLIT workgroups (the same XCD);
+  // each tile's terms are split over nsplit workgroups (the same XCD);
   // split h sums terms [h R / S, (h + 1) R / S) into dG (h = 0) or slice
   // h - 1 of dP
-  const int split = loc2 % FORCE_SPLIT, loc = loc2 / FORCE_SPLIT;
+  const int split = loc2 % nsplit, loc = loc2 / nsplit;
   const int mu = xcd + 8 * (loc / ntri);
   if (mu >= R) return;
-  const int b_lo = split * R / FORCE_SPLIT, b_hi = (split + 1) * R / FORCE_SPLIT;
+  const int b_lo = split * R / nsplit, b_hi = (split + 1) * R / nsplit;
   // upper-triangular tile index -> (I, J), I <= J
   if (loc % ntri == 0 && split == 0 && threadIdx.x == 0) nrm[mu] = 0ull;  // k_force_join accumulates it
   int tri = loc % ntri, I = 0;
@@ -240,7 +240,7 @@ constexpr int FS_LP = FS_T + 1;      // LDS pitch
 constexpr int FS_THREADS = 64 * FS_W;
 
 template <typename TT>
-__global__ __launch_bounds__(FS_THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_force_strip(int n, int R, int T, const ForceTerm* __restrict__ terms,
+__global__ __launch_bounds__(FS_THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_force_strip(int n, int R, int T, int nsplit, const ForceTerm* __restrict__ terms,
                                                           const double* __restrict__ coef,
                                                           double* __restrict__ dG, double* __restrict__ dP,
                                                           unsigned long long* __restrict__ nrm) {
@@ -255,10 +255,10 @@ __global__ __launch_bounds__(FS_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
 
   const int ntri = T * (T + 1) / 2;
   const int xcd = blockIdx.x & 7, loc2 = blockIdx.x >> 3;
-  const int split = loc2 % FORCE_SPLIT, loc = loc2 / FORCE_SPLIT;
+  const int split = loc2 % nsplit, loc = loc2 / nsplit;
   const int mu = xcd + 8 * (loc / ntri);
   if (mu >= R) return;
-  const int b_lo = split * R / FORCE_SPLIT, b_hi = (split + 1) * R / FORCE_SPLIT;
+  const int b_lo = split * R / nsplit, b_hi = (split + 1) * R / nsplit;
   if (loc % ntri == 0 && split == 0 && threadIdx.x == 0) nrm[mu] = 0ull;  // k_force_join accumulates it
   int tri = loc % ntri, I = 0;
   while (tri >= T - I) { tri -= T - I; ++I; }
@@ -471,7 +471,7 @@ __global__ __launch_bounds__(512) void k_force_elem(int n, int R, int T, const F
 // nrm[mu] as an ordered bit pattern (k_force cleared it).  grid:
 // (ceil(n / 16), R); one wave per row.
 __global__ __launch_bounds__(256) void k_force_join(double* __restrict__ dG, const double* __restrict__ dP,
-                                                    const double* __restrict__ dE, int n, int R,
+                                                    const double* __restrict__ dE, int n, int R, int nsplit,
                                                     unsigned long long* __restrict__ nrm) {
   __shared__ double red[4];
   const int mu = blockIdx.y;
@@ -487,8 +487,7 @@ __global__ __launch_bounds__(256) void k_force_join(double* __restrict__ dG, con
     for (int j = lane; j < n; j += 64) {
       const long long o = (long long)i * n + j;
       double v = d[o] + de[o];
-#pragma unroll
-      for (int h = 0; h + 1 < FORCE_SPLIT; ++h) v += dp[h * pstride + o];
+      for (int h = 0; h + 1 < nsplit; ++h) v += dp[h * pstride + o];
       d[o] = v;
       s += fabs(v);
     }
@@ -508,21 +507,22 @@ static long long force_area(int n, int e) {
 }
 
 hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, double* dG, double* dP,
-                        unsigned long long* nrm, int mode, hipStream_t s) {
+                        unsigned long long* nrm, int mode, int nsplit, hipStream_t s) {
+  if (nsplit < 1 || nsplit > FORCE_SPLIT_MAX || nsplit > R) return hipErrorInvalidValue;
   const int per_xcd = (R + 7) / 8;
   if (mode == FORCE_FP32 && force_area(n, FS_T) < force_area(n, 64)) {
     const int T = (n + FS_T - 1) / FS_T;
-    const dim3 grid(8 * per_xcd * (T * (T + 1) / 2) * FORCE_SPLIT), block(FS_THREADS);
-    hipLaunchKernelGGL((k_force_strip<float>), grid, block, 0, s, n, R, T, terms, coef, dG, dP, nrm);
+    const dim3 grid(8 * per_xcd * (T * (T + 1) / 2) * nsplit), block(FS_THREADS);
+    hipLaunchKernelGGL((k_force_strip<float>), grid, block, 0, s, n, R, T, nsplit, terms, coef, dG, dP, nrm);
     return hipGetLastError();
   }
   const int T = (n + 63) / 64;
   const int ntri = T * (T + 1) / 2;
-  const dim3 grid(8 * per_xcd * ntri * FORCE_SPLIT), block(256);
+  const dim3 grid(8 * per_xcd * ntri * nsplit), block(256);
   if (mode == FORCE_FP64)
-    hipLaunchKernelGGL((k_force<double, true>), grid, block, 0, s, n, R, T, terms, coef, dG, dP, nrm);
+    hipLaunchKernelGGL((k_force<double, true>), grid, block, 0, s, n, R, T, nsplit, terms, coef, dG, dP, nrm);
   else
-    hipLaunchKernelGGL((k_force<float, false>), grid, block, 0, s, n, R, T, terms, coef, dG, dP, nrm);
+    hipLaunchKernelGGL((k_force<float, false>), grid, block, 0, s, n, R, T, nsplit, terms, coef, dG, dP, nrm);
   return hipGetLastError();
 }
 
@@ -534,9 +534,9 @@ hipError_t launch_force_elem(int n, int R, const ForceTerm* terms, const double*
   return hipGetLastError();
 }
 
-hipError_t launch_force_join(double* dG, const double* dP, const double* dE, int n, int R, unsigned long long* nrm,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_force_join, dim3((n + 15) / 16, R), dim3(256), 0, s, dG, dP, dE, n, R, nrm);
+hipError_t launch_force_join(double* dG, const double* dP, const double* dE, int n, int R, int nsplit,
+                             unsigned long long* nrm, hipStream_t s) {
+  hipLaunchKernelGGL(k_force_join, dim3((n + 15) / 16, R), dim3(256), 0, s, dG, dP, dE, n, R, nsplit, nrm);
   return hipGetLastError();
 }
 

@@ -376,17 +376,16 @@ __global__ __launch_bounds__(256) void k_gj_unscramble(const double* __restrict_
 }
 
 // Register budget: the panel (n x B doubles) lives in the registers of one
-// workgroup of at most 512 threads, RPT x B doubles per thread.  Every shape
-// used up to n = 2048 compiles without spilling (32 x 3 spilled 377 VGPRs
-// and took ~1 ms per panel at n = 1204).
+// workgroup of at most 512 threads, RPT x B doubles per thread (n <= 4096).
+// Every shape compiles without spilling (32 x 3 spilled 377 VGPRs and took
+// ~1 ms per panel at n = 1204; 8 x 8 spilled 21).
 GjPanelShape gj_panel_shape(int n) {
   GjPanelShape sh;
   if (n <= 512) { sh.B = 32; sh.rpt = 1; }
   else if (n <= 1024) { sh.B = 32; sh.rpt = 2; }
   else if (n <= 1536) { sh.B = 24; sh.rpt = 3; }
   else if (n <= 2048) { sh.B = 16; sh.rpt = 4; }
-  else if (n <= 4096) { sh.B = 8; sh.rpt = 8; }
-  else { sh.B = 4; sh.rpt = 16; }
+  else { sh.B = 6; sh.rpt = 8; }
   const int rows = (n + sh.rpt - 1) / sh.rpt;
   sh.nt = ((rows + 63) / 64) * 64;
   if (sh.nt > 512) sh.nt = 512;
@@ -418,8 +417,7 @@ hipError_t launch_gj_panel(double* M, long long mstride, int nmat, int n, int k,
   else if (sh.rpt == 2) GJ_LAUNCH(32, 2);
   else if (sh.rpt == 3) GJ_LAUNCH(24, 3);
   else if (sh.rpt == 4) GJ_LAUNCH(16, 4);
-  else if (sh.rpt == 8) GJ_LAUNCH(8, 8);
-  else GJ_LAUNCH(4, 16);
+  else GJ_LAUNCH(6, 8);
 #undef GJ_LAUNCH
   return hipGetLastError();
 }
@@ -450,8 +448,7 @@ hipError_t set_gj_lds_limit(size_t bytes) {
   if ((e = hipFuncSetAttribute((const void*)k_gj_panel<32, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)k_gj_panel<24, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)k_gj_panel<16, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_gj_panel<8, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_gj_panel<4, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return hipFuncSetAttribute((const void*)k_gj_panel<6, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 }  // namespace sgs

@@ -9,10 +9,14 @@
 // P = [[0, a], [-a, 0]], Pf = a Pf(D + (b1 b0^T - b0 b1^T) / a), b0 / b1 the
 // first two rows of B.  Before each step the largest entry of the current
 // first column is moved to position 1 by a symmetric swap (sign flip).
-// Blocked with delayed updates: inside a panel of NBH steps the current
-// trailing matrix is A + U V^T - V U^T (U = b1, V = b0 / a per step); only the
-// two columns a step needs are formed, and after the panel the trailing
-// matrix takes A += [U V] [V -U]^T as one complex GEMM.
+// Blocked with delayed updates, on two levels: inside a super-panel of up to
+// 32 steps the current trailing matrix is A + U V^T - V U^T (U = b1, V = b0 / a
+// per step); only the two columns a step needs are formed, each as a gathered
+// row of A plus the sum over the earlier steps.  Panels of up to NBH steps
+// keep their own U, V in registers and take the super-panel's earlier steps
+// from a small global buffer; after the super-panel the trailing matrix takes
+// A += [U V] [V -U]^T as one complex GEMM of depth up to 64 (the matrix is read
+// and written once per super-panel instead of once per register panel).
 #include "sgs_internal.h"
 #include "wave_ops.h"
 
@@ -20,70 +24,132 @@ namespace sgs {
 
 constexpr int PF_MAX_WAVES = 8;
 
-// One panel of NBH elimination steps on the compact m x m trailing matrix A
-// (planar, leading dimension ld, imaginary plane at +plane), for every
-// matrix of the batch (one workgroup each).  Logical row l of the panel is
-// owned by thread l % nt (slot l / nt < RPT), which keeps in registers its U
-// and V entries, its current column value c0 and its stored index pl (row l
-// of the panel is stored row pl of A; the stored matrix is never written
-// during the panel).  Step s (p = 2 s):
-//   c0_l = -A[pl_p][pl_l] + sum_t (U_l V_p - V_l U_p)_t      (l > p)
+// Deferred columns of one super-panel: for every earlier step t < kd of the
+// super-panel, U_t and V_t of every stored row, row-major: entry
+// [(row * PF_DEFER + t) * 4 + {U re, U im, V re, V im}], so a row's entries
+// are contiguous (16-byte loads per lane, uniform loads for a gathered row).
+// The current matrix of the super-panel is
+//   B[i][j] = A[i][j] + sum_t (U_t[i] V_t[j] - V_t[i] U_t[j])
+// over those steps and the panel's own (held in registers); a gather of row g
+// at the lanes' rows adds sum_{t < kd} (U_t[l] V_t[g] - V_t[l] U_t[g]).
+constexpr int PF_DEFER = 32;   // deferred steps per super-panel, at most
+typedef double dpair __attribute__((ext_vector_type(2)));
+
+// One panel of at most NBH elimination steps of a super-panel, for every
+// matrix of the batch (one workgroup each).  A is the stored (compact)
+// m0 x m0 matrix the super-panel started from (planar, leading dimension ld,
+// imaginary plane at +plane); the panel takes the steps at logical positions
+// p0, p0 + 2, ..., p0 + 2 (ns - 1).  Logical row l >= p0 is owned by thread
+// (l - p0) % nt (slot (l - p0) / nt < RPT), which keeps in registers its U
+// and V entries of this panel, its current column value c0 and its stored
+// index pl (logical row l is stored row perm[l]; the stored matrix is never
+// written during a super-panel).  Step s (p = p0 + 2 s):
+//   c0_l = B[l][p]                                         (l > p)
 // the pivot row q maximizes |c0_q| (wave maxima of a packed key, posted per
 // wave with the candidate's record: U, V, c0, pl); after one barrier every
 // thread takes the best post.  Rows p+1 and q exchange (a sign flip of the
 // Pfaffian): the owner of row q takes the record that row p+1 posted; row
 // p+1 is eliminated and needs no registers.  With a = -c0_q:
-//   c1_l = -A[pl_q][pl_l] + sum_t (U_l V_q - V_l U_q)_t,
-//   U_l[s] = -c1_l,  V_l[s] = -c0_l / a                         (l > p + 1)
+//   c1_l = B[l][q],  U_l[s] = -c1_l,  V_l[s] = -c0_l / a          (l > p + 1)
 // The gather of row pl_q for c1 and the gather of the next step's pivot row
-// are issued together, and the owner of row p + 2 posts its U and V for the
-// next step before the second barrier: two barriers and one global latency
-// per step.  At the end the panel writes, for the trailing logical rows
-// l >= 2 ns, the GEMM operands L = [U | V] and Rm = [V | -U] transposed
-// (2 NBH x mp, row l - 2 ns in column l - 2 ns) and perm[l] = pl_l; the
-// trailing GEMM reads the old matrix through that permutation and writes the
-// next, compact trailing matrix into the other buffer.
-//   acc : per matrix {ln|Pf|, cos arg, sin arg}; first: start from Pf = 1
-// dynamic LDS: m ints
+// are issued together (with their deferred sums), and the owner of row p + 2
+// posts its U and V for the next step before the second barrier: two barriers
+// and one global latency per step.
+// At the end the panel appends its steps to the deferred columns and saves
+// perm; the super-panel's last panel instead writes, for the trailing logical
+// rows l >= pe = p0 + 2 ns, the GEMM operands L = [U | V] and Rm = [V | -U]
+// of all kall steps of the super-panel, stored transposed (2 kall x mp, mp =
+// m0 - pe, row l - pe in column l - pe), and perm[l] = pl_l; the trailing
+// GEMM reads the old matrix through perm + pe and writes the next, compact
+// trailing matrix into the other buffer.
+//   acc : per matrix {ln|Pf|, cos arg, sin arg}; first_acc: start from Pf = 1
+//   first: the super-panel's first panel (perm starts as the identity)
+// dynamic LDS: m0 ints
 template <int NBH, int RPT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void k_pf_panel(const double* __restrict__ Aall, long long astride, long long plane, int ld, int m,
-                double* __restrict__ Lall, double* __restrict__ RMall, long long lstride, long long l_im,
-                int* __restrict__ permall, int pstride, double* __restrict__ acc, int first,
-                int* __restrict__ status) {
+void k_pf_panel(const double* __restrict__ Aall, long long astride, long long plane, int ld, int m0, int p0,
+                int ns, int kd, int kall, int first, int last, const double* __restrict__ Dall,
+                double* __restrict__ Dwall, long long dstride, double* __restrict__ Lall,
+                double* __restrict__ RMall, long long lstride, long long l_im, int* __restrict__ permall,
+                int pstride, double* __restrict__ acc, int first_acc, int* __restrict__ status) {
   constexpr int RB = 4 * NBH + 4;  // record: U re, U im, V re, V im (NBH each), c0 re, c0 im, pl (+ pad)
   __shared__ __attribute__((aligned(16))) double slot[2][PF_MAX_WAVES][RB];
   __shared__ unsigned long long skey[2][PF_MAX_WAVES];
   __shared__ __attribute__((aligned(16))) double p1rec[2][RB];
   __shared__ __attribute__((aligned(16))) double bc[4 * NBH];  // U re, U im, V re, V im of row p
-  extern __shared__ int perm[];   // logical -> stored index, for the pivot rows of later steps
+  extern __shared__ int perm[];   // logical -> stored index (entries >= p0)
   const int mat = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
+  const int m = m0;
   const double* __restrict__ Ar = Aall + (long long)mat * astride;
   const double* __restrict__ Ai = Ar + plane;
+  int* __restrict__ gperm = permall + (long long)mat * pstride;
+  // deferred columns: read through Db (entries t < kd), written through Dw
+  // (entries kd .. kd + ns - 1 of the trailing rows) at the end
+  const dpair* __restrict__ Db = (const dpair*)(Dall + (long long)mat * dstride);
+  dpair* __restrict__ Dw = (dpair*)(Dwall + (long long)mat * dstride);
+  constexpr int RS = 2 * PF_DEFER;  // row stride in pairs
+
+  for (int l = p0 + tid; l < m; l += nt) perm[l] = first ? l : gperm[l];
+  for (int e = tid; e < 4 * NBH; e += nt) bc[e] = 0.0;  // row p0's U, V before the first step
+  __syncthreads();
 
   double ur[RPT][NBH], ui[RPT][NBH], vr[RPT][NBH], vi[RPT][NBH];
   double c0r[RPT], c0i[RPT], prr[RPT], pri[RPT];
   int pl[RPT];
+  // sum over the deferred steps of (U_t[l] V_t[g] - V_t[l] U_t[g]) for the
+  // lanes' rows l against rows g1 and g2 (complex, accumulated into d*).
+  // The rows g are uniform: their entries come through the scalar cache.
+  auto deferred = [&](int g1, int g2, double (&d1r)[RPT], double (&d1i)[RPT], double (&d2r)[RPT],
+                      double (&d2i)[RPT]) {
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int l = tid + r * nt;
-    c0r[r] = 0.0;
-    c0i[r] = 0.0;
-    pl[r] = l;
+    for (int r = 0; r < RPT; ++r) { d1r[r] = 0.0; d1i[r] = 0.0; d2r[r] = 0.0; d2i[r] = 0.0; }
+    const dpair* __restrict__ B1 = Db + (long long)__builtin_amdgcn_readfirstlane(g1) * RS;
+    const dpair* __restrict__ B2 = Db + (long long)__builtin_amdgcn_readfirstlane(g2) * RS;
+#pragma unroll 4
+    for (int t = 0; t < kd; ++t) {
+      const dpair u1 = B1[2 * t], v1 = B1[2 * t + 1];
+      const dpair u2 = B2[2 * t], v2 = B2[2 * t + 1];
 #pragma unroll
-    for (int t = 0; t < NBH; ++t) { ur[r][t] = 0.0; ui[r][t] = 0.0; vr[r][t] = 0.0; vi[r][t] = 0.0; }
-    // the first pivot row is stored row 0
-    prr[r] = (l > 0 && l < m) ? -Ar[l] : 0.0;
-    pri[r] = (l > 0 && l < m) ? -Ai[l] : 0.0;
+      for (int r = 0; r < RPT; ++r) {
+        const dpair* __restrict__ own = Db + (long long)pl[r] * RS;
+        const dpair ou = own[2 * t], ov = own[2 * t + 1];
+        d1r[r] = fma(ou.x, v1.x, d1r[r]); d1r[r] = fma(-ou.y, v1.y, d1r[r]);
+        d1r[r] = fma(-ov.x, u1.x, d1r[r]); d1r[r] = fma(ov.y, u1.y, d1r[r]);
+        d1i[r] = fma(ou.x, v1.y, d1i[r]); d1i[r] = fma(ou.y, v1.x, d1i[r]);
+        d1i[r] = fma(-ov.x, u1.y, d1i[r]); d1i[r] = fma(-ov.y, u1.x, d1i[r]);
+        d2r[r] = fma(ou.x, v2.x, d2r[r]); d2r[r] = fma(-ou.y, v2.y, d2r[r]);
+        d2r[r] = fma(-ov.x, u2.x, d2r[r]); d2r[r] = fma(ov.y, u2.y, d2r[r]);
+        d2i[r] = fma(ou.x, v2.y, d2i[r]); d2i[r] = fma(ou.y, v2.x, d2i[r]);
+        d2i[r] = fma(-ov.x, u2.y, d2i[r]); d2i[r] = fma(-ov.y, u2.x, d2i[r]);
+      }
+    }
+  };
+  {
+    const int g0 = perm[p0];  // the first pivot row
+    double d1r[RPT], d1i[RPT], d2r[RPT], d2i[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int l = p0 + tid + r * nt;
+      pl[r] = l < m ? perm[l] : 0;  // a valid row index for every slot
+    }
+    deferred(g0, g0, d1r, d1i, d2r, d2i);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int l = p0 + tid + r * nt;
+      c0r[r] = 0.0;
+      c0i[r] = 0.0;
+#pragma unroll
+      for (int t = 0; t < NBH; ++t) { ur[r][t] = 0.0; ui[r][t] = 0.0; vr[r][t] = 0.0; vi[r][t] = 0.0; }
+      const bool act = l > p0 && l < m;
+      const long long o = (long long)g0 * ld + pl[r];
+      prr[r] = act ? -Ar[o] + d1r[r] : 0.0;
+      pri[r] = act ? -Ai[o] + d1i[r] : 0.0;
+    }
   }
-  for (int l = tid; l < m; l += nt) perm[l] = l;
-  for (int e = tid; e < 4 * NBH; e += nt) bc[e] = 0.0;  // row p's U, V before the first step
   double la = 0.0, phr = 1.0, phi = 0.0;  // uniform
-  if (!first) { la = acc[mat * 3]; phr = acc[mat * 3 + 1]; phi = acc[mat * 3 + 2]; }
+  if (!first_acc) { la = acc[mat * 3]; phr = acc[mat * 3 + 1]; phi = acc[mat * 3 + 2]; }
   bool sing = false;
-  const int ns = min(NBH, m / 2);
-  __syncthreads();
 
   // The step loop stays rolled (unrolled it is tens of KB of code fetched once
   // per panel: instruction-cache bound).  U and V entries are kept by age:
@@ -93,7 +159,7 @@ void k_pf_panel(const double* __restrict__ Aall, long long astride, long long pl
   // appends the new entry.  Posted records carry the same layout.
 #pragma unroll 1
   for (int s = 0; s < ns; ++s) {
-    const int p = 2 * s, par = s & 1;
+    const int p = p0 + 2 * s, par = s & 1;
     // current column p and the pivot search keys
     unsigned long long mine[RPT];
     unsigned long long key = 0;
@@ -101,7 +167,7 @@ void k_pf_panel(const double* __restrict__ Aall, long long astride, long long pl
     // (broadcast reads; the VALU only multiplies)
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-      const int l = tid + r * nt;
+      const int l = p0 + tid + r * nt;
       const bool act = l > p && l < m;
       double xr = prr[r], xi = pri[r], yr = 0.0, yi = 0.0;
 #pragma unroll
@@ -137,7 +203,7 @@ void k_pf_panel(const double* __restrict__ Aall, long long astride, long long pl
     for (int r = 0; r < RPT; ++r) {
 #pragma unroll
       for (int k2 = 0; k2 < 2; ++k2) {
-        const bool post = k2 == 0 ? (key != 0ull && mine[r] == key) : (tid + r * nt == p + 1);
+        const bool post = k2 == 0 ? (key != 0ull && mine[r] == key) : (p0 + tid + r * nt == p + 1);
         if (post) {
           double* rec = k2 == 0 ? slot[par][w] : p1rec[par];
 #pragma unroll
@@ -166,7 +232,7 @@ void k_pf_panel(const double* __restrict__ Aall, long long astride, long long pl
     const double* __restrict__ rq = bad ? p1rec[par] : slot[par][ww];
     const bool flip = q != p + 1;
     const double ar = -rq[4 * NBH], ai = -rq[4 * NBH + 1];  // a = B[p][p+1] = -c0 of the new row p + 1
-    const int plq = (int)rq[4 * NBH + 2];
+    const int plq = min(max((int)rq[4 * NBH + 2], 0), m - 1);
     const double a2 = ar * ar + ai * ai;
     if (bad || !(a2 > 0.0) || !isfinite(a2)) sing = true;
     la += 0.5 * log(a2);
@@ -182,7 +248,7 @@ void k_pf_panel(const double* __restrict__ Aall, long long astride, long long pl
     // the row that moves to position q takes the record of the old row p + 1
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-      if (flip && tid + r * nt == q) {
+      if (flip && p0 + tid + r * nt == q) {
 #pragma unroll
         for (int t = 0; t < NBH; ++t) {
           ur[r][t] = p1rec[par][t]; ui[r][t] = p1rec[par][NBH + t];
@@ -193,20 +259,23 @@ void k_pf_panel(const double* __restrict__ Aall, long long astride, long long pl
         pl[r] = pp1;
       }
     }
-    // gathers: row pl_q now (c1) and the next step's pivot row
+    // gathers: row pl_q now (c1) and the next step's pivot row, each with its
+    // deferred sum
     const int p2 = (q == p + 2) ? pp1 : pp2;
     const bool more = s + 1 < ns;
+    double d1r[RPT], d1i[RPT], d2r[RPT], d2i[RPT];
+    deferred(plq, p2, d1r, d1i, d2r, d2i);
     // row q's U, V: broadcast reads from its LDS record
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-      const int l = tid + r * nt;
+      const int l = p0 + tid + r * nt;
       const bool act = l > p + 1 && l < m;
       const long long o1 = (long long)plq * ld + pl[r];
       const long long o2 = (long long)p2 * ld + pl[r];
       const double g1r = act ? Ar[o1] : 0.0, g1i = act ? Ai[o1] : 0.0;
       const bool nxt = more && l > p + 2 && l < m;
       const double g2r = nxt ? Ar[o2] : 0.0, g2i = nxt ? Ai[o2] : 0.0;
-      double xr = -g1r, xi = -g1i, yr = 0.0, yi = 0.0;
+      double xr = -g1r + d1r[r], xi = -g1i + d1i[r], yr = 0.0, yi = 0.0;
 #pragma unroll
       for (int t = 0; t < NBH; ++t) {
         const double upr = rq[t], upi = rq[NBH + t];
@@ -237,14 +306,14 @@ void k_pf_panel(const double* __restrict__ Aall, long long astride, long long pl
       ui[r][NBH - 1] = act ? -xi : 0.0;
       vr[r][NBH - 1] = act ? br * inr - bi * ini : 0.0;
       vi[r][NBH - 1] = act ? br * ini + bi * inr : 0.0;
-      prr[r] = -g2r;
-      pri[r] = -g2i;
+      prr[r] = nxt ? -g2r + d2r[r] : 0.0;
+      pri[r] = nxt ? -g2i + d2i[r] : 0.0;
     }
     // the next step's pivot row posts its U and V
     if (more) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
-        if (tid + r * nt == p + 2) {
+        if (p0 + tid + r * nt == p + 2) {
 #pragma unroll
           for (int t = 0; t < NBH; ++t) {
             bc[t] = ur[r][t]; bc[NBH + t] = ui[r][t]; bc[2 * NBH + t] = vr[r][t]; bc[3 * NBH + t] = vi[r][t];
@@ -267,29 +336,61 @@ void k_pf_panel(const double* __restrict__ Aall, long long astride, long long pl
       ur[r][NBH - 1] = 0.0; ui[r][NBH - 1] = 0.0; vr[r][NBH - 1] = 0.0; vi[r][NBH - 1] = 0.0;
     }
   }
-  // GEMM operands for the trailing rows, stored transposed (K x mp, leading
-  // dimension mp = m - 2 ns) so that consecutive lanes write consecutive
-  // addresses: Lt = [U | V]^T, Rt = [V | -U]^T; and the permutation
-  const int pe = 2 * ns, mp = m - pe;
-  double* Lr = Lall + (long long)mat * lstride;
-  double* Li = Lr + l_im;
-  double* Rr = RMall + (long long)mat * lstride;
-  double* Ri = Rr + l_im;
-  int* gperm = permall + (long long)mat * pstride;
+  const int pe = p0 + 2 * ns;
+  if (!last) {
+    // append this panel's steps to the deferred columns (trailing rows only:
+    // eliminated rows are never gathered again) and keep the permutation
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int l = tid + r * nt;
-    if (l >= pe && l < m) {
-      const int i = l - pe;
+    for (int r = 0; r < RPT; ++r) {
+      const int l = p0 + tid + r * nt;
+      if (l >= pe && l < m) {
+        dpair* __restrict__ own = Dw + (long long)pl[r] * RS;
 #pragma unroll
-      for (int t = 0; t < NBH; ++t) {
-        const long long ou = (long long)t * mp + i, ov = (long long)(NBH + t) * mp + i;
-        Lr[ou] = ur[r][t]; Li[ou] = ui[r][t];
-        Lr[ov] = vr[r][t]; Li[ov] = vi[r][t];
-        Rr[ou] = vr[r][t]; Ri[ou] = vi[r][t];
-        Rr[ov] = -ur[r][t]; Ri[ov] = -ui[r][t];
+        for (int t = 0; t < NBH; ++t) {
+          if (t < ns) {
+            own[2 * (kd + t)] = dpair{ur[r][t], ui[r][t]};
+            own[2 * (kd + t) + 1] = dpair{vr[r][t], vi[r][t]};
+          }
+        }
+        gperm[l] = pl[r];
       }
-      gperm[i] = pl[r];
+    }
+  } else {
+    // GEMM operands for the trailing rows, stored transposed (K x mp, leading
+    // dimension mp = m - pe) so that consecutive lanes write consecutive
+    // addresses: Lt = [U | V]^T, Rt = [V | -U]^T over all kall steps (the
+    // deferred ones first); and the permutation
+    const int mp = m - pe;
+    double* Lr = Lall + (long long)mat * lstride;
+    double* Li = Lr + l_im;
+    double* Rr = RMall + (long long)mat * lstride;
+    double* Ri = Rr + l_im;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int l = p0 + tid + r * nt;
+      if (l >= pe && l < m) {
+        const int i = l - pe;
+        const dpair* __restrict__ own = Db + (long long)pl[r] * RS;
+        for (int t = 0; t < kd; ++t) {
+          const dpair xu = own[2 * t], xv = own[2 * t + 1];
+          const long long ou = (long long)t * mp + i, ov = (long long)(kall + t) * mp + i;
+          Lr[ou] = xu.x; Li[ou] = xu.y;
+          Lr[ov] = xv.x; Li[ov] = xv.y;
+          Rr[ou] = xv.x; Ri[ou] = xv.y;
+          Rr[ov] = -xu.x; Ri[ov] = -xu.y;
+        }
+#pragma unroll
+        for (int t = 0; t < NBH; ++t) {
+          if (t < ns) {
+            const long long ou = (long long)(kd + t) * mp + i, ov = (long long)(kall + kd + t) * mp + i;
+            Lr[ou] = ur[r][t]; Li[ou] = ui[r][t];
+            Lr[ov] = vr[r][t]; Li[ov] = vi[r][t];
+            Rr[ou] = vr[r][t]; Ri[ou] = vi[r][t];
+            Rr[ov] = -ur[r][t]; Ri[ov] = -ui[r][t];
+          }
+        }
+        gperm[l] = pl[r];
+      }
     }
   }
   if (tid == 0) {
@@ -307,15 +408,16 @@ size_t pf_panel_lds_bytes(int m, int nbh) {
 
 PfPanelShape pf_panel_shape(int m) {
   PfPanelShape sh;
-  // at most 512 threads (256 VGPRs each): register rows x panel depth fixed;
-  // the shapes up to m = 1536 compile without spilling (8 x 2 and 4 x 4
-  // spill 18 and 58 VGPRs: 4 x 4 took ~100 us per step at m = 1204)
+  // at most 512 threads (256 VGPRs each): register rows x panel depth fixed.
+  // Every shape up to m = 2048 compiles without spilling (with the deferred
+  // sums 7 x 2 spilled 2 VGPRs, 4 x 4 112); above that the 1 x 8 one spills
+  // (correct, slower).  The rank of the trailing updates is set by the
+  // super-panel, not by these depths.
   if (m <= 512) { sh.nbh = 16; sh.rpt = 1; }
-  else if (m <= 1024) { sh.nbh = 7; sh.rpt = 2; }
+  else if (m <= 1024) { sh.nbh = 6; sh.rpt = 2; }
   else if (m <= 1536) { sh.nbh = 4; sh.rpt = 3; }
-  else if (m <= 2048) { sh.nbh = 4; sh.rpt = 4; }
-  else if (m <= 4096) { sh.nbh = 2; sh.rpt = 8; }
-  else { sh.nbh = 1; sh.rpt = 16; }
+  else if (m <= 2048) { sh.nbh = 2; sh.rpt = 4; }
+  else { sh.nbh = 1; sh.rpt = 8; }
   const int rows = (m + sh.rpt - 1) / sh.rpt;
   sh.nt = ((rows + 63) / 64) * 64;
   if (sh.nt > 512) sh.nt = 512;
@@ -324,20 +426,25 @@ PfPanelShape pf_panel_shape(int m) {
   return sh;
 }
 
-hipError_t launch_pf_panel(const double* A, long long astride, long long plane, int ld, int m, int nmat,
-                           double* L, double* RM, long long lstride, long long l_im, int* perm, int pstride,
-                           double* acc, int first, int* status, hipStream_t s) {
-  const PfPanelShape sh = pf_panel_shape(m);
-  const size_t lds = pf_panel_lds_bytes(m, sh.nbh);
-#define PF_LAUNCH(NB, RP)                                                                               \
-  hipLaunchKernelGGL((k_pf_panel<NB, RP>), dim3(nmat), dim3(sh.nt), lds, s, A, astride, plane, ld, m, L, \
-                     RM, lstride, l_im, perm, pstride, acc, first, status)
+hipError_t launch_pf_panel(const double* A, long long astride, long long plane, int ld, int m0, int p0, int ns,
+                           int kd, int kall, int first, int last, int nmat, double* D, long long dstride, double* L,
+                           double* RM, long long lstride, long long l_im, int* perm, int pstride, double* acc,
+                           int first_acc, int* status, hipStream_t s) {
+  const PfPanelShape sh = pf_panel_shape(m0 - p0);
+  if (p0 < 0 || (p0 & 1) || ns < 1 || ns > sh.nbh || p0 + 2 * ns > m0 || kd < 0 || kd + ns > kall ||
+      kall > PF_DEFER || (last && kd + ns != kall) || (long long)sh.nt * sh.rpt < m0 - p0 || m0 > 0xffff ||
+      (long long)m0 * 4 * PF_DEFER > dstride)
+    return hipErrorInvalidValue;
+  const size_t lds = pf_panel_lds_bytes(m0, sh.nbh);
+#define PF_LAUNCH(NB, RP)                                                                                        \
+  hipLaunchKernelGGL((k_pf_panel<NB, RP>), dim3(nmat), dim3(sh.nt), lds, s, A, astride, plane, ld, m0, p0, ns, kd, \
+                     kall, first, last, (const double*)D, D, dstride, L, RM, lstride, l_im, perm, pstride, acc,  \
+                     first_acc, status)
   if (sh.nbh == 16) PF_LAUNCH(16, 1);
-  else if (sh.nbh == 7) PF_LAUNCH(7, 2);
-  else if (sh.nbh == 4 && sh.rpt == 3) PF_LAUNCH(4, 3);
-  else if (sh.nbh == 4) PF_LAUNCH(4, 4);
-  else if (sh.nbh == 2) PF_LAUNCH(2, 8);
-  else PF_LAUNCH(1, 16);
+  else if (sh.nbh == 6) PF_LAUNCH(6, 2);
+  else if (sh.nbh == 4) PF_LAUNCH(4, 3);
+  else if (sh.nbh == 2) PF_LAUNCH(2, 4);
+  else PF_LAUNCH(1, 8);
 #undef PF_LAUNCH
   return hipGetLastError();
 }

@@ -177,9 +177,15 @@ struct PfPanelShape {
 };
 PfPanelShape pf_panel_shape(int m);
 size_t pf_panel_lds_bytes(int m, int nbh);
-hipError_t launch_pf_panel(const double* A, long long astride, long long plane, int ld, int m, int nmat,
-                           double* L, double* RM, long long lstride, long long l_im, int* perm, int pstride,
-                           double* acc, int first, int* status, hipStream_t s);
+// one panel of ns steps at logical positions p0, p0 + 2, ... of the
+// super-panel (kall <= 32 steps in all, kd before this panel) of the stored
+// m0 x m0 matrix A; D: the super-panel's deferred columns (dstride >= 128 m0
+// doubles per matrix, row-major [row][t][U re, U im, V re, V im]); last:
+// write the trailing GEMM operands L, RM and perm (entries >= p0 + 2 ns)
+hipError_t launch_pf_panel(const double* A, long long astride, long long plane, int ld, int m0, int p0, int ns,
+                           int kd, int kall, int first, int last, int nmat, double* D, long long dstride, double* L,
+                           double* RM, long long lstride, long long l_im, int* perm, int pstride, double* acc,
+                           int first_acc, int* status, hipStream_t s);
 hipError_t launch_pair_sum(const double* gam, int n, const int* pa, const int* pb, int P, double* S,
                            double* logdet, hipStream_t s);
 hipError_t launch_eps_fock(const HamDev& h, int P, int R, const double* W, const double* Di,
@@ -241,21 +247,20 @@ hipError_t set_renyi2_lds_limit();
 hipError_t launch_renyi2(const ObsState& s, int nA, double* part, double* out, hipStream_t st);
 
 enum : int { FORCE_FP64 = 0, FORCE_FP32 = 1 };
-// k_force: the dense products, FORCE_SPLIT workgroups per output tile, each
+// k_force: the dense products, nsplit workgroups per output tile, each
 // summing one range of the terms b: range 0 into dG, range h > 0 into slice
-// h - 1 of dP ((FORCE_SPLIT - 1) R n^2 float64; clears nrm); k_force_elem:
+// h - 1 of dP ((FORCE_SPLIT_MAX - 1) R n^2 float64; clears nrm); k_force_elem:
 // the elementwise terms into dE; k_force_join: dG += (the dP slices) + dE and
-// the 1-norms.  (One, three, four or five ranges measured no faster than two
-// at n = 400, R = 16.)
-constexpr int FORCE_SPLIT = 2;
+// the 1-norms.
+constexpr int FORCE_SPLIT_MAX = 4;
 hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, double* dG, double* dP,
-                        unsigned long long* nrm, int mode, hipStream_t s);
+                        unsigned long long* nrm, int mode, int nsplit, hipStream_t s);
 // direct_y = 0: the products carry Re(c1 i Y) (FP64: B = c1 (D + i 1)) and
 // k_force_elem leaves it out
 hipError_t launch_force_elem(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
                              const int* impos, int M, int direct_y, double* dE, hipStream_t s);
-hipError_t launch_force_join(double* dG, const double* dP, const double* dE, int n, int R, unsigned long long* nrm,
-                             hipStream_t s);
+hipError_t launch_force_join(double* dG, const double* dP, const double* dE, int n, int R, int nsplit,
+                             unsigned long long* nrm, hipStream_t s);
 hipError_t launch_euler(const double* gam, const double* dG, double dtau, int n, int R, double* X,
                         int* ctl, unsigned long long* resid, int nresid, unsigned long long* nrm,
                         hipStream_t s);

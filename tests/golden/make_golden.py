@@ -6,6 +6,8 @@ Run from the repository root:
     python tests/golden/make_golden.py traj400      # anderson_L99_R16_traj500.json (hours)
     python tests/golden/make_golden.py step800      # anderson_L199_R32_U1_step.json (minutes)
     python tests/golden/make_golden.py step1204     # tck_L150_R24_J0.3_step.json (minutes)
+    python tests/golden/make_golden.py cond800      # adds phase-matrix conditions (minutes)
+    python tests/golden/make_golden.py cond1204
 
 Each value records the oracle routine that produced it and the passage of
 Boutin & Bauer (arXiv:2105.01088) it follows.  Inputs come from sgs_inputs
@@ -93,7 +95,34 @@ def one_step(name, seed):
                dgamma_max=float(np.abs(r.dgamma).max()),
                change_norm=[float(np.linalg.norm(r.gammas[m] - gam[m])) for m in range(gam.shape[0])])
     out.update(_samples(r.gammas, seed=seed))
+    out["phase_cond"] = phase_conditions(gam)
     with open(os.path.join(HERE, f"{name}_step.json"), "w") as f:
+        json.dump(out, f)
+
+
+def phase_conditions(gam):
+    """2-norm condition number of every matrix C_ab (1 <= a < b) whose Pfaffian
+    gives the phase of G_ab (Schur-reduced triple product, Sec. II.B):
+    [[a, b, cond], ...]; a phase computed by elimination is accurate to about
+    n cond eps."""
+    from oracle import gaussian as ga
+    R = gam.shape[0]
+    out = []
+    for a in range(1, R):
+        for b in range(a + 1, R):
+            c = ga.schur_matrix(gam[0], gam[a], gam[b])
+            out.append([a, b, float(np.linalg.cond(c))])
+    return out
+
+
+def add_phase_conditions(name):
+    """Add phase_cond to an existing one-step golden (same states)."""
+    path = os.path.join(HERE, f"{name}_step.json")
+    with open(path) as f:
+        out = json.load(f)
+    ham, gam, cfg = si.config_problem(name)
+    out["phase_cond"] = phase_conditions(gam)
+    with open(path, "w") as f:
         json.dump(out, f)
 
 
@@ -107,5 +136,9 @@ if __name__ == "__main__":
         one_step("anderson_L199_R32_U1", seed=800)
     elif what == "step1204":
         one_step("tck_L150_R24_J0.3", seed=1204)
+    elif what == "cond800":
+        add_phase_conditions("anderson_L199_R32_U1")
+    elif what == "cond1204":
+        add_phase_conditions("tck_L150_R24_J0.3")
     else:
         raise SystemExit(f"unknown golden: {what}")
