@@ -328,7 +328,7 @@ def main(argv=None):
         st32 = ctx32.status()
         e32 = e32.cpu().numpy()
         e64 = energies.cpu().numpy()
-        out["fp32_refine"] = {
+        out["fp32_force"] = {
             "ms_per_step": ms32, "pair_evals_per_s": P / (ms32 / 1e3), "status": st32,
             "speedup_vs_fp64": ms_step / ms32,
             "E_rel_diff_vs_fp64_max": float((np.abs(e32 - e64) / np.abs(e64)).max()),

@@ -51,7 +51,7 @@ extern "C" {
 #define SGS_EINVAL (-1)    /* bad argument: null pointer, size, index, option */
 #define SGS_ENOTSKEW (-2)  /* an input covariance matrix is not skew-symmetric */
 #define SGS_ENOTPURE (-3)  /* an input covariance matrix violates Gamma^2 = -1 */
-#define SGS_EPARITY (-4)   /* reserved: odd-parity input (Pf Gamma = -1)        */
+#define SGS_EPARITY (-4)   /* an input state has odd parity (Pf Gamma != +1)  */
 #define SGS_ESINGULAR (-5) /* Gamma_a + Gamma_b singular, or G not positive     */
 #define SGS_ENOCONV (-6)   /* purification or eigen-solve did not converge      */
 #define SGS_EHIP (-7)      /* a HIP runtime call failed                         */
@@ -63,12 +63,16 @@ extern "C" {
 
 /* sgs_options.precision */
 #define SGS_FP64 0          /* every stage in float64                          */
-#define SGS_FP32_REFINE 1   /* the force's dense product (Eq. EOM-Gamma3) on   */
+#define SGS_FP32_FORCE 1    /* the force's dense product (Eq. EOM-Gamma3) on   */
                             /* the float32 matrix cores (about 1e-7 relative, */
                             /* far below the O(dtau) error of the Euler step);*/
                             /* inverses, overlaps, Wick elements, eigen-solve */
                             /* stay float64, and the float64 purification     */
-                            /* returns every step to the pure states          */
+                            /* returns every step to the pure states.  (No    */
+                            /* float32 inverse with float64 refinement: its   */
+                            /* float64 residual alone costs what the float64  */
+                            /* inverse does at the 2:1 float32:float64 matrix */
+                            /* rate of this GPU.)                             */
 /* sgs_options.weight: the scalar c_mu of Eq. (Bmu) (Sec. III.A) */
 #define SGS_W_PRINTED 0     /* c_mu = 1 / (lambda_mu lambda~_mu^*)             */
 #define SGS_W_UNIT 1        /* c_mu = lambda~_mu lambda_mu^* / |lambda~_mu lambda_mu| */
@@ -122,7 +126,7 @@ typedef struct {
 } sgs_tune;
 
 typedef struct {
-  int32_t precision;       /* SGS_FP64 (default) or SGS_FP32_REFINE            */
+  int32_t precision;       /* SGS_FP64 (default) or SGS_FP32_FORCE            */
   int32_t weight;          /* SGS_W_PRINTED (default) or SGS_W_UNIT            */
   double g_rel_threshold;  /* canonical orthogonalization: eigenvectors of G   */
                            /* below this fraction of its largest eigenvalue are*/
@@ -159,14 +163,18 @@ int sgs_workspace_bytes(const sgs_problem* probs, int32_t nprob,
  *                  state after state, the R_p covariance matrices (n_p*n_p
  *                  row-major each): sum_p R_p n_p^2 doubles.  Read by every
  *                  evaluation and overwritten in place by sgs_step.  Each
- *                  matrix must be skew with |Gamma^2 + 1| <= 1e-10 (checked
- *                  here, synchronously).
+ *                  matrix must be skew (|Gamma + Gamma^T| <= 1e-12), pure
+ *                  (|Gamma^2 + 1| <= 1e-10) and of even parity (Pf Gamma =
+ *                  +1, as for every state generated from the vacuum by
+ *                  SO(2N); the overlap phases of Sec. II.B are taken for
+ *                  those), all checked here, synchronously; a NaN fails the
+ *                  first check that meets it.
  *   workspace    : device buffer of at least sgs_workspace_bytes, 256-byte
  *                  aligned, owned by the caller.
  *   opt          : NULL for defaults.
  *   stream       : hipStream_t to enqueue on (NULL = the default stream).
  * On success *out holds the context.  Errors: SGS_EINVAL, SGS_ENOTSKEW,
- * SGS_ENOTPURE, SGS_EWORKSPACE, SGS_EHIP. */
+ * SGS_ENOTPURE, SGS_EPARITY, SGS_EWORKSPACE, SGS_EHIP. */
 int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob,
              double* gamma, void* workspace, size_t ws_bytes,
              const sgs_options* opt, void* stream);
@@ -177,8 +185,15 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob,
  *   log_abs_G[a*R+b] = ln|<phi_a|phi_b>|       (0 on the diagonal)
  *   arg_G[a*R+b]     = arg <phi_a|phi_b>       (gauge <phi_0|phi_mu> > 0)
  *   eps[2*(a*R+b)+{0,1}] = h_ab / G_ab         (complex, interleaved)
- * Any output may be NULL.  Errors: SGS_EINVAL. */
-int sgs_pair_eval(sgs_ctx* ctx, double* log_abs_G, double* arg_G, double* eps);
+ * and, problem after problem, for its P_p = R_p (R_p - 1) / 2 pairs a < b in
+ * the order (0,1), (0,2), ..., (0,R-1), (1,2), ..., the transition matrix of
+ * Eq. (def-delta-matrix)
+ *   delta[2*(p*n*n + k*n + l) + {0,1}] = Delta^{ba}_kl
+ *          = [(i (Gamma_b - Gamma_a) - 2) (Gamma_a + Gamma_b)^{-1}]_kl
+ *   (complex interleaved, n_p x n_p row-major; <phi_a| c_k c_l |phi_b> =
+ *   i G_ab Delta^{ba}_kl for k != l; Delta^{ab} is its complex conjugate).
+ * Any output may be NULL.  Errors: SGS_EINVAL, SGS_EHIP. */
+int sgs_pair_eval(sgs_ctx* ctx, double* log_abs_G, double* arg_G, double* eps, double* delta);
 
 /* Advance every problem by nsteps imaginary-time steps of size dtau
  * (Sec. III.C, App. A).  energies (device, may be NULL): nsteps*nprob

@@ -13,7 +13,7 @@ from ._lib import (  # noqa: F401
     load_library,
     default_options,
     SGS_FP64,
-    SGS_FP32_REFINE,
+    SGS_FP32_FORCE,
     SGS_W_PRINTED,
     SGS_W_UNIT,
     SGS_UPD_EULER,

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsgs.so")
 
 SGS_FP64 = 0
-SGS_FP32_REFINE = 1
+SGS_FP32_FORCE = 1
 SGS_W_PRINTED = 0
 SGS_W_UNIT = 1
 SGS_UPD_EULER = 0
@@ -70,7 +70,7 @@ def load_library(path: str = LIB_PATH):
     lib.sgs_workspace_bytes.argtypes = [POINTER(sgs_problem), c_int32, POINTER(sgs_options), POINTER(c_size_t)]
     lib.sgs_init.argtypes = [POINTER(c_void_p), POINTER(sgs_problem), c_int32, c_void_p, c_void_p, c_size_t,
                              POINTER(sgs_options), c_void_p]
-    lib.sgs_pair_eval.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.sgs_pair_eval.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.sgs_step.argtypes = [c_void_p, c_double, c_int32, c_void_p]
     lib.sgs_energy.argtypes = [c_void_p, c_void_p, c_void_p]
     lib.sgs_observables.argtypes = [c_void_p, c_int32, POINTER(c_int32), c_int32, POINTER(c_double), c_int32,
@@ -240,14 +240,30 @@ class SGS:
         return self.gamma[o:o + self.R[p] * self.n[p] ** 2].view(self.R[p], self.n[p], self.n[p])
 
     # -- calls ------------------------------------------------------------
-    def pair_eval(self):
+    def pair_eval(self, delta: bool = False):
+        """(log|G|, arg G, eps) as flat device tensors; with delta=True also the
+        transition matrices Delta^{ba} of every pair a < b (complex, one
+        (P_p, n_p, n_p) tensor per problem)."""
         torch = self.torch
         tot = sum(r * r for r in self.R)
         la = torch.empty(tot, dtype=torch.float64, device=self.device)
         ar = torch.empty(tot, dtype=torch.float64, device=self.device)
         ep = torch.empty(2 * tot, dtype=torch.float64, device=self.device)
-        _check(self.lib.sgs_pair_eval(self.ctx, la.data_ptr(), ar.data_ptr(), ep.data_ptr()), "sgs_pair_eval")
-        return la, ar, ep
+        dl = None
+        if delta:
+            ptot = sum(r * (r - 1) // 2 * n * n for r, n in zip(self.R, self.n))
+            dl = torch.empty(max(1, 2 * ptot), dtype=torch.float64, device=self.device)
+        _check(self.lib.sgs_pair_eval(self.ctx, la.data_ptr(), ar.data_ptr(), ep.data_ptr(), _ptr(dl)),
+               "sgs_pair_eval")
+        if not delta:
+            return la, ar, ep
+        out, off = [], 0
+        for r, n in zip(self.R, self.n):
+            p = r * (r - 1) // 2
+            v = dl[2 * off:2 * (off + p * n * n)].view(p, n, n, 2)
+            out.append(torch.complex(v[..., 0], v[..., 1]))
+            off += p * n * n
+        return la, ar, ep, out
 
     def step(self, dtau: float, nsteps: int = 1, energies: bool = True):
         torch = self.torch

@@ -1047,7 +1047,7 @@ void sgs_default_options(sgs_options* o) {
 }
 
 static int check_options(const sgs_options& o) {
-  if (o.precision != SGS_FP64 && o.precision != SGS_FP32_REFINE) return SGS_EINVAL;
+  if (o.precision != SGS_FP64 && o.precision != SGS_FP32_FORCE) return SGS_EINVAL;
   if (o.weight != SGS_W_PRINTED && o.weight != SGS_W_UNIT) return SGS_EINVAL;
   if (!(o.g_rel_threshold > 0.0 && o.g_rel_threshold < 1.0)) return SGS_EINVAL;
   if (!(o.purify_tol > 0.0) || o.purify_iters < 1 || o.purify_iters > 64) return SGS_EINVAL;
@@ -1112,8 +1112,10 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
     lds_gj = std::max(lds_gj, gj_panel_lds_bytes(q.n, 0, gj_panel_shape(q.n).B));
     lds_solve = std::max(lds_solve, solve_lds_bytes(q.R));
   }
+  int nmax = 2;
+  for (auto& q : c->pr) nmax = std::max(nmax, q.n);
   if (set_gj_lds_limit(lds_gj) != hipSuccess || set_solve_lds_limit(lds_solve) != hipSuccess ||
-      set_renyi2_lds_limit() != hipSuccess) {
+      set_renyi2_lds_limit() != hipSuccess || set_pf_sign_lds_limit(nmax) != hipSuccess) {
     delete c;
     return SGS_EHIP;
   }
@@ -1157,21 +1159,36 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
         hipStreamSynchronize(c->s) != hipSuccess) { delete c; return SGS_EHIP; }
     std::memcpy(&d, &hv, sizeof(d));
     if (!(d <= 1e-10)) { delete c; return SGS_ENOTPURE; }
+    // parity: Pf Gamma = +1 for every state (the overlap phases of Sec. II.B
+    // are taken for even states generated from the vacuum)
+    double* signs = reinterpret_cast<double*>(q.nsres);
+    std::vector<double> hs(q.R, 0.0);
+    if (launch_pf_sign(q.gam, q.nsX0, q.n, q.R, signs, c->s) != hipSuccess ||
+        hipMemcpyAsync(hs.data(), signs, q.R * sizeof(double), hipMemcpyDeviceToHost, c->s) != hipSuccess ||
+        hipStreamSynchronize(c->s) != hipSuccess) { delete c; return SGS_EHIP; }
+    for (double v : hs)
+      if (v != 1.0) { delete c; return SGS_EPARITY; }
   }
   *out = c;
   return SGS_OK;
 }
 
-int sgs_pair_eval(sgs_ctx* c, double* log_abs_G, double* arg_G, double* eps) {
+int sgs_pair_eval(sgs_ctx* c, double* log_abs_G, double* arg_G, double* eps, double* delta) {
   if (!c) return SGS_EINVAL;
-  long long off = 0;
+  long long off = 0, doff = 0;
   if (c->fork() != hipSuccess) return SGS_EHIP;
   for (auto& q : c->pr) {
     const int RR = q.R * q.R;
     if (pair_stage(c, q, nullptr, log_abs_G ? log_abs_G + off : nullptr, arg_G ? arg_G + off : nullptr,
                    eps ? eps + 2 * off : nullptr) != hipSuccess)
       return SGS_EHIP;
+    const long long tot = (long long)q.P * q.n * q.n;
+    // the worker's scratch holds this problem's transition matrices until its
+    // next problem: copied out on the worker's stream
+    if (delta && launch_delta_out(q.W, q.Di, tot, delta + 2 * doff, c->wk[q.worker].s) != hipSuccess)
+      return SGS_EHIP;
     off += RR;
+    doff += tot;
   }
   if (c->join() != hipSuccess) return SGS_EHIP;
   c->evaluated = true;

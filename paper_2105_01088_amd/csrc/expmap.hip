@@ -93,11 +93,11 @@ __global__ __launch_bounds__(256) void k_exp_norm(const double* __restrict__ row
                                                   int* __restrict__ status) {
   __shared__ double red[256];
   double mx = 0.0;
-  for (int e = threadIdx.x; e < total; e += 256) mx = fmax(mx, rowsum[e]);
+  for (int e = threadIdx.x; e < total; e += 256) mx = nan_max(mx, rowsum[e]);
   red[threadIdx.x] = mx;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    if ((int)threadIdx.x < off) red[threadIdx.x] = nan_max(red[threadIdx.x], red[threadIdx.x + off]);
     __syncthreads();
   }
   if (threadIdx.x == 0) {

@@ -492,12 +492,12 @@ __global__ __launch_bounds__(256) void k_force_join(double* __restrict__ dG, con
       s += fabs(v);
     }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    mx = fmax(mx, s);
+    mx = nan_max(mx, s);
   }
   if (lane == 0) red[wv] = mx;
   __syncthreads();
   if (threadIdx.x == 0)
-    atomicMax(nrm + mu, (unsigned long long)__double_as_longlong(fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))));
+    atomicMax(nrm + mu, (unsigned long long)__double_as_longlong(nan_max(nan_max(red[0], red[1]), nan_max(red[2], red[3]))));
 }
 
 // upper-triangle tiles of edge e that cover n, times the tile area

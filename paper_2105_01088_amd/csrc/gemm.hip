@@ -259,7 +259,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             T v = alpha * acc[p][bi][bj][r] + beta * cval[p][bi][bj][r];
             if (p == 0 && row == col) v += diag;
             D[(long long)row * ldd + col + p * dim] = v;
-            if (rmax != nullptr) rm = fmax(rm, fabs((double)v + (row == col ? 1.0 : 0.0)));
+            if (rmax != nullptr) rm = nan_max(rm, fabs((double)v + (row == col ? 1.0 : 0.0)));
           }
         }
       }
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     red[threadIdx.x] = rm;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+      if ((int)threadIdx.x < off) red[threadIdx.x] = nan_max(red[threadIdx.x], red[threadIdx.x + off]);
       __syncthreads();
     }
     if (threadIdx.x == 0) atomicMax(rmax + J.gate, (unsigned long long)__double_as_longlong(red[0]));

@@ -289,4 +289,24 @@ hipError_t launch_build_c(int n, const double* gam, const double* T, const doubl
   return hipGetLastError();
 }
 
+// Transition matrices for the caller (Eq. def-delta-matrix):
+// Delta^{ba} = -2 W + i Im Delta^{ba}, complex interleaved, for the pairs
+// (a < b) in order.
+__global__ __launch_bounds__(256) void k_delta_out(const double* __restrict__ W, const double* __restrict__ Di,
+                                                   long long total, double* __restrict__ out) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    out[2 * e] = -2.0 * W[e];
+    out[2 * e + 1] = Di[e];
+  }
+}
+
+hipError_t launch_delta_out(const double* W, const double* Di, long long total, double* out, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  long long b = (total + 255) / 256;
+  if (b > 65536) b = 65536;
+  hipLaunchKernelGGL(k_delta_out, dim3((int)b), dim3(256), 0, s, W, Di, total, out);
+  return hipGetLastError();
+}
+
 }  // namespace sgs

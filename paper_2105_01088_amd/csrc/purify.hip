@@ -18,6 +18,7 @@
 // as that state's last (ctl[2 + mu]); later GEMM jobs of the state exit at
 // once, and once every state is marked whole launches do (ctl[0], ctl[1]).
 #include "sgs_internal.h"
+#include "wave_ops.h"
 
 namespace sgs {
 
@@ -63,12 +64,12 @@ __global__ void k_ns_resid(const double* __restrict__ Q, int n, long long total,
     const long long r = e % nn;
     const int i = (int)(r / n), j = (int)(r - (long long)i * n);
     const double v = Q[e] + (i == j ? 1.0 : 0.0);
-    mx = fmax(mx, fabs(v));
+    mx = nan_max(mx, fabs(v));
   }
   red[threadIdx.x] = mx;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    if ((int)threadIdx.x < off) red[threadIdx.x] = nan_max(red[threadIdx.x], red[threadIdx.x + off]);
     __syncthreads();
   }
   if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
@@ -130,12 +131,12 @@ __global__ void k_skew_resid(const double* __restrict__ G, int n, long long tota
        e += (long long)gridDim.x * blockDim.x) {
     const long long mu = e / nn, r = e - mu * nn;
     const int i = (int)(r / n), j = (int)(r - (long long)i * n);
-    mx = fmax(mx, fabs(G[e] + G[mu * nn + (long long)j * n + i]));
+    mx = nan_max(mx, fabs(G[e] + G[mu * nn + (long long)j * n + i]));
   }
   red[threadIdx.x] = mx;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    if ((int)threadIdx.x < off) red[threadIdx.x] = nan_max(red[threadIdx.x], red[threadIdx.x + off]);
     __syncthreads();
   }
   if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
@@ -147,6 +148,95 @@ hipError_t launch_skew_resid(const double* G, int n, long long total, unsigned l
   if (b > 8192) b = 8192;
   hipLaunchKernelGGL(k_skew_resid, dim3((int)b), dim3(256), 0, s, G, n, total, out);
   return hipGetLastError();
+}
+
+}  // namespace sgs
+
+namespace sgs {
+
+// Sign of Pf(Gamma) of each covariance matrix (the parity of the Gaussian
+// state, +1 even), for the check of sgs_init.  One workgroup per matrix works
+// on a copy in S by 2 x 2 pivot elimination: with the largest entry of the
+// current first column moved to position 1 by a symmetric swap (a sign flip),
+// [[0, a, b0], [-a, 0, b1], [-b0^T, -b1^T, D]] has Pfaffian
+// a Pf(D + (b1 b0^T - b0 b1^T) / a).  Only the signs of the pivots and the
+// flips are kept.  out[mu] = +1 or -1, or 0 for a singular or non-finite
+// matrix.  Run once per context, so the plain (unblocked) form: each step
+// reads and writes the trailing matrix.
+// dynamic LDS: 2 n doubles (rows 0 and 1 of the current step)
+__global__ __launch_bounds__(1024) void k_pf_sign(const double* __restrict__ G, double* __restrict__ S, int n,
+                                                  double* __restrict__ out) {
+  extern __shared__ double brow[];  // b0 then b1
+  __shared__ unsigned long long wkey[16];
+  __shared__ int spiv;
+  const int mu = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
+  const long long nn = (long long)n * n;
+  const double* __restrict__ g = G + mu * nn;
+  double* __restrict__ M = S + mu * nn;
+  for (long long e = tid; e < nn; e += nt) M[e] = g[e];
+  __syncthreads();
+  double sgn = 1.0;
+  bool bad = false;
+  for (int k = 0; k + 1 < n; k += 2) {
+    // pivot: largest |M[i][k]|, i > k
+    unsigned long long key = 0;
+    for (int i = k + 1 + tid; i < n; i += nt) key = umax64(key, pivot_key(M[(long long)i * n + k], i));
+    key = wave_max_u64(key);
+    if (lane == 0) wkey[w] = key;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long best = 0;
+      for (int x = 0; x < nw; ++x) best = umax64(best, wkey[x]);
+      spiv = best == 0ull ? -1 : 0xffff - (int)(best & 0xffffull);
+    }
+    __syncthreads();
+    const int q = spiv;
+    if (q < 0 || q <= k || q >= n) { bad = true; break; }
+    if (q != k + 1) {
+      // symmetric swap of rows and columns k + 1 and q
+      for (int j = tid; j < n; j += nt) {
+        const double t = M[(long long)(k + 1) * n + j];
+        M[(long long)(k + 1) * n + j] = M[(long long)q * n + j];
+        M[(long long)q * n + j] = t;
+      }
+      __syncthreads();
+      for (int j = tid; j < n; j += nt) {
+        const double t = M[(long long)j * n + k + 1];
+        M[(long long)j * n + k + 1] = M[(long long)j * n + q];
+        M[(long long)j * n + q] = t;
+      }
+      sgn = -sgn;
+      __syncthreads();
+    }
+    const double a = M[(long long)k * n + k + 1];
+    if (!(fabs(a) > 0.0) || !isfinite(a)) { bad = true; break; }
+    if (a < 0.0) sgn = -sgn;
+    const int m = n - k - 2;
+    for (int j = tid; j < m; j += nt) {
+      brow[j] = M[(long long)k * n + k + 2 + j];
+      brow[n + j] = M[(long long)(k + 1) * n + k + 2 + j];
+    }
+    __syncthreads();
+    const double ra = 1.0 / a;
+    for (long long e = tid; e < (long long)m * m; e += nt) {
+      const int i = (int)(e / m), j = (int)(e - (long long)i * m);
+      M[(long long)(k + 2 + i) * n + k + 2 + j] += (brow[n + i] * brow[j] - brow[i] * brow[n + j]) * ra;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) out[mu] = bad ? 0.0 : sgn;
+}
+
+hipError_t launch_pf_sign(const double* G, double* S, int n, int R, double* out, hipStream_t s) {
+  if (n < 2 || (n & 1) || n > 8192) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pf_sign, dim3(R), dim3(1024), 2 * (size_t)n * sizeof(double), s, G, S, n, out);
+  return hipGetLastError();
+}
+
+hipError_t set_pf_sign_lds_limit(int n) {
+  return hipFuncSetAttribute((const void*)k_pf_sign, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(2 * (size_t)n * sizeof(double)));
 }
 
 }  // namespace sgs

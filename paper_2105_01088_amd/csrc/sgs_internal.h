@@ -67,6 +67,14 @@ __device__ __forceinline__ SGS_GLOBAL T* as_global(T* p) {
   return (SGS_GLOBAL T*)p;
 }
 
+// Maximum that keeps NaN (fmax drops it): a residual or norm over data with a
+// NaN must not look small.  With values >= 0 or NaN (a positive quiet NaN)
+// the unsigned order of the bit patterns agrees, so atomicMax on them keeps
+// NaN as well.
+__device__ __forceinline__ double nan_max(double a, double b) {
+  return (a != a || b != b) ? __builtin_nan("") : (a > b ? a : b);
+}
+
 // Jobs of XCD x occupy table entries [off[x], off[x+1]); their tile_begin
 // counts tiles within that XCD; max_tiles = largest per-XCD tile count.
 // map (optional, device): the job of every workgroup b (tile b / 8 of XCD
@@ -196,6 +204,8 @@ hipError_t launch_apply_fock(const SparseA& sa, int n, int P, int R, const doubl
 // dense A: adds the impurity-block Fock correction into Y = Delta A, Yd = Gamma A
 hipError_t launch_fock_imp(const SparseA& sa, int n, int P, int R, const double* W, const double* Di,
                            const double* gam, const double* Fc, double* Y, double* Yd, hipStream_t s);
+// out (complex interleaved) = -2 W + i Di over total elements
+hipError_t launch_delta_out(const double* W, const double* Di, long long total, double* out, hipStream_t s);
 hipError_t launch_build_c(int n, const double* gam, const double* T, const double* Xr, const int* qa,
                           const int* qb, int Q, double* Cm, hipStream_t s);
 size_t solve_lds_bytes(int R);
@@ -282,5 +292,9 @@ hipError_t launch_finalize(const double* X0, const double* X1, int n, int R, dou
                            int maxit, int* status, hipStream_t s);
 hipError_t launch_skew_resid(const double* G, int n, long long total, unsigned long long* out,
                              hipStream_t s);
+// sign of Pf(Gamma_mu) for R matrices (out: +1, -1, or 0 if singular), working
+// on copies in S (R n^2 doubles); one workgroup per matrix
+hipError_t launch_pf_sign(const double* G, double* S, int n, int R, double* out, hipStream_t s);
+hipError_t set_pf_sign_lds_limit(int n);
 
 }  // namespace sgs

@@ -197,7 +197,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
   __syncthreads();
   if (tid == 0) {
     double smax = 0.0;
-    for (int k = 0; k < R; ++k) smax = fmax(smax, sv[k]);
+    for (int k = 0; k < R; ++k) smax = nan_max(smax, sv[k]);
     int cnt = 0;
     if (!(smax > 0.0) || !isfinite(smax)) atomicCAS(a.status, ST_OK, ST_SINGULAR);
     for (int k = 0; k < R; ++k)
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
   }
   __syncthreads();
   double lmax = 0.0;
-  for (int j = 0; j < R; ++j) lmax = fmax(lmax, sqrt(lr[j] * lr[j] + li[j] * li[j]));
+  for (int j = 0; j < R; ++j) lmax = nan_max(lmax, sqrt(lr[j] * lr[j] + li[j] * li[j]));
   for (int e = tid; e < R * R; e += blockDim.x) {
     const int mu = e / R, b = e % R;
     double rr, ri;  // w_mu lambda_b

@@ -100,5 +100,5 @@ def test_strerror_and_null_context():
     assert b"workspace" in lib.sgs_strerror(-9)
     assert b"exponential" in lib.sgs_strerror(-10)
     assert lib.sgs_step(None, 0.05, 1, None) == -1
-    assert lib.sgs_pair_eval(None, None, None, None) == -1
+    assert lib.sgs_pair_eval(None, None, None, None, None) == -1
     assert lib.sgs_energy(None, None, None) == -1
