@@ -127,6 +127,8 @@ def main(argv=None):
                     help="exp: the orthogonal exponential-map update instead of Euler + purification")
     ap.add_argument("--dtau", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each step as one HIP graph launch (no per-stage times)")
     ap.add_argument("--tune", default=None,
                     help="tuning table: a JSON file written by paper_2105_01088_amd/autotune.py, or an "
                          "inline JSON list of rows")
@@ -174,7 +176,7 @@ def main(argv=None):
     prec = 1 if args.precision == "fp32" else 0
     upd = 1 if args.update == "exp" else 0
     ctx = SGS([ham], [gam], options=default_options(weight=weight, precision=prec, update=upd,
-                                                    tune=_tune_arg(args.tune)))
+                                                    tune=_tune_arg(args.tune), graph=int(args.graph)))
     stream = ctx.stream
     gold = golden_step(args.config) if (weight == 1 and upd == 0 and dtau == 0.05) else None
     # warmup (the first step is compared with the oracle's stored step)
@@ -245,13 +247,15 @@ def main(argv=None):
     value = P * args.steps / (ms_total / 1e3)
     f_ms, f_n = stages["force"]
     f_avg_ms = f_ms / max(1, f_n)
-    achieved = force_flops(n, R) / (f_avg_ms / 1e3) / 1e12
+    achieved = force_flops(n, R) / (f_avg_ms / 1e3) / 1e12 if f_avg_ms > 0 else None
     peak = FP32_PEAK_TFLOPS if prec == 1 else FP64_PEAK_TFLOPS
     Q = (R - 1) * (R - 2) // 2
     stage_ms = {k: v[0] / max(1, args.steps) for k, v in stages.items()}
 
     def frac(flops, ms):
-        tf = flops / (ms / 1e3) / 1e12 if ms > 0 else 0.0
+        if not ms > 0:
+            return None
+        tf = flops / (ms / 1e3) / 1e12
         return {"achieved": tf, "frac": tf / FP64_PEAK_TFLOPS, "flops": flops, "ms": ms}
 
     out = {
@@ -262,6 +266,7 @@ def main(argv=None):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "us_per_step": ms_step * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -272,6 +277,7 @@ def main(argv=None):
             "model": cfg["model"], "L": cfg["L"], "N_modes": ham.N, "n_majoranas": n, "R": R,
             "pairs_per_step": P, "dtau": dtau, "seed": cfg["seed"],
             "weights": args.weight, "precision": args.precision, "update": args.update,
+            "graph": bool(args.graph),
         },
         "roofline": {
             "bound": "mfma",
@@ -279,7 +285,7 @@ def main(argv=None):
             "achieved": achieved,
             "peak": peak,
             "unit": "TFLOP/s",
-            "frac": achieved / peak,
+            "frac": achieved / peak if achieved is not None else None,
             "traffic": FORCE_TRAFFIC_BYTES.get((args.config, args.precision)),
             "force_avg_ms": f_avg_ms,
             "force_flops_per_launch": force_flops(n, R),
@@ -388,8 +394,9 @@ def bench_batched(args):
     weight = 1 if args.weight == "unit" else 0
     rates = {}
     ms = {}
-    for streams in (1, 4):
-        ctx = SGS(hams, gams, options=default_options(weight=weight, streams=streams))
+    for streams, graph in ((1, 0), (4, 0), (4, 1)):
+        key = (streams, graph)
+        ctx = SGS(hams, gams, options=default_options(weight=weight, streams=streams, graph=graph))
         ctx.step(dtau, max(1, args.warmup))
         torch.cuda.synchronize()
         if ctx.status() != 0:
@@ -404,19 +411,19 @@ def bench_batched(args):
         if ctx.status() != 0:
             raise SystemExit(f"device status {ctx.status()} in the timed region")
         total = t0.elapsed_time(t1)
-        ms[streams] = total / args.steps
-        rates[streams] = pairs * args.steps / (total / 1e3)
+        ms[key] = total / args.steps
+        rates[key] = pairs * args.steps / (total / 1e3)
         ctx.close()
         del ctx
         torch.cuda.empty_cache()
     out = {
         "metric": "Gaussian-pair evals/s",
-        "value": rates[4],
+        "value": rates[(4, 1)],
         "unit": "pair-evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms[4],
+        "ms_per_step": ms[(4, 1)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -425,7 +432,10 @@ def bench_batched(args):
         "config": {"workload": f"batched{count}", "problems": count, "pairs_per_step": pairs,
                    "n_range": [min(h.n for h in hams), max(h.n for h in hams)], "dtau": dtau, "seed": 0,
                    "weights": args.weight, "precision": args.precision},
-        "sequential": {"value": rates[1], "ms_per_step": ms[1], "streams": 1},
+        "launch": "one HIP graph launch per step for all problems (4 worker streams inside)",
+        "sequential": {"value": rates[(1, 0)], "ms_per_step": ms[(1, 0)], "streams": 1,
+                       "speedup": rates[(4, 1)] / rates[(1, 0)]},
+        "streams4_eager": {"value": rates[(4, 0)], "ms_per_step": ms[(4, 0)]},
         "roofline": None,
     }
     print(json.dumps(out), flush=True)

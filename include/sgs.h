@@ -147,6 +147,14 @@ typedef struct {
   const sgs_tune* tune;    /* host, ntune rows sorted by n_max, read by        */
   int32_t ntune;           /* sgs_workspace_bytes / sgs_init; NULL / 0: the    */
                            /* built-in choices (default)                      */
+  int32_t graph;           /* 1: sgs_step captures one step of every problem  */
+                           /* into a HIP graph (again when dtau changes) and  */
+                           /* launches it once per step: one launch per step  */
+                           /* for the whole batch.  Results are identical.    */
+                           /* The problems then share one worker stream       */
+                           /* (streams is ignored); stage timing is not       */
+                           /* recorded.  0 (default): kernels are enqueued    */
+                           /* per step                                        */
 } sgs_options;
 
 /* Fill *opt with the defaults listed above. */

@@ -51,7 +51,7 @@ class sgs_options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("weight", c_int32), ("g_rel_threshold", c_double),
                 ("purify_tol", c_double), ("purify_iters", c_int32),
                 ("streams", c_int32), ("update", c_int32), ("exp_coef", c_double),
-                ("tune", POINTER(sgs_tune)), ("ntune", c_int32)]
+                ("tune", POINTER(sgs_tune)), ("ntune", c_int32), ("graph", c_int32)]
 
 
 _lib = None

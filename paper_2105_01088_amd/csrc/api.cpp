@@ -195,7 +195,10 @@ struct StageTimer {
 };
 
 // device staging of the observables (polynomial terms, partial sums)
+constexpr int GRAPH_RING = 1024;  // replays between copies of the energies
+
 struct ObsBuf {
+  double* ering = nullptr;  // energies of graph replays: GRAPH_RING x nprob
   int* rows = nullptr;
   double* coef = nullptr;
   int* off = nullptr;
@@ -227,7 +230,17 @@ struct sgs_ctx {
   StageTimer timer;
   StageTimer mute;  // never switched on
   ObsBuf obs;
+  // graph replay of one step (sgs_options.graph): the energies of successive
+  // replays go to ering[ctr * nprob + p], copied out after the replays
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t gs = nullptr;  // capture stream (the caller's may be the legacy default stream)
+  double gdtau = 0.0;
+  int* ectr = nullptr;
+  double* ering = nullptr;
+  bool capturing = false;
   ~sgs_ctx() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (gs) (void)hipStreamDestroy(gs);
     for (auto& w : wk) {
       if (w.ev_fork) (void)hipEventDestroy(w.ev_fork);
       if (w.ev_join) (void)hipEventDestroy(w.ev_join);
@@ -498,7 +511,7 @@ static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, c
                    int max_workers, bool expmap, const sgs_options& opt, ObsBuf* ob = nullptr,
                    int* nworkers = nullptr) {
   Arena ar{base, 0};
-  ar.take<int>(64);  // status word and spare
+  ar.take<int>(64);  // status word and spare (the graph's step counter)
   {
     ObsBuf o;
     o.rows = ar.take<int>(6 * (size_t)OBS_MAX_TERMS);
@@ -506,6 +519,7 @@ static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, c
     o.off = ar.take<int>((size_t)OBS_MAX_POLY + 1);
     o.part = ar.take<double>(2 * 32 * 32);
     o.vpart = ar.take<double>((size_t)32 * 32 * VAR_CHUNKS * 10);
+    o.ering = ar.take<double>((size_t)GRAPH_RING * nprob);
     if (ob) *ob = o;
   }
   pr.assign(nprob, Prob());
@@ -856,8 +870,9 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
   hipStream_t s = wk.s;
   const int n = q.n, P = q.P, R = q.R;
   const long long nn = (long long)n * n;
-  // stage times are recorded for the problems of worker 0
-  StageTimer& tm = q.worker == 0 ? c->timer : c->mute;
+  // stage times are recorded for the problems of worker 0 (not while a step
+  // is being captured into a graph)
+  StageTimer& tm = q.worker == 0 && !c->capturing ? c->timer : c->mute;
   const int P0 = std::min(P, R - 1);  // pairs (0, a): their inverses feed the phases
   const bool fork = q.Q > 0;
   if (P > 0) {
@@ -955,6 +970,8 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
   a.tab_eps = o_eps ? o_eps : q.tab_eps;
   a.Gt = q.Gt; a.ht = q.ht; a.lam = q.lam; a.lamt = q.lamt; a.coef = q.coef; a.E = q.E;
   a.energy_slot = energy_slot; a.status = c->status;
+  a.slot_ctr = c->capturing ? c->ectr : nullptr;
+  a.slot_stride = (int)c->pr.size();
   a.g_thr = c->opt.g_rel_threshold;
   a.weight = c->opt.weight;
   tm.begin(SGS_STAGE_SOLVE, s);
@@ -969,7 +986,7 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
   hipStream_t s = wk.s;
   const int n = q.n, R = q.R;
   const long long nn = (long long)n * n;
-  StageTimer& tm = q.worker == 0 ? c->timer : c->mute;
+  StageTimer& tm = q.worker == 0 && !c->capturing ? c->timer : c->mute;
   tm.begin(SGS_STAGE_FORCE, s);
   const int fmode = c->opt.precision == SGS_FP64 ? FORCE_FP64 : FORCE_FP32;
   if (q.force_seq) {
@@ -1044,6 +1061,7 @@ void sgs_default_options(sgs_options* o) {
   o->exp_coef = 0.25;
   o->tune = nullptr;
   o->ntune = 0;
+  o->graph = 0;
 }
 
 static int check_options(const sgs_options& o) {
@@ -1055,6 +1073,7 @@ static int check_options(const sgs_options& o) {
   if (o.update != SGS_UPD_EULER && o.update != SGS_UPD_EXP) return SGS_EINVAL;
   if (!(o.exp_coef > 0.0 && o.exp_coef <= 1e6)) return SGS_EINVAL;
   if (o.ntune < 0 || o.ntune > 64 || (o.ntune > 0 && !o.tune)) return SGS_EINVAL;
+  if (o.graph != 0 && o.graph != 1) return SGS_EINVAL;
   for (int i = 0; i < o.ntune; ++i) {
     const sgs_tune& t = o.tune[i];
     if (t.n_max < 2 || (i > 0 && t.n_max <= o.tune[i - 1].n_max)) return SGS_EINVAL;
@@ -1075,7 +1094,7 @@ int sgs_workspace_bytes(const sgs_problem* probs, int32_t nprob, const sgs_optio
   for (int p = 0; p < nprob; ++p)
     if ((rc = check_problem(probs[p]))) return rc;
   std::vector<Prob> pr;
-  *bytes = plan(pr, probs, nprob, nullptr, device_lds_max(), o.streams, o.update == SGS_UPD_EXP, o);
+  *bytes = plan(pr, probs, nprob, nullptr, device_lds_max(), o.graph ? 1 : o.streams, o.update == SGS_UPD_EXP, o);
   return SGS_OK;
 }
 
@@ -1096,12 +1115,18 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
   c->s = (hipStream_t)stream;
   c->lds_max = device_lds_max();
   int nworkers = 1;
-  const size_t need = plan(c->pr, probs, nprob, (char*)workspace, c->lds_max, c->opt.streams,
+  // graph mode: one worker stream (the capture of several workers' fork and
+  // join ended the process in sgs_step on the device tested, cause not
+  // found; each problem still runs its inverses and phase chain on streams
+  // of its own inside the graph)
+  const size_t need = plan(c->pr, probs, nprob, (char*)workspace, c->lds_max, c->opt.graph ? 1 : c->opt.streams,
                            c->opt.update == SGS_UPD_EXP, c->opt, &c->obs, &nworkers);
   c->opt.tune = nullptr;  // read above; the caller's table need not outlive init
   c->opt.ntune = 0;
   if (ws_bytes < need) { delete c; return SGS_EWORKSPACE; }
   c->status = (int*)workspace;
+  c->ectr = (int*)workspace + 16;
+  c->ering = c->obs.ering;
   double* g = gamma;
   for (int p = 0; p < nprob; ++p) {
     c->pr[p].gam = g;
@@ -1195,9 +1220,75 @@ int sgs_pair_eval(sgs_ctx* c, double* log_abs_G, double* arg_G, double* eps, dou
   return SGS_OK;
 }
 
+// One step of every problem, enqueued (or captured) on the context's streams.
+static hipError_t enqueue_step(sgs_ctx* c, double dtau, double* energies, long long k) {
+  const int np = (int)c->pr.size();
+  if (c->fork() != hipSuccess) return hipErrorUnknown;
+  for (int p = 0; p < np; ++p) {
+    Prob& q = c->pr[p];
+    double* slot = c->capturing ? c->ering + p : (energies ? energies + k * np + p : nullptr);
+    HCHK(pair_stage(c, q, slot, nullptr, nullptr, nullptr));
+    HCHK(update_stage(c, q, dtau));
+  }
+  return c->join();
+}
+
+// Graph replay: one step of every problem captured once (again when dtau
+// changes), then launched nsteps times; the solve writes each replay's
+// energies at a device counter into the ring, which is copied out in chunks.
+static int step_graph(sgs_ctx* c, double dtau, int nsteps, double* energies) {
+  const int np = (int)c->pr.size();
+  if (!c->gexec || c->gdtau != dtau) {
+    if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+    if (!c->gs && hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking) != hipSuccess) return SGS_EHIP;
+    hipGraph_t g = nullptr;
+    // the private stream stands in for the context's stream (worker 0's)
+    // while the step is captured; the graph is launched on the context's
+    hipStream_t s0 = c->s;
+    c->s = c->gs;
+    c->wk[0].s = c->gs;
+    hipError_t e = hipStreamBeginCapture(c->gs, hipStreamCaptureModeThreadLocal);
+    const bool began = e == hipSuccess;
+    if (began) {
+      c->capturing = true;
+      e = enqueue_step(c, dtau, nullptr, 0);
+      if (e == hipSuccess) e = launch_bump_counter(c->ectr, c->gs);
+      c->capturing = false;
+    }
+    const hipError_t e2 = began ? hipStreamEndCapture(c->gs, &g) : e;
+    c->s = s0;
+    c->wk[0].s = s0;
+    if (e != hipSuccess || e2 != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return SGS_EHIP;
+    }
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { c->gexec = nullptr; return SGS_EHIP; }
+    c->gdtau = dtau;
+  }
+  for (int k0 = 0; k0 < nsteps; k0 += GRAPH_RING) {
+    const int kn = std::min(GRAPH_RING, nsteps - k0);
+    if (launch_set_counter(c->ectr, 0, c->s) != hipSuccess) return SGS_EHIP;
+    for (int k = 0; k < kn; ++k)
+      if (hipGraphLaunch(c->gexec, c->s) != hipSuccess) return SGS_EHIP;
+    if (energies && hipMemcpyAsync(energies + (long long)k0 * np, c->ering, (size_t)kn * np * sizeof(double),
+                                   hipMemcpyDeviceToDevice, c->s) != hipSuccess)
+      return SGS_EHIP;
+  }
+  return SGS_OK;
+}
+
 int sgs_step(sgs_ctx* c, double dtau, int32_t nsteps, double* energies) {
   if (!c || nsteps < 0 || !std::isfinite(dtau) || dtau <= 0.0) return SGS_EINVAL;
   const int np = (int)c->pr.size();
+  if (c->opt.graph && nsteps > 0) {
+    const int rc = step_graph(c, dtau, nsteps, energies);
+    if (rc != SGS_OK) return rc;
+    c->evaluated = false;
+    for (auto& w : c->wk) w.owner = -1;
+    return SGS_OK;
+  }
   // independent problems run concurrently, one stream per worker
   if (c->fork() != hipSuccess) return SGS_EHIP;
   for (int k = 0; k < nsteps; ++k)

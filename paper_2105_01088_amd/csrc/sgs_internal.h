@@ -156,6 +156,8 @@ struct SolveArgs {
   double* coef;         // c1 (R*R complex) then c2 (R*R complex)
   double* E;            // 1
   double* energy_slot;  // optional: energies[k * nprob + p]
+  const int* slot_ctr;  // optional: energy_slot is advanced by *slot_ctr * slot_stride
+  int slot_stride;
   int* status;
   double g_thr;
   int weight;           // 0 printed, 1 unit
@@ -210,6 +212,9 @@ hipError_t launch_build_c(int n, const double* gam, const double* T, const doubl
                           const int* qb, int Q, double* Cm, hipStream_t s);
 size_t solve_lds_bytes(int R);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
+// *ctr = v / *ctr += 1 (one thread), for the step counter of a replayed graph
+hipError_t launch_set_counter(int* ctr, int v, hipStream_t s);
+hipError_t launch_bump_counter(int* ctr, hipStream_t s);
 hipError_t set_solve_lds_limit(size_t bytes);
 // Observables (obs.hip): the current tables of one problem.
 struct ObsState {

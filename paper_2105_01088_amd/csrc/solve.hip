@@ -327,7 +327,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
   }
   if (tid == 0) {
     a.E[0] = E;
-    if (a.energy_slot) a.energy_slot[0] = E;
+    if (a.energy_slot) a.energy_slot[a.slot_ctr ? (long long)*a.slot_ctr * a.slot_stride : 0] = E;
   }
 }
 
@@ -339,6 +339,19 @@ size_t solve_lds_bytes(int R) {
 
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_solve, dim3(1), dim3(64), solve_lds_bytes(a.R), s, a);
+  return hipGetLastError();
+}
+
+__global__ void k_set_counter(int* ctr, int v) { *ctr = v; }
+__global__ void k_bump_counter(int* ctr) { *ctr += 1; }
+
+hipError_t launch_set_counter(int* ctr, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, s, ctr, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_bump_counter(int* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_bump_counter, dim3(1), dim3(1), 0, s, ctr);
   return hipGetLastError();
 }
 
