@@ -122,7 +122,8 @@ typedef struct {
                         /* summing a range of the terms, 1..4                */
   int32_t force_elem;   /* elementwise force terms: 1 beside the products on */
                         /* a second stream, 2 after them on the same stream  */
-  int32_t reserved[2];
+  int32_t force_tile;   /* force products: output tile edge, 64 or 128      */
+  int32_t reserved[1];
 } sgs_tune;
 
 typedef struct {

@@ -41,10 +41,11 @@ class sgs_problem(ctypes.Structure):
 
 class sgs_tune(ctypes.Structure):
     _fields_ = [("n_max", c_int32), ("gj_super", c_int32), ("gj_first", c_int32), ("pf_super", c_int32),
-                ("force_split", c_int32), ("force_elem", c_int32), ("reserved", c_int32 * 2)]
+                ("force_split", c_int32), ("force_elem", c_int32), ("force_tile", c_int32),
+                ("reserved", c_int32 * 1)]
 
 
-TUNE_FIELDS = ("n_max", "gj_super", "gj_first", "pf_super", "force_split", "force_elem")
+TUNE_FIELDS = ("n_max", "gj_super", "gj_first", "pf_super", "force_split", "force_elem", "force_tile")
 
 
 class sgs_options(ctypes.Structure):

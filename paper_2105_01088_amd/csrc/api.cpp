@@ -48,6 +48,7 @@ struct Prob {
   int gj_super = 128;  // super-panel width (a multiple of gj_nb)
   bool gj_first = false;  // pairs (0, a) inverted before the others start
   int force_split = 2;    // workgroups per force output tile (term ranges)
+  int force_tile = 0;     // force output tile edge (64 or 128; 0: by size and precision)
   bool force_seq = false;  // elementwise force terms after the products, same stream
   int worker = 0;  // stream (and scratch region) this problem runs on
   bool expmap = false;  // exponential-map update instead of Euler + purification
@@ -500,6 +501,7 @@ static void pick_tuning(Prob& q, const sgs_options& o) {
     if (t.pf_super > 0) q.pf_super = t.pf_super;
     if (t.force_split > 0) q.force_split = t.force_split;
     if (t.force_elem > 0) q.force_seq = t.force_elem == 2;
+    if (t.force_tile > 0) q.force_tile = t.force_tile;
     break;
   }
   q.gj_super = std::max(q.gj_nb, std::min(GJ_SUPER_MAX, q.gj_super / q.gj_nb * q.gj_nb));
@@ -989,9 +991,10 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
   StageTimer& tm = q.worker == 0 && !c->capturing ? c->timer : c->mute;
   tm.begin(SGS_STAGE_FORCE, s);
   const int fmode = c->opt.precision == SGS_FP64 ? FORCE_FP64 : FORCE_FP32;
+  const int ftile = q.force_tile ? q.force_tile : force_tile_default(n, fmode);
   if (q.force_seq) {
     // the elementwise terms after the dense products, on the same stream
-    HCHK(launch_force(n, R, q.terms, q.coef, q.dG, q.dP, q.dgnorm, fmode, q.force_split, s));
+    HCHK(launch_force(n, R, q.terms, q.coef, q.dG, q.dP, q.dgnorm, fmode, q.force_split, ftile, s));
     HCHK(launch_force_elem(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, fmode == FORCE_FP32, q.dE, s));
     tm.end(SGS_STAGE_FORCE, s);
   } else {
@@ -1001,7 +1004,7 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
     HCHK(hipStreamWaitEvent(wk.s2, wk.ev_f, 0));
     HCHK(launch_force_elem(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, fmode == FORCE_FP32, q.dE, wk.s2));
     HCHK(hipEventRecord(wk.ev_fe, wk.s2));
-    HCHK(launch_force(n, R, q.terms, q.coef, q.dG, q.dP, q.dgnorm, fmode, q.force_split, s));
+    HCHK(launch_force(n, R, q.terms, q.coef, q.dG, q.dP, q.dgnorm, fmode, q.force_split, ftile, s));
     tm.end(SGS_STAGE_FORCE, s);
     HCHK(hipStreamWaitEvent(s, wk.ev_fe, 0));
   }
@@ -1078,7 +1081,8 @@ static int check_options(const sgs_options& o) {
     const sgs_tune& t = o.tune[i];
     if (t.n_max < 2 || (i > 0 && t.n_max <= o.tune[i - 1].n_max)) return SGS_EINVAL;
     if (t.gj_super > GJ_SUPER_MAX || t.gj_first > 2 || t.pf_super > PF_SUPER_MAX ||
-        t.force_split > FORCE_SPLIT_MAX || t.force_elem > 2)
+        t.force_split > FORCE_SPLIT_MAX || t.force_elem > 2 ||
+        (t.force_tile != 0 && t.force_tile != 64 && t.force_tile != 128))
       return SGS_EINVAL;
   }
   return SGS_OK;
@@ -1140,7 +1144,8 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
   int nmax = 2;
   for (auto& q : c->pr) nmax = std::max(nmax, q.n);
   if (set_gj_lds_limit(lds_gj) != hipSuccess || set_solve_lds_limit(lds_solve) != hipSuccess ||
-      set_renyi2_lds_limit() != hipSuccess || set_pf_sign_lds_limit(nmax) != hipSuccess) {
+      set_renyi2_lds_limit() != hipSuccess || set_pf_sign_lds_limit(nmax) != hipSuccess ||
+      set_force_lds_limit() != hipSuccess) {
     delete c;
     return SGS_EHIP;
   }

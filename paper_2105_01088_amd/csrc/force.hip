@@ -500,20 +500,210 @@ __global__ __launch_bounds__(256) void k_force_join(double* __restrict__ dG, con
     atomicMax(nrm + mu, (unsigned long long)__double_as_longlong(nan_max(nan_max(red[0], red[1]), nan_max(red[2], red[3]))));
 }
 
+// The dense products with 128 x 128 output tiles, for large n: eight waves,
+// each holding a 32 x 64 block of the tile in 2 x 4 MFMA accumulators, so a
+// workgroup stages twice the operand bytes of a 64 x 64 tile per slab for four
+// times the matrix-core work (16 instead of 8 flops per staged byte).  The K
+// slabs (16 deep) are double-buffered in LDS: the raw loads of slab k + 1 are
+// in flight while slab k is multiplied, then written (with the B operand
+// formed, as in k_force) into the other buffer, one barrier per slab.  One
+// workgroup per CU (the buffers take 132 KB of LDS in float64), two waves per
+// SIMD.  (Four waves of 64 x 64, one per SIMD, left the LDS-to-MFMA latency
+// exposed: 49 instead of 26 ms at n = 800, R = 32.)  Grid, XCD mapping,
+// term split and skew write-out as in k_force; diagonal tiles are made
+// exactly skew through LDS.
+constexpr int FB_T = 128;            // tile edge
+constexpr int FB_LP = FB_T + 4;      // LDS pitch (elements)
+
+template <typename TT>
+constexpr size_t force_big_lds_bytes() {
+  return (2 * 2 * 2 * FTK * FB_LP * sizeof(TT)) > (FB_T * (FB_T + 1) * sizeof(double))
+             ? (2 * 2 * 2 * FTK * FB_LP * sizeof(TT))
+             : (FB_T * (FB_T + 1) * sizeof(double));
+}
+
+template <typename TT, bool IY>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_force_big(
+    int n, int R, int T, int nsplit, const ForceTerm* __restrict__ terms, const double* __restrict__ coef,
+    double* __restrict__ dG, double* __restrict__ dP, unsigned long long* __restrict__ nrm) {
+  typedef typename Vec4<TT>::type V4;
+  extern __shared__ __attribute__((aligned(16))) char lds_big[];
+  typedef TT Slab[FTK][FB_LP];
+  Slab* As = (Slab*)lds_big;      // As[buf * 2 + part]
+  Slab* Bs = (Slab*)lds_big + 4;  // Bs[buf * 2 + part]
+  double (*Tt)[FB_T + 1] = (double (*)[FB_T + 1])lds_big;
+
+  const int ntri = T * (T + 1) / 2;
+  const int xcd = blockIdx.x & 7, loc2 = blockIdx.x >> 3;
+  const int split = loc2 % nsplit, loc = loc2 / nsplit;
+  const int mu = xcd + 8 * (loc / ntri);
+  if (mu >= R) return;
+  const int b_lo = split * R / nsplit, b_hi = (split + 1) * R / nsplit;
+  if (loc % ntri == 0 && split == 0 && threadIdx.x == 0) nrm[mu] = 0ull;  // k_force_join accumulates it
+  int tri = loc % ntri, I = 0;
+  while (tri >= T - I) { tri -= T - I; ++I; }
+  const int J = I + tri;
+  const int row0 = I * FB_T, col0 = J * FB_T;
+  const long long nn = (long long)n * n;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;  // rows wm * 32 .. +31, columns wn * 64 .. +63
+  V4 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = V4{0, 0, 0, 0};
+
+  const double* c1t = coef;
+  // A slab: rows row0 .. +127, k kc .. kc+15 (thread: row tid >> 2, 4
+  // consecutive k); B slab: k kc .. kc+15, columns col0 .. +127 (thread:
+  // column tid & 127, k rows 4 (tid >> 7) + r)
+  const int a_i = tid >> 2, a_k = (tid & 3) * 4;
+  const int b_k = (tid >> 7) * 4, b_j = tid & 127;
+
+  for (int b = b_lo; b < b_hi; ++b) {
+    const ForceTerm tm = terms[mu * R + b];
+    const double x1 = c1t[2 * tm.coef], y1 = c1t[2 * tm.coef + 1];
+    const bool im = tm.Yi != nullptr;
+    const double sg = tm.sgn, ds = tm.dr_scale;
+    const double sgi = im ? sg : 0.0;  // zero imaginary parts for a real term
+    const SGS_GLOBAL double* __restrict__ Yr = as_global(tm.Yr);
+    const SGS_GLOBAL double* __restrict__ Yi = as_global(im ? tm.Yi : tm.Yr);
+    const SGS_GLOBAL double* __restrict__ Dr = as_global(tm.Dr);
+    const SGS_GLOBAL double* __restrict__ Di = as_global(im ? tm.Di : tm.Dr);
+    double ra[2][4], rd[2][4];
+    auto load = [&](int kc) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = row0 + a_i, gk = kc + a_k + r;
+        const bool ok = gi < n && gk < n;
+        const long long o = ok ? (long long)gi * n + gk : 0;
+        ra[0][r] = ok ? Yr[o] : 0.0;
+        ra[1][r] = ok ? Yi[o] : 0.0;
+        const int gk2 = kc + b_k + r, gj = col0 + b_j;
+        const bool okb = gk2 < n && gj < n;
+        const long long ob = okb ? (long long)gk2 * n + gj : 0;
+        rd[0][r] = okb ? Dr[ob] : 0.0;
+        rd[1][r] = okb ? Di[ob] : 0.0;
+      }
+    };
+    auto store = [&](int kc, int buf) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // IY: B = c1 (D + i 1), so the product also carries Re(c1 i Y)
+        const double dr = ds * rd[0][r],
+                     di = sgi * rd[1][r] + (IY && kc + b_k + r == col0 + b_j && col0 + b_j < n ? 1.0 : 0.0);
+        As[2 * buf][a_k + r][a_i] = (TT)ra[0][r];
+        As[2 * buf + 1][a_k + r][a_i] = (TT)(sgi * ra[1][r]);
+        Bs[2 * buf][b_k + r][b_j] = (TT)(x1 * dr - y1 * di);
+        Bs[2 * buf + 1][b_k + r][b_j] = (TT)(-(x1 * di + y1 * dr));
+      }
+    };
+    __syncthreads();  // the previous term's last slab has been read
+    load(0);
+    store(0, 0);
+    __syncthreads();
+    int buf = 0;
+    for (int kc = 0; kc < n; kc += FTK) {
+      const bool more = kc + FTK < n;
+      if (more) load(kc + FTK);
+#pragma unroll
+      for (int kk = 0; kk < FTK / 4; ++kk) {
+        const int kr = kk * 4 + (lane >> 4);
+        TT ah[2][2], bh[2][4];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) ah[u][q] = As[2 * buf + u][kr][wm * 32 + q * 16 + (lane & 15)];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bh[u][q] = Bs[2 * buf + u][kr][wn * 64 + q * 16 + (lane & 15)];
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma_t(ah[0][bi], bh[0][bj], acc[bi][bj]);
+        if (im) {
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma_t(ah[1][bi], bh[1][bj], acc[bi][bj]);
+        }
+      }
+      if (more) store(kc + FTK, buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  // ---- total, skew write-out ----
+  __syncthreads();
+  double* out = (split == 0 ? dG : dP + (long long)(split - 1) * R * nn) + (long long)mu * nn;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int li = wm * 32 + bi * 16 + acc_row<TT>(lane, r);
+        const int lj = wn * 64 + bj * 16 + (lane & 15);
+        const int gi = row0 + li, gj = col0 + lj;
+        double v = 0.0;
+        if (gi < n && gj < n) v = (double)acc[bi][bj][r];
+        if (I == J) Tt[li][lj] = v;
+        else if (gi < n && gj < n) {
+          out[(long long)gi * n + gj] = v;
+          out[(long long)gj * n + gi] = -v;
+        }
+      }
+  if (I == J) {
+    __syncthreads();
+    for (int e = tid; e < FB_T * FB_T; e += 512) {
+      const int li = e / FB_T, lj = e % FB_T;
+      const int gi = row0 + li, gj = col0 + lj;
+      if (gi < n && gj < n) out[(long long)gi * n + gj] = 0.5 * (Tt[li][lj] - Tt[lj][li]);
+    }
+  }
+}
+
+hipError_t set_force_lds_limit() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_force_big<double, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)force_big_lds_bytes<double>());
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_force_big<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)force_big_lds_bytes<float>());
+}
+
 // upper-triangle tiles of edge e that cover n, times the tile area
 static long long force_area(int n, int e) {
   const long long t = (n + e - 1) / e;
   return t * (t + 1) / 2 * e * e;
 }
 
+// Built-in tile edge: 128 x 128 where measured faster (float64 at n = 1204:
+// 64.7 instead of 69.2 ms; at n = 800 the 64 x 64 tiles win, 25.7 against
+// 35.6 ms; float32 from n = 600: 68 -> ~50 ms at n = 1204)
+int force_tile_default(int n, int mode) { return n >= (mode == FORCE_FP32 ? 600 : 1000) ? 128 : 64; }
+
 hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, double* dG, double* dP,
-                        unsigned long long* nrm, int mode, int nsplit, hipStream_t s) {
+                        unsigned long long* nrm, int mode, int nsplit, int tile, hipStream_t s) {
+  const bool big = tile == 128;
   if (nsplit < 1 || nsplit > FORCE_SPLIT_MAX || nsplit > R) return hipErrorInvalidValue;
   const int per_xcd = (R + 7) / 8;
-  if (mode == FORCE_FP32 && force_area(n, FS_T) < force_area(n, 64)) {
+  if (mode == FORCE_FP32 && !big && force_area(n, FS_T) < force_area(n, 64)) {
     const int T = (n + FS_T - 1) / FS_T;
     const dim3 grid(8 * per_xcd * (T * (T + 1) / 2) * nsplit), block(FS_THREADS);
     hipLaunchKernelGGL((k_force_strip<float>), grid, block, 0, s, n, R, T, nsplit, terms, coef, dG, dP, nrm);
+    return hipGetLastError();
+  }
+  if (big) {
+    const int T = (n + FB_T - 1) / FB_T;
+    const dim3 grid(8 * per_xcd * (T * (T + 1) / 2) * nsplit), block(512);
+    if (mode == FORCE_FP64)
+      hipLaunchKernelGGL((k_force_big<double, true>), grid, block, force_big_lds_bytes<double>(), s, n, R, T, nsplit,
+                         terms, coef, dG, dP, nrm);
+    else
+      hipLaunchKernelGGL((k_force_big<float, false>), grid, block, force_big_lds_bytes<float>(), s, n, R, T, nsplit,
+                         terms, coef, dG, dP, nrm);
     return hipGetLastError();
   }
   const int T = (n + 63) / 64;

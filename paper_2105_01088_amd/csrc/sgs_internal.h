@@ -268,8 +268,11 @@ enum : int { FORCE_FP64 = 0, FORCE_FP32 = 1 };
 // the elementwise terms into dE; k_force_join: dG += (the dP slices) + dE and
 // the 1-norms.
 constexpr int FORCE_SPLIT_MAX = 4;
+hipError_t set_force_lds_limit();  // the 128 x 128 tile kernels' LDS (once per context)
+int force_tile_default(int n, int mode);  // 64 or 128
+// tile: output tile edge, 64 or 128
 hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, double* dG, double* dP,
-                        unsigned long long* nrm, int mode, int nsplit, hipStream_t s);
+                        unsigned long long* nrm, int mode, int nsplit, int tile, hipStream_t s);
 // direct_y = 0: the products carry Re(c1 i Y) (FP64: B = c1 (D + i 1)) and
 // k_force_elem leaves it out
 hipError_t launch_force_elem(int n, int R, const ForceTerm* terms, const double* coef, const double* A,

@@ -249,3 +249,22 @@ def test_fp32_plain_error_bound():
     assert np.abs(g32 - g64).max() < 1e-5
     assert np.abs(e32 - e64).max() < 1e-8 * np.abs(e64).max()
     assert np.all(np.diff(e32) <= 1e-10 * abs(e32[0]))
+
+
+@pytest.mark.parametrize("tile", [64, 128])
+@pytest.mark.parametrize("L,R,seed", [(32, 3, 5), (64, 4, 6)])
+def test_force_tiles_match_oracle(tile, L, R, seed):
+    """Both force tile edges (64 x 64, 128 x 128 with eight waves) on ragged
+    sizes n = 132 and 260 (one tile plus a sliver; two plus a sliver),
+    whatever the built-in choice for that n: one step at 1e-10."""
+    ham = si.anderson(L, 1.2, 0.7)
+    gam = si.random_states(ham.N, R, seed)
+    _say(f"[step] force tile {tile}, n={ham.n} R={R}")
+    ctx = _ctx(ham, gam, weight=1, tune=[{"n_max": 4096, "force_tile": tile}])
+    e = ctx.step(0.05, 1)
+    assert ctx.status() == 0
+    g_new = ctx.gammas(0).cpu().numpy()
+    ref = osgs.step(ham, gam, 0.05, mode="unit")
+    assert abs(e.cpu().item() - ref.E) < TOL_E * abs(ref.E)
+    assert np.abs(g_new - ref.gammas).max() < TOL_GAMMA
+    ctx.close()
