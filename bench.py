@@ -30,11 +30,18 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 
-# HBM bytes per k_force launch, from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# counters on this workload (FETCH_SIZE scaled by 2.0, WRITE_SIZE by 1.0: the
-# factors a 1 GiB device copy reads back).  Only valid for the kernel and
-# workload it was taken on; any other combination reports null.
-FORCE_TRAFFIC_BYTES = {("anderson_L99_R16", "fp64"): 2.666e9}
+# HBM bytes per launch of the force products, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE counters on the workload (FETCH_SIZE scaled by 1.99989,
+# WRITE_SIZE by 1.0: the factors a 1 GiB device copy reads back), in
+# profiles/force_tck_L150_R24_fp64.md.  Only valid for the kernel and workload
+# they were taken on; any other combination reports null.
+FORCE_TRAFFIC_BYTES = {("tck_L150_R24_J0.3", "fp64", "k_force_big"): 6.6228e10}
+
+
+def force_kernel(n: int, precision: str) -> str:
+    """Name of the force-product kernel the library's built-in choice uses:
+    128 x 128 tiles from n = 1000 in float64 (n = 600 in float32)."""
+    return "k_force_big" if n >= (600 if precision == "fp32" else 1000) else "k_force"
 
 
 def inverse_flops(n: int, P: int) -> float:
@@ -281,12 +288,13 @@ def main(argv=None):
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_force",
+            "kernel": force_kernel(n, args.precision),
             "achieved": achieved,
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak if achieved is not None else None,
-            "traffic": FORCE_TRAFFIC_BYTES.get((args.config, args.precision)),
+            "traffic": (None if args.tune else
+                        FORCE_TRAFFIC_BYTES.get((args.config, args.precision, force_kernel(n, args.precision)))),
             "force_avg_ms": f_avg_ms,
             "force_flops_per_launch": force_flops(n, R),
         },
