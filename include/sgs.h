@@ -90,6 +90,11 @@ extern "C" {
 #define SGS_OBS_RENYI2 2    /* S_2 = -ln Tr rho_A^2, Eq. (S2_SGS)              */
 #define SGS_OBS_VARIANCE 3  /* <H>, <H^2>, delta_H^2 of Eq. (residual)         */
 
+/* Renyi-2 evaluation methods (SGS_OBS_RENYI2, optional third iarg) */
+#define SGS_REN_AUTO 0   /* by subsystem size and conditioning               */
+#define SGS_REN_BLOCK 1  /* block form of order 2 nA for every term          */
+#define SGS_REN_SPLIT 2  /* split form wherever a block is invertible        */
+
 typedef struct sgs_ctx sgs_ctx; /* opaque */
 
 /* One impurity problem (Sec. II.A).  Host pointers, read by sgs_init only. */
@@ -230,10 +235,25 @@ int sgs_energy(sgs_ctx* ctx, double* E, double* lambda);
  *                   out (device) = 2*npoly doubles, complex results.
  *                   Limits: npoly <= 4096, nterm <= 16384.  Waits for the
  *                   stream before returning.
- *   SGS_OBS_RENYI2: iargs = {problem, nA} with nA even, the subsystem being
- *                   Majoranas 0..nA-1 (2 <= nA <= 32); dargs unused;
- *                   out (device) = 1 double, S_2 = -ln Tr rho_A^2
- *                   (Eq. S2_SGS, App. B; R^4 Pfaffians of order 2 nA).
+ *   SGS_OBS_RENYI2: iargs = {problem, nA} or {problem, nA, method} with nA
+ *                   even, 2 <= nA <= min(n, 1024), the subsystem being
+ *                   Majoranas 0..nA-1; dargs unused; out (device) =
+ *                   1 double, S_2 = -ln Tr rho_A^2 (Eq. S2_SGS, App. B).
+ *                   Only one term per orbit of the rank-4 tensor's two
+ *                   symmetries (exchange of the pairs, complex
+ *                   conjugation) is evaluated, about R^4 / 4 Pfaffians.
+ *                   method: SGS_REN_AUTO (default): block form of
+ *                   Eq. (pfMA), order 2 nA, in on-chip memory for
+ *                   nA <= 32; above that the split form of
+ *                   Eq. (TrArho2_final), Pf(K_q) Pf(K_p - K_q^{-1}) of
+ *                   order nA, inverting the better-conditioned block, and
+ *                   the block form for terms whose blocks both have a
+ *                   1-norm condition number above 1e6.  SGS_REN_BLOCK:
+ *                   block form for every term (batched).  SGS_REN_SPLIT:
+ *                   split form wherever a block is invertible.
+ *                   Above nA = 32 the call allocates device memory (kept
+ *                   by the context, up to about 2 GiB plus
+ *                   R (R + 1) nA^2 16 bytes) and waits for the stream.
  *   SGS_OBS_VARIANCE: iargs = {problem}; dargs unused; out (device) =
  *                   3 doubles {<H>, <H^2>, delta_H^2 = <H^2> - <H>^2} of the
  *                   problem's Hamiltonian (Eq. residual, Sec. IV.A), by

@@ -21,6 +21,9 @@ from ._lib import (  # noqa: F401
     SGS_OBS_POLY,
     SGS_OBS_RENYI2,
     SGS_OBS_VARIANCE,
+    SGS_REN_AUTO,
+    SGS_REN_BLOCK,
+    SGS_REN_SPLIT,
     rotate_state,
     rotate_state_noalloc,
 )

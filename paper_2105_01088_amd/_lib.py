@@ -25,6 +25,7 @@ SGS_UPD_EXP = 1
 SGS_OBS_POLY = 1
 SGS_OBS_RENYI2 = 2
 SGS_OBS_VARIANCE = 3
+SGS_REN_AUTO, SGS_REN_BLOCK, SGS_REN_SPLIT = 0, 1, 2
 STAGES = ("inverse", "delta", "wick", "phase", "pfaffian", "solve", "force", "purify")
 
 
@@ -316,9 +317,11 @@ class SGS:
         v = self.observables(SGS_OBS_VARIANCE, [int(problem)], [], 3).cpu().numpy()
         return float(v[0]), float(v[1]), float(v[2])
 
-    def renyi2(self, nA: int, problem: int = 0) -> float:
-        """S_2 = -ln Tr rho_A^2 of the current state, A = Majoranas 0..nA-1."""
-        return float(self.observables(SGS_OBS_RENYI2, [int(problem), int(nA)], [], 1).cpu().item())
+    def renyi2(self, nA: int, problem: int = 0, method: int = SGS_REN_AUTO) -> float:
+        """S_2 = -ln Tr rho_A^2 of the current state, A = Majoranas 0..nA-1;
+        method: SGS_REN_AUTO, SGS_REN_BLOCK or SGS_REN_SPLIT."""
+        iargs = [int(problem), int(nA), int(method)]
+        return float(self.observables(SGS_OBS_RENYI2, iargs, [], 1).cpu().item())
 
     def set_timing(self, on: bool = True):
         _check(self.lib.sgs_set_timing(self.ctx, 1 if on else 0), "sgs_set_timing")

@@ -42,6 +42,22 @@ struct JobTable {
   XcdMap xm{};
 };
 
+// Batched Pfaffians of B complex skew matrices of order m, planar (matrix b
+// at A0 + 2 m^2 b, imaginary plane at + m^2, leading dimension m).  Blocked
+// on two levels (register panels inside super-panels of `super` steps, then
+// one trailing complex GEMM per super-panel); the trailing matrices ping-pong
+// between A0 and A1, so A0 does not survive a run.
+struct PfBatch {
+  int m = 0, B = 0, super = PF_SUPER_MAX;
+  double *A0 = nullptr, *A1 = nullptr, *UV = nullptr, *RM = nullptr, *PD = nullptr;
+  int* perm = nullptr;
+  long long uvstride = 0, uv_im = 0, pdstride = 0;
+  struct Panel { int sp, p0, ns, kd; };
+  std::vector<int> sm, sk;   // super-panels: stored order, steps
+  std::vector<Panel> pan;    // register panels of every super-panel
+  std::vector<JobTable> jt;  // trailing update of each super-panel
+};
+
 struct Prob {
   int N = 0, n = 0, R = 0, P = 0, Q = 0, M = 0, nq = 0, nnz_up = 0, nnz = 0;
   int gj_nb = 16;
@@ -57,11 +73,11 @@ struct Prob {
   double a2 = 0.0;  // |A|_F^2
   double* gam = nullptr;
   // dense work
-  double *W, *Di, *Y, *Yd, *T1, *Xr, *Cm, *Cm2, *UV, *RM, *PD, *gjE, *gjB, *dG, *dP, *dE, *nsX0, *nsX1, *nsQ, *Adense;
+  double *W, *Di, *Y, *Yd, *T1, *Xr, *gjE, *gjB, *dG, *dP, *dE, *nsX0, *nsX1, *nsQ, *Adense;
   // small
   double *pfacc, *logdet, *eps, *Fc, *coef, *Gt, *ht, *lam, *lamt, *E, *tab_la, *tab_arg, *tab_eps;
   double *up_v, *colval, *q_val;
-  int *piv, *pa, *pb, *qa, *qb, *pidx, *qidx, *up_k, *up_l, *colptr, *rowidx, *imp, *impos, *q_idx, *q_loc, *pfperm;
+  int *piv, *pa, *pb, *qa, *qb, *pidx, *qidx, *up_k, *up_l, *colptr, *rowidx, *imp, *impos, *q_idx, *q_loc;
   unsigned long long* resid;
   unsigned long long* nsres;
   unsigned long long* dgnorm;
@@ -76,14 +92,10 @@ struct Prob {
   ExpCoef excf{};
   // Gauss-Jordan: inner updates per panel and trailing updates per
   // super-panel, for the pairs (0, a) (jgj0, jgs0) and the rest (jgj1, jgs1)
-  std::vector<JobTable> jgj0, jgj1, jgs0, jgs1, jpf;
+  std::vector<JobTable> jgj0, jgj1, jgs0, jgs1;
   std::vector<int> gj_k, gj_b, gj_s, gs_k, gs_nb;
-  // Pfaffian: super-panels (stored size, steps) and their register panels
-  int pf_super = PF_SUPER_MAX;
-  struct PfPanel { int sp, p0, ns, kd; };
-  std::vector<int> ps_m, ps_k;
-  std::vector<PfPanel> pf_pan;
-  long long uvstride = 0, uv_im = 0, pdstride = 0;
+  // Pfaffians of the Q matrices C_ab (order n)
+  PfBatch pf;
 };
 
 // per pair: the panel's Brow (b x super-panel) or a super-panel's pivot rows (nb x n)
@@ -203,7 +215,6 @@ struct ObsBuf {
   int* rows = nullptr;
   double* coef = nullptr;
   int* off = nullptr;
-  double* part = nullptr;
   double* vpart = nullptr;  // variance partial sums, R (R + 1) / 2 x VAR_CHUNKS x 5 complex
 };
 
@@ -231,6 +242,9 @@ struct sgs_ctx {
   StageTimer timer;
   StageTimer mute;  // never switched on
   ObsBuf obs;
+  // device buffers of the Renyi-2 evaluation, grown on demand
+  void* ren = nullptr;
+  size_t ren_bytes = 0;
   // graph replay of one step (sgs_options.graph): the energies of successive
   // replays go to ering[ctr * nprob + p], copied out after the replays
   hipGraphExec_t gexec = nullptr;
@@ -255,6 +269,7 @@ struct sgs_ctx {
       if (w.own_s && w.s) (void)hipStreamDestroy(w.s);
     }
     if (ev_start) (void)hipEventDestroy(ev_start);
+    if (ren) (void)hipFree(ren);
   }
   // fork: every worker stream waits for the work enqueued so far on s
   hipError_t fork() {
@@ -309,6 +324,48 @@ static int nnz_count(const sgs_problem& p, int* up) {
   return nz;
 }
 
+// Buffers of a Pfaffian batch (order m, B matrices).
+static void pf_carve(PfBatch& b, Arena& ar) {
+  const long long mm = (long long)b.m * b.m;
+  b.uvstride = 2LL * b.m * 2 * PF_SUPER_MAX;  // planar: re block then im block
+  b.uv_im = (long long)b.m * 2 * PF_SUPER_MAX;
+  b.pdstride = 4LL * b.m * PF_SUPER_MAX;  // deferred columns: [row][step][U re, U im, V re, V im]
+  b.A0 = ar.take<double>(std::max(1LL, 2 * b.B * mm));
+  b.A1 = ar.take<double>(std::max(1LL, 2 * b.B * mm));
+  b.perm = ar.take<int>(std::max(1LL, (long long)b.B * b.m));
+  b.UV = ar.take<double>(std::max(1LL, b.B * b.uvstride));
+  b.RM = ar.take<double>(std::max(1LL, b.B * b.uvstride));
+  b.PD = ar.take<double>(std::max(1LL, b.B * b.pdstride));
+}
+
+// Schedule of a Pfaffian batch: super-panels of `super` steps (fewer at the
+// end), each swept by register panels sized for the rows they hold; storage
+// for the job table of every super-panel's trailing update.
+static void pf_schedule(PfBatch& b, Arena& ar) {
+  b.sm.clear(); b.sk.clear(); b.pan.clear();
+  for (int m = b.m; m > 0;) {
+    const int k = std::min(b.super, m / 2);
+    const int sp = (int)b.sm.size();
+    b.sm.push_back(m);
+    b.sk.push_back(k);
+    for (int done = 0; done < k;) {
+      const int p0 = 2 * done;
+      const int ns = std::min(pf_panel_shape(m - p0).nbh, k - done);
+      b.pan.push_back({sp, p0, ns, done});
+      done += ns;
+    }
+    m -= 2 * k;
+  }
+  const int T = (b.m + 63) / 64;
+  const int jobs = std::max(1, b.B);
+  b.jt.assign(b.sm.size(), JobTable());
+  for (auto& t : b.jt) {
+    t.dev = ar.take<GemmJob>(jobs);
+    t.map_cap = 8 * jobs * T * T;
+    t.dmap = ar.take<int>((size_t)t.map_cap);
+  }
+}
+
 // Scratch of one evaluation: per-pair and per-state dense matrices.  Problems
 // that run one after another on the same worker stream share one region.
 static void carve_scratch(Prob& q, Arena& ar) {
@@ -320,15 +377,7 @@ static void carve_scratch(Prob& q, Arena& ar) {
   q.Yd = ar.take<double>(R * nn);
   q.T1 = ar.take<double>(std::max(1LL, (R - 1) * nn));
   q.Xr = ar.take<double>(std::max(1LL, (R - 1) * nn));
-  q.Cm = ar.take<double>(std::max(1LL, 2 * Q * nn));
-  q.Cm2 = ar.take<double>(std::max(1LL, 2 * Q * nn));
-  q.uvstride = 2LL * n * 2 * PF_SUPER_MAX;  // planar: re block then im block
-  q.uv_im = (long long)n * 2 * PF_SUPER_MAX;
-  q.pdstride = 4LL * n * PF_SUPER_MAX;  // deferred columns: [row][step][U re, U im, V re, V im]
-  q.pfperm = ar.take<int>(std::max(1LL, (long long)Q * n));
-  q.UV = ar.take<double>(std::max(1LL, Q * q.uvstride));
-  q.RM = ar.take<double>(std::max(1LL, Q * q.uvstride));
-  q.PD = ar.take<double>(std::max(1LL, Q * q.pdstride));
+  pf_carve(q.pf, ar);
   q.gjE = ar.take<double>(std::max(1LL, (long long)P * n * GJ_NB_MAX));
   q.gjB = ar.take<double>(std::max(1LL, (long long)P * gj_brow_stride(n)));
   q.dG = ar.take<double>(R * nn);
@@ -423,24 +472,7 @@ static void carve_jobs(Prob& q, Arena& ar) {
   for (auto& t : q.jgj1) table(t, q.P - P0);
   for (auto& t : q.jgs0) table(t, 2 * P0);
   for (auto& t : q.jgs1) table(t, 2 * (q.P - P0));
-  // Pfaffian schedule: super-panels of pf_super steps (fewer at the end),
-  // each swept by register panels sized for the rows they hold
-  q.ps_m.clear(); q.ps_k.clear(); q.pf_pan.clear();
-  for (int m = n; m > 0;) {
-    const int k = std::min(q.pf_super, m / 2);
-    const int sp = (int)q.ps_m.size();
-    q.ps_m.push_back(m);
-    q.ps_k.push_back(k);
-    for (int done = 0; done < k;) {
-      const int p0 = 2 * done;
-      const int ns = std::min(pf_panel_shape(m - p0).nbh, k - done);
-      q.pf_pan.push_back({sp, p0, ns, done});
-      done += ns;
-    }
-    m -= 2 * k;
-  }
-  q.jpf.assign(q.ps_m.size(), JobTable());
-  for (auto& t : q.jpf) table(t, q.Q);
+  pf_schedule(q.pf, ar);
   table(q.jdi, q.P);
   table(q.jya, q.denseA ? 2 * q.P + q.R : 0);
   table(q.jt1, q.R - 1);
@@ -479,15 +511,17 @@ constexpr int MAX_WORKERS = 4;  // concurrent streams for independent problems
 // instead of the compressed-column product
 constexpr int DENSE_A_PER_COLUMN = 16;
 
+// Pfaffian super-panels of 32 steps (rank-64 trailing updates) beat 16 and
+// 24 at n = 800 and 1204 (92.5 / 95.0 / 93.3 and 190 / 200 / 193 ms per
+// step); at n = 400 one register panel of 16 steps per update is best (the
+// chain is bound by the panels' latency there, not by the updates)
+static int pf_super_default(int m) { return m <= 512 ? 16 : PF_SUPER_MAX; }
+
 // Built-in scheduling choices by size, then the caller's tuning row (if any).
 static void pick_tuning(Prob& q, const sgs_options& o) {
   q.gj_nb = pick_gj_nb(q.n, 0);
   q.gj_super = 128;
-  // Pfaffian super-panels of 32 steps (rank-64 trailing updates) beat 16 and
-  // 24 at n = 800 and 1204 (92.5 / 95.0 / 93.3 and 190 / 200 / 193 ms per
-  // step); at n = 400 one register panel of 16 steps per update is best (the
-  // chain is bound by the panels' latency there, not by the updates)
-  q.pf_super = q.n <= 512 ? 16 : PF_SUPER_MAX;
+  q.pf.super = pf_super_default(q.n);
   // measured at n = 400, 800, 1204: both batches of inverses start together
   // (with the pairs (0, a) first the phase chain then shares the GPU with the
   // other inverses for its whole length: 256 instead of 253 ms per step at
@@ -498,14 +532,14 @@ static void pick_tuning(Prob& q, const sgs_options& o) {
     if (q.n > t.n_max) continue;
     if (t.gj_super > 0) q.gj_super = t.gj_super;
     if (t.gj_first > 0) q.gj_first = t.gj_first == 1;
-    if (t.pf_super > 0) q.pf_super = t.pf_super;
+    if (t.pf_super > 0) q.pf.super = t.pf_super;
     if (t.force_split > 0) q.force_split = t.force_split;
     if (t.force_elem > 0) q.force_seq = t.force_elem == 2;
     if (t.force_tile > 0) q.force_tile = t.force_tile;
     break;
   }
   q.gj_super = std::max(q.gj_nb, std::min(GJ_SUPER_MAX, q.gj_super / q.gj_nb * q.gj_nb));
-  q.pf_super = std::max(1, std::min(PF_SUPER_MAX, q.pf_super));
+  q.pf.super = std::max(1, std::min(PF_SUPER_MAX, q.pf.super));
   q.force_split = std::max(1, std::min(std::min(FORCE_SPLIT_MAX, q.R), q.force_split));
 }
 
@@ -519,7 +553,6 @@ static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, c
     o.rows = ar.take<int>(6 * (size_t)OBS_MAX_TERMS);
     o.coef = ar.take<double>(2 * (size_t)OBS_MAX_TERMS);
     o.off = ar.take<int>((size_t)OBS_MAX_POLY + 1);
-    o.part = ar.take<double>(2 * 32 * 32);
     o.vpart = ar.take<double>((size_t)32 * 32 * VAR_CHUNKS * 10);
     o.ering = ar.take<double>((size_t)GRAPH_RING * nprob);
     if (ob) *ob = o;
@@ -531,6 +564,8 @@ static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, c
     q.N = sp.N; q.n = 2 * sp.N; q.R = sp.R;
     q.P = q.R * (q.R - 1) / 2;
     q.Q = (q.R - 1) * (q.R - 2) / 2;
+    q.pf.m = q.n;
+    q.pf.B = q.Q;
     q.nq = sp.nq; q.e0 = sp.e0;
     q.M = sp.nq > 0 ? impurity_count(sp) : 0;
     q.nnz = nnz_count(sp, &q.nnz_up);
@@ -603,6 +638,36 @@ static hipError_t upload_jobs(JobTable& t) {
     if (e == hipSuccess) t.xm.map = t.dmap;
   }
   return e;
+}
+
+// Trailing updates of a Pfaffian batch: super-panel t reads the compact
+// trailing matrix from buffer t % 2 and its GEMM writes the next one, read
+// through the super-panel's permutation, into the other buffer:
+//   A' = A[perm, perm] + [U V] [V -U]^T   (depth 2 k)
+static hipError_t pf_jobs(PfBatch& b) {
+  const int n = b.m;
+  const long long nn = (long long)n * n;
+  for (size_t t = 0; t < b.sm.size(); ++t) {
+    const int m = b.sm[t], k = b.sk[t];
+    const int mp = m - 2 * k, K = 2 * k;
+    JobTable& jt = b.jt[t];
+    jt.host.clear(); jt.ntiles = 0; jt.cplx = true;
+    double* cin = (t & 1) ? b.A1 : b.A0;
+    double* cout = (t & 1) ? b.A0 : b.A1;
+    if (mp > 0)
+      for (int qq = 0; qq < b.B; ++qq) {
+        // the last panel stores [U V] and [V -U] transposed (K x mp)
+        GemmJob j = job(b.UV + qq * b.uvstride, mp, 1, b.RM + qq * b.uvstride, mp, 0, cin + qq * 2 * nn, n,
+                        cout + qq * 2 * nn, n, mp, mp, K, 1.0, 1.0);
+        j.a_im = b.uv_im; j.b_im = b.uv_im; j.c_im = nn; j.d_im = nn;
+        j.cperm = b.perm + (long long)qq * n + 2 * k;
+        j.mirror = -1;  // the trailing matrix stays skew
+        add_job(jt, j);
+      }
+    hipError_t e = upload_jobs(jt);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Job tables of the exponential-map update (buffers: P -> nsX0, K -> nsQ,
@@ -779,29 +844,7 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
                        1.0, 1.0));
   }
   HIPCHK(upload_jobs(q.jt1)); HIPCHK(upload_jobs(q.jxr));
-  // Pfaffian super-panels: super-panel t reads the compact trailing matrix
-  // from buffer t % 2 and its GEMM writes the next one, read through the
-  // super-panel's permutation, into the other buffer:
-  //   A' = A[perm, perm] + [U V] [V -U]^T   (depth 2 k)
-  for (size_t t = 0; t < q.ps_m.size(); ++t) {
-    const int m = q.ps_m[t], k = q.ps_k[t];
-    const int mp = m - 2 * k, K = 2 * k;
-    JobTable& jt = q.jpf[t];
-    jt.host.clear(); jt.ntiles = 0; jt.cplx = true;
-    double* cin = (t & 1) ? q.Cm2 : q.Cm;
-    double* cout = (t & 1) ? q.Cm : q.Cm2;
-    if (mp > 0)
-      for (int qq = 0; qq < q.Q; ++qq) {
-        // the last panel stores [U V] and [V -U] transposed (K x mp)
-        GemmJob j = job(q.UV + qq * q.uvstride, mp, 1, q.RM + qq * q.uvstride, mp, 0, cin + qq * 2 * nn, n,
-                        cout + qq * 2 * nn, n, mp, mp, K, 1.0, 1.0);
-        j.a_im = q.uv_im; j.b_im = q.uv_im; j.c_im = nn; j.d_im = nn;
-        j.cperm = q.pfperm + (long long)qq * n + 2 * k;
-        j.mirror = -1;  // the trailing matrix stays skew
-        add_job(jt, j);
-      }
-    HIPCHK(upload_jobs(jt));
-  }
+  HIPCHK(pf_jobs(q.pf));
   // Newton-Schulz: Q = X X ; X' = 0.5 X Q + 1.5 X (ping-pong)
   for (int par = 0; par < 2; ++par) {
     double* Xin = par ? q.nsX1 : q.nsX0;
@@ -867,6 +910,22 @@ static hipError_t run_gemm(const JobTable& t, hipStream_t s) {
     if (_e != hipSuccess) return _e;          \
   } while (0)
 
+// All B Pfaffians of a batch: {ln|Pf|, cos arg, sin arg} per matrix into acc;
+// a vanishing pivot sets ST_SINGULAR in *status (ln|Pf| is then not finite).
+static hipError_t pf_run(const PfBatch& b, double* acc, int* status, hipStream_t s) {
+  const long long nn = (long long)b.m * b.m;
+  for (size_t i = 0; i < b.pan.size(); ++i) {
+    const PfBatch::Panel& pp = b.pan[i];
+    const int sp = pp.sp, k = b.sk[sp];
+    const bool last = pp.kd + pp.ns == k;
+    const double* cin = (sp & 1) ? b.A1 : b.A0;
+    HCHK(launch_pf_panel(cin, 2 * nn, nn, b.m, b.sm[sp], pp.p0, pp.ns, pp.kd, k, pp.kd == 0, last, b.B, b.PD,
+                         b.pdstride, b.UV, b.RM, b.uvstride, b.uv_im, b.perm, b.m, acc, i == 0, status, s));
+    if (last) HCHK(run_gemm(b.jt[sp], s));
+  }
+  return hipSuccess;
+}
+
 static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o_la, double* o_arg, double* o_eps) {
   Worker& wk = c->wk[q.worker];
   hipStream_t s = wk.s;
@@ -928,19 +987,10 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
       tm.begin(SGS_STAGE_PHASE, s2);
       HCHK(run_gemm(q.jt1, s2));
       HCHK(run_gemm(q.jxr, s2));
-      HCHK(launch_build_c(n, q.gam, q.T1, q.Xr, q.qa, q.qb, q.Q, q.Cm, s2));
+      HCHK(launch_build_c(n, q.gam, q.T1, q.Xr, q.qa, q.qb, q.Q, q.pf.A0, s2));
       tm.end(SGS_STAGE_PHASE, s2);
       tm.begin(SGS_STAGE_PFAFFIAN, s2);
-      for (size_t i = 0; i < q.pf_pan.size(); ++i) {
-        const Prob::PfPanel& pp = q.pf_pan[i];
-        const int sp = pp.sp, k = q.ps_k[sp];
-        const bool last = pp.kd + pp.ns == k;
-        const double* cin = (sp & 1) ? q.Cm2 : q.Cm;
-        HCHK(launch_pf_panel(cin, 2 * nn, nn, n, q.ps_m[sp], pp.p0, pp.ns, pp.kd, k, pp.kd == 0, last, q.Q, q.PD,
-                             q.pdstride, q.UV, q.RM, q.uvstride, q.uv_im, q.pfperm, n, q.pfacc, i == 0, c->status,
-                             s2));
-        if (last) HCHK(run_gemm(q.jpf[sp], s2));
-      }
+      HCHK(pf_run(q.pf, q.pfacc, c->status, s2));
       tm.end(SGS_STAGE_PFAFFIAN, s2);
       HCHK(hipEventRecord(wk.ev_join, s2));
     }
@@ -1144,7 +1194,7 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
   int nmax = 2;
   for (auto& q : c->pr) nmax = std::max(nmax, q.n);
   if (set_gj_lds_limit(lds_gj) != hipSuccess || set_solve_lds_limit(lds_solve) != hipSuccess ||
-      set_renyi2_lds_limit() != hipSuccess || set_pf_sign_lds_limit(nmax) != hipSuccess ||
+      set_ren_lds_limit() != hipSuccess || set_pf_sign_lds_limit(nmax) != hipSuccess ||
       set_force_lds_limit() != hipSuccess) {
     delete c;
     return SGS_EHIP;
@@ -1344,6 +1394,169 @@ static hipError_t ensure_tables(sgs_ctx* c, int p) {
   return e;
 }
 
+// ---------------------------------------------------------------------------
+// Renyi-2 entropy (App. B)
+// ---------------------------------------------------------------------------
+constexpr double REN_KAPPA_MAX = 1e6;  // split form only with a block better conditioned than this
+constexpr size_t REN_BATCH_BYTES = (size_t)1 << 30;  // device memory of one Pfaffian batch, about
+constexpr int REN_BATCH_MAX = 512;  // matrices per batch
+
+// bytes of a Pfaffian batch of B matrices of order m with its job tables and
+// results (3 doubles per matrix)
+static size_t ren_batch_bytes(int m, int B) {
+  Arena probe{nullptr, 0};
+  PfBatch b;
+  b.m = m; b.B = B; b.super = pf_super_default(m);
+  pf_carve(b, probe);
+  pf_schedule(b, probe);
+  probe.take<double>(3 * (size_t)B);
+  return probe.off + 256;
+}
+
+static int ren_batch_size(int m, int want) {
+  const size_t one = ren_batch_bytes(m, 1);
+  const long long fit = (long long)(REN_BATCH_BYTES / one);
+  return (int)std::max(1LL, std::min<long long>(fit, std::min(REN_BATCH_MAX, std::max(1, want))));
+}
+
+static void ren_batch_carve(PfBatch& b, int m, int B, double** acc, Arena& ar) {
+  b.m = m; b.B = B; b.super = pf_super_default(m);
+  pf_carve(b, ar);
+  pf_schedule(b, ar);
+  *acc = ar.take<double>(3 * (size_t)B);
+}
+
+// S_2 of problem q into out (device).  One representative (p, q) per orbit of
+// the exchange and conjugation symmetries, p <= q over ordered pairs
+// p = a R + b and orbit size w = (p == q ? 1 : 2) ((p*, q*) == (p, q) ? 1 : 2).
+// Waits for the stream before returning.
+static int renyi2(sgs_ctx* c, Prob& q, int nA, int method, double* out) {
+  const int R = q.R, RR = R * R, nu = R * (R + 1) / 2;
+  const hipStream_t st = c->s;
+  ObsState s{q.n, R, q.gam, q.W, q.Di, q.lam, q.Gt, q.pidx};
+  std::vector<RenTerm> reps;
+  auto conj_pair = [R](int p) { return (p % R) * R + p / R; };
+  for (int p = 0; p < RR; ++p)
+    for (int r = p; r < RR; ++r) {
+      int cp = conj_pair(p), cr = conj_pair(r);
+      if (cp > cr) std::swap(cp, cr);
+      if (cp < p || (cp == p && cr < r)) continue;  // (p*, r*) represents this orbit
+      const int w = (p == r ? 1 : 2) * (cp == p && cr == r ? 1 : 2);
+      reps.push_back({p, r, 0, w});
+    }
+  const int nterm = (int)reps.size();
+  const bool lds = method == SGS_REN_AUTO && nA <= REN_LDS_MAX_NA;
+  const bool split = !lds && method != SGS_REN_BLOCK;
+  const long long mm = (long long)nA * nA;
+  const int B1 = split ? ren_batch_size(nA, std::max(nu, nterm)) : 0;
+  const int B2 = lds ? 0 : ren_batch_size(2 * nA, nterm);
+  // device memory: status, terms, term values, classes, inverses, condition
+  // numbers, the classes' Pfaffians, then the two batches
+  auto layout = [&](Arena& ar, int** status, RenTerm** dterms, double** tval, int2** uxy, double** inv,
+                    double** kappa, double** uacc, PfBatch* b1, double** acc1, PfBatch* b2, double** acc2) {
+    *status = ar.take<int>(64);
+    *dterms = ar.take<RenTerm>(nterm);
+    *tval = ar.take<double>(nterm);
+    *uxy = ar.take<int2>(nu);
+    *inv = split ? ar.take<double>((size_t)nu * 2 * mm) : nullptr;
+    *kappa = ar.take<double>(nu);
+    *uacc = ar.take<double>(3 * (size_t)nu);
+    if (B1) ren_batch_carve(*b1, nA, B1, acc1, ar);
+    if (B2) ren_batch_carve(*b2, 2 * nA, B2, acc2, ar);
+  };
+  int* status; RenTerm* dterms; double *tval, *inv, *kappa, *uacc, *acc1 = nullptr, *acc2 = nullptr;
+  int2* uxy;
+  PfBatch b1, b2;
+  {
+    Arena probe{nullptr, 0};
+    layout(probe, &status, &dterms, &tval, &uxy, &inv, &kappa, &uacc, &b1, &acc1, &b2, &acc2);
+    const size_t need = probe.off + 256;
+    // the previous call's kernels may still read the job tables
+    if (hipStreamSynchronize(st) != hipSuccess) return SGS_EHIP;
+    if (c->ren_bytes < need) {
+      if (c->ren) (void)hipFree(c->ren);
+      c->ren = nullptr;
+      c->ren_bytes = 0;
+      if (hipMalloc(&c->ren, need) != hipSuccess) return SGS_EHIP;
+      c->ren_bytes = need;
+    }
+    Arena ar{(char*)c->ren, 0};
+    layout(ar, &status, &dterms, &tval, &uxy, &inv, &kappa, &uacc, &b1, &acc1, &b2, &acc2);
+  }
+  if (lds) {
+    if (hipMemcpy(dterms, reps.data(), reps.size() * sizeof(RenTerm), hipMemcpyHostToDevice) != hipSuccess ||
+        launch_ren_lds(s, nA, dterms, nterm, tval, st) != hipSuccess ||
+        launch_ren_sum(tval, nterm, out, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+      return SGS_EHIP;
+    return SGS_OK;
+  }
+  // classes: Pf(K_u), K_u^{-1} and its condition number
+  std::vector<double> kap(nu, __builtin_huge_val());
+  if (split) {
+    std::vector<int2> cls;
+    for (int x = 0; x < R; ++x)
+      for (int y = x; y < R; ++y) cls.push_back(make_int2(x, y));
+    if (hipMemcpy(uxy, cls.data(), cls.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess ||
+        pf_jobs(b1) != hipSuccess)
+      return SGS_EHIP;
+    for (int u0 = 0; u0 < nu; u0 += B1) {
+      const int nb = std::min(B1, nu - u0);
+      if (launch_ren_blocks(s, nA, uxy, u0, B1, nu, b1.A0, inv, st) != hipSuccess ||
+          pf_run(b1, acc1, status, st) != hipSuccess ||
+          hipMemcpyAsync(uacc + 3 * (size_t)u0, acc1, 3 * (size_t)nb * sizeof(double), hipMemcpyDeviceToDevice,
+                         st) != hipSuccess)
+        return SGS_EHIP;
+    }
+    if (launch_ren_inverse(inv, nu, nA, kappa, st) != hipSuccess ||
+        hipMemcpyAsync(kap.data(), kappa, nu * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return SGS_EHIP;
+  }
+  // split terms first (block q inverted), then block-form terms
+  const double kmax = method == SGS_REN_SPLIT ? __builtin_huge_val() : REN_KAPPA_MAX;
+  auto cls_of = [R](int p) {
+    int x = p / R, y = p % R;
+    if (x > y) std::swap(x, y);
+    return x * (2 * R - x + 1) / 2 + (y - x);
+  };
+  std::vector<RenTerm> order;
+  order.reserve(nterm);
+  for (RenTerm t : reps) {
+    const double kp = kap[cls_of(t.p)], kq = kap[cls_of(t.q)];
+    if (split && std::min(kp, kq) < kmax) {
+      if (kp < kq) std::swap(t.p, t.q);  // invert the better-conditioned block
+      t.split = 1;
+      order.push_back(t);
+    }
+  }
+  const int nsplit = (int)order.size();
+  for (const RenTerm& t : reps) {
+    const double kp = kap[cls_of(t.p)], kq = kap[cls_of(t.q)];
+    if (!(split && std::min(kp, kq) < kmax)) order.push_back(t);
+  }
+  if (hipMemcpy(dterms, order.data(), order.size() * sizeof(RenTerm), hipMemcpyHostToDevice) != hipSuccess)
+    return SGS_EHIP;
+  for (int t0 = 0; t0 < nsplit; t0 += B1) {
+    const int cnt = std::min(B1, nsplit - t0);
+    if (launch_ren_terms(s, nA, 1, dterms, t0, cnt, B1, inv, b1.A0, st) != hipSuccess ||
+        pf_run(b1, acc1, status, st) != hipSuccess ||
+        launch_ren_combine(s, nA, 1, dterms, t0, cnt, acc1, uacc, tval, st) != hipSuccess)
+      return SGS_EHIP;
+  }
+  if (nsplit < nterm) {
+    if (pf_jobs(b2) != hipSuccess) return SGS_EHIP;
+    for (int t0 = nsplit; t0 < nterm; t0 += B2) {
+      const int cnt = std::min(B2, nterm - t0);
+      if (launch_ren_terms(s, nA, 0, dterms, t0, cnt, B2, nullptr, b2.A0, st) != hipSuccess ||
+          pf_run(b2, acc2, status, st) != hipSuccess ||
+          launch_ren_combine(s, nA, 0, dterms, t0, cnt, acc2, uacc, tval, st) != hipSuccess)
+        return SGS_EHIP;
+    }
+  }
+  if (launch_ren_sum(tval, nterm, out, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return SGS_EHIP;
+  return SGS_OK;
+}
+
 int sgs_observables(sgs_ctx* c, int32_t kind, const int32_t* iargs, int32_t niargs, const double* dargs,
                     int32_t ndargs, double* out) {
   if (!c || !iargs || niargs < 1 || !out) return SGS_EINVAL;
@@ -1403,13 +1616,12 @@ int sgs_observables(sgs_ctx* c, int32_t kind, const int32_t* iargs, int32_t niar
     return SGS_OK;
   }
   if (kind == SGS_OBS_RENYI2) {
-    if (niargs != 2) return SGS_EINVAL;
-    const int nA = iargs[1];
-    if (nA < 2 || nA > OBS_MAX_NA || (nA & 1) || nA > n) return SGS_EINVAL;
+    if (niargs != 2 && niargs != 3) return SGS_EINVAL;
+    const int nA = iargs[1], method = niargs == 3 ? iargs[2] : SGS_REN_AUTO;
+    if (nA < 2 || nA > REN_MAX_NA || (nA & 1) || nA > n) return SGS_EINVAL;
+    if (method < SGS_REN_AUTO || method > SGS_REN_SPLIT) return SGS_EINVAL;
     if (ensure_tables(c, p) != hipSuccess) return SGS_EHIP;
-    ObsState s{n, q.R, q.gam, q.W, q.Di, q.lam, q.Gt, q.pidx};
-    if (launch_renyi2(s, nA, c->obs.part, out, c->s) != hipSuccess) return SGS_EHIP;
-    return SGS_OK;
+    return renyi2(c, q, nA, method, out);
   }
   return SGS_EINVAL;
 }

@@ -28,32 +28,9 @@
 //
 // Storage: the pair p = (a < b) keeps W = (Gamma_a + Gamma_b)^{-1} and
 // Im Delta^{ba}; Delta^{ba} = -2 W + i Im, Delta^{ab} = its conjugate.
-#include "sgs_internal.h"
+#include "obs_common.h"
 
 namespace sgs {
-
-struct cd {
-  double r, i;
-};
-__device__ __forceinline__ cd cmul(cd a, cd b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
-__device__ __forceinline__ cd cconj(cd a) { return {a.r, -a.i}; }
-
-// Delta^{xy}_{kl} of problem tables (x, y states; x == y gives Gamma_x)
-__device__ __forceinline__ cd delta_at(const ObsState& s, int x, int y, int k, int l) {
-  const long long nn = (long long)s.n * s.n;
-  const long long o = (long long)k * s.n + l;
-  if (x == y) return {s.gam[(long long)x * nn + o], 0.0};
-  const int p = s.pidx[x * s.R + y];
-  const double re = -2.0 * s.W[(long long)p * nn + o];
-  const double im = s.Di[(long long)p * nn + o];
-  // pair (min, max) stores Delta^{max,min}
-  return x > y ? cd{re, im} : cd{re, -im};
-}
-
-__device__ __forceinline__ cd lam_at(const ObsState& s, int i) { return {s.lam[2 * i], s.lam[2 * i + 1]}; }
-__device__ __forceinline__ cd g_at(const ObsState& s, int i, int j) {
-  return {s.Gt[2 * (i * s.R + j)], s.Gt[2 * (i * s.R + j) + 1]};
-}
 
 // block-wide complex sum in a fixed order (deterministic); red holds blockDim.x
 // entries, blockDim.x a power of two
@@ -105,116 +82,6 @@ __global__ __launch_bounds__(256) void k_obs_poly(ObsState s, const int* __restr
   }
   const cd tot = block_sum(acc, red);
   if (threadIdx.x == 0) { out[2 * t] = tot.r; out[2 * t + 1] = tot.i; }
-}
-
-// grid: R*R blocks (pair (a, b)), one wave each; every block sums over (g, d)
-// the terms of Tr rho_A^2 and writes its complex partial sum to part[a*R+b].
-// dynamic LDS: two m x (m + 1) planes, m = 2 nA <= 64
-__global__ __launch_bounds__(64) void k_renyi2(ObsState s, int nA, double* __restrict__ part) {
-  extern __shared__ double zs[];
-  const int m = 2 * nA, ld = m + 1;
-  double* Zr = zs;
-  double* Zi = zs + m * ld;
-  const int R = s.R;
-  const int a = blockIdx.x / R, b = blockIdx.x % R;
-  const int lane = threadIdx.x;
-  const double ln2 = 0.69314718055994530942;
-  double sr = 0.0, si = 0.0;  // meaningful in lane 0
-  for (int gd = 0; gd < R * R; ++gd) {
-    const int g = gd / R, d = gd % R;
-    // Z = [[D_ab, i 1], [-i 1, D_gd]]
-    for (int e = lane; e < m * m; e += 64) {
-      const int i = e / m, j = e % m;
-      cd v{0.0, 0.0};
-      if (i < nA && j < nA) v = delta_at(s, a, b, i, j);
-      else if (i >= nA && j >= nA) v = delta_at(s, g, d, i - nA, j - nA);
-      else if (i < nA && j == i + nA) v = {0.0, 1.0};
-      else if (i >= nA && i == j + nA) v = {0.0, -1.0};
-      Zr[i * ld + j] = v.r;
-      Zi[i * ld + j] = v.i;
-    }
-    __syncthreads();
-    // Pfaffian by elimination with 2 x 2 pivots and symmetric row/column
-    // exchanges (each exchange flips the sign): ln|Pf| and the unit phase
-    double la = 0.0, pr = 1.0, pi = 0.0;
-    bool zero = false;
-    for (int k = 0; k < m && !zero; k += 2) {
-      // pivot: largest |Z[i][k]|, i > k (lane i)
-      double best = -1.0;
-      int bi = k + 1;
-      if (lane > k && lane < m) {
-        const double xr = Zr[lane * ld + k], xi = Zi[lane * ld + k];
-        best = xr * xr + xi * xi;
-        bi = lane;
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o);
-        const int oi = __shfl_xor(bi, o);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      const int q = bi;
-      if (q != k + 1) {
-        if (lane < m) {
-          double t = Zr[q * ld + lane]; Zr[q * ld + lane] = Zr[(k + 1) * ld + lane]; Zr[(k + 1) * ld + lane] = t;
-          t = Zi[q * ld + lane]; Zi[q * ld + lane] = Zi[(k + 1) * ld + lane]; Zi[(k + 1) * ld + lane] = t;
-        }
-        __syncthreads();
-        if (lane < m) {
-          double t = Zr[lane * ld + q]; Zr[lane * ld + q] = Zr[lane * ld + k + 1]; Zr[lane * ld + k + 1] = t;
-          t = Zi[lane * ld + q]; Zi[lane * ld + q] = Zi[lane * ld + k + 1]; Zi[lane * ld + k + 1] = t;
-        }
-        __syncthreads();
-        pr = -pr;
-        pi = -pi;
-      }
-      const double ar = Zr[k * ld + k + 1], ai = Zi[k * ld + k + 1];
-      const double a2 = ar * ar + ai * ai;
-      if (!(a2 > 0.0)) { zero = true; break; }
-      la += 0.5 * log(a2);
-      {
-        const double nr = pr * ar - pi * ai, ni = pr * ai + pi * ar;
-        const double nm = 1.0 / sqrt(nr * nr + ni * ni);
-        pr = nr * nm;
-        pi = ni * nm;
-      }
-      // trailing update Z[i][j] += (Z[k+1][i] Z[k][j] - Z[k][i] Z[k+1][j]) / a, lane = column j
-      const double ir = ar / a2, ii = -ai / a2;
-      if (lane >= k + 2 && lane < m) {
-        const int j = lane;
-        const cd b0j{Zr[k * ld + j], Zi[k * ld + j]}, b1j{Zr[(k + 1) * ld + j], Zi[(k + 1) * ld + j]};
-        for (int i = k + 2; i < m; ++i) {
-          const cd b0i{Zr[k * ld + i], Zi[k * ld + i]}, b1i{Zr[(k + 1) * ld + i], Zi[(k + 1) * ld + i]};
-          const cd x = cmul(b1i, b0j), y = cmul(b0i, b1j);
-          const cd u = cmul(cd{x.r - y.r, x.i - y.i}, cd{ir, ii});
-          Zr[i * ld + j] += u.r;
-          Zi[i * ld + j] += u.i;
-        }
-      }
-      __syncthreads();
-    }
-    if (lane == 0 && !zero) {
-      // coefficient lambda_a lambda_b^* lambda_g lambda_d^* G_ba G_dg, in log form
-      const cd c = cmul(cmul(cmul(lam_at(s, a), cconj(lam_at(s, b))), cmul(lam_at(s, g), cconj(lam_at(s, d)))),
-                        cmul(g_at(s, b, a), g_at(s, d, g)));
-      const double cm = sqrt(c.r * c.r + c.i * c.i);
-      if (cm > 0.0) {
-        const double mag = exp(log(cm) + la - 0.25 * m * ln2);  // 2^{-N_A}, N_A = m / 4
-        const cd ph = cmul(cd{c.r / cm, c.i / cm}, cd{pr, pi});
-        sr += mag * ph.r;
-        si += mag * ph.i;
-      }
-    }
-    __syncthreads();
-  }
-  if (lane == 0) { part[2 * blockIdx.x] = sr; part[2 * blockIdx.x + 1] = si; }
-}
-
-// one thread: S_2 = -ln Re(sum of the partial sums), fixed order
-__global__ void k_renyi2_final(const double* __restrict__ part, int count, double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double s = 0.0;
-  for (int t = 0; t < count; ++t) s += part[2 * t];
-  out[0] = -log(s);
 }
 
 // ---- variance of H ----
@@ -472,23 +339,6 @@ hipError_t launch_variance(const ObsState& s, const VarHam& h, double e0, double
 hipError_t launch_obs_poly(const ObsState& s, const int* rows, const double* coef, const int* off, int npoly,
                            double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_obs_poly, dim3(npoly), dim3(256), 0, st, s, rows, coef, off, out);
-  return hipGetLastError();
-}
-
-size_t renyi2_lds_bytes(int nA) {
-  const size_t m = 2 * (size_t)nA;
-  return 2 * m * (m + 1) * sizeof(double);
-}
-
-hipError_t set_renyi2_lds_limit() {
-  return hipFuncSetAttribute((const void*)k_renyi2, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)renyi2_lds_bytes(OBS_MAX_NA));
-}
-
-hipError_t launch_renyi2(const ObsState& s, int nA, double* part, double* out, hipStream_t st) {
-  if (nA < 2 || nA > OBS_MAX_NA || (nA & 1)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_renyi2, dim3(s.R * s.R), dim3(64), renyi2_lds_bytes(nA), st, s, nA, part);
-  hipLaunchKernelGGL(k_renyi2_final, dim3(1), dim3(64), 0, st, part, s.R * s.R, out);
   return hipGetLastError();
 }
 

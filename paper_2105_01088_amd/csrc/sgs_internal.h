@@ -252,14 +252,29 @@ constexpr int VAR_CHUNKS = 16;  // workgroups per transition block
 // a2 = |A|_F^2
 hipError_t launch_variance(const ObsState& s, const VarHam& h, double e0, double a2, double* part, double* out,
                            hipStream_t st);
-constexpr int OBS_MAX_NA = 32;      // Renyi-2 subsystem: at most 32 Majoranas
 constexpr int OBS_MAX_TERMS = 16384;
 constexpr int OBS_MAX_POLY = 4096;
 hipError_t launch_obs_poly(const ObsState& s, const int* rows, const double* coef, const int* off, int npoly,
                            double* out, hipStream_t st);
-size_t renyi2_lds_bytes(int nA);
-hipError_t set_renyi2_lds_limit();
-hipError_t launch_renyi2(const ObsState& s, int nA, double* part, double* out, hipStream_t st);
+// Renyi-2 (renyi.hip): one representative term of the rank-4 tensor, the
+// ordered pairs p = a R + b, q = g R + d and the orbit size w; the split form
+// inverts block q
+struct RenTerm {
+  int p, q, split, w;
+};
+constexpr int REN_LDS_MAX_NA = 32;  // block form in LDS (order 2 nA <= 64)
+constexpr int REN_MAX_NA = 1024;    // batched path (block form of order <= 2048)
+size_t ren_lds_bytes(int nA);
+hipError_t set_ren_lds_limit();
+hipError_t launch_ren_lds(const ObsState& s, int nA, const RenTerm* terms, int nterm, double* tval, hipStream_t st);
+hipError_t launch_ren_blocks(const ObsState& s, int nA, const int2* uxy, int u0, int nb, int nu, double* dst,
+                             double* inv, hipStream_t st);
+hipError_t launch_ren_inverse(double* K, int nu, int m, double* kappa, hipStream_t st);
+hipError_t launch_ren_terms(const ObsState& s, int nA, int split, const RenTerm* terms, int t0, int count, int nb,
+                            const double* inv, double* dst, hipStream_t st);
+hipError_t launch_ren_combine(const ObsState& s, int nA, int split, const RenTerm* terms, int t0, int count,
+                              const double* acc, const double* uacc, double* tval, hipStream_t st);
+hipError_t launch_ren_sum(const double* tval, int nterm, double* out, hipStream_t st);
 
 enum : int { FORCE_FP64 = 0, FORCE_FP32 = 1 };
 // k_force: the dense products, nsplit workgroups per output tile, each

@@ -118,7 +118,7 @@ def test_observables_reject_bad_arguments():
     with pytest.raises(SGSError):
         ctx.observables(SGS_OBS_RENYI2, [0, 3], [], 1)       # odd nA
     with pytest.raises(SGSError):
-        ctx.observables(SGS_OBS_RENYI2, [0, 34], [], 1)      # beyond the limit
+        ctx.observables(SGS_OBS_RENYI2, [0, 34], [], 1)      # larger than the system
     with pytest.raises(SGSError):
         ctx.observables(SGS_OBS_POLY, [0, 1, 1, 0, 2, 3, 1, -1, -1], [1.0, 0.0], 2)  # unsorted word
     with pytest.raises(SGSError):

@@ -565,3 +565,45 @@ def test_wilson_tail_hoppings_enter_the_chain():
         if len(ops) == 2 and ops[0][1] and not ops[1][1] and ops[0][0] != ops[1][0]:
             hops[(ops[0][0], ops[1][0])] = c
     assert abs(hops[(si.siam_mode(22, 0), si.siam_mode(23, 0))] + 1.2 ** -20) < 1e-15
+
+
+def test_renyi2_tensor_symmetries_and_split_form():
+    """The terms of Eq. (S2_SGS) satisfy T(p, q) = T(q, p) and
+    T(p*, q*) = T(p, q)^* with (a, b)* = (b, a), and the block Pfaffian of
+    Eq. (pfMA) equals the split product Pf(K_q) Pf(K_p - K_q^{-1}) of
+    Eq. (TrArho2_final) with either block inverted (App. B); summing w Re T
+    over one representative per orbit reproduces S_2."""
+    from oracle import gaussian as ga
+    from oracle.pfaffian import pfaffian_log
+    ham = si.anderson(5, 1.0, 0.5)
+    R, nA = 3, 8
+    g = si.random_states(ham.N, R, seed=3)
+    E, lam, tab = sgs.energy(ham, g)
+    K = {(a, b): (g[a] if a == b else ga.delta(g[a], g[b]))[:nA, :nA] for a in range(R) for b in range(R)}
+    one = np.eye(nA)
+
+    def pf(m):
+        la, ph = pfaffian_log(m)
+        return ph * math.exp(la)
+
+    def term(a, b, c, d):
+        coef = lam[a] * np.conj(lam[b]) * lam[c] * np.conj(lam[d]) * tab.G[b, a] * tab.G[d, c]
+        return coef * pf(np.block([[K[a, b], 1j * one], [-1j * one, K[c, d]]])) / 2 ** (nA // 2)
+
+    total = 0.0
+    for p in range(R * R):
+        for q in range(R * R):
+            a, b = divmod(p, R)
+            c, d = divmod(q, R)
+            t = term(a, b, c, d)
+            assert abs(t - term(c, d, a, b)) < 1e-12 * max(1.0, abs(t))
+            assert abs(t - np.conj(term(b, a, d, c))) < 1e-12 * max(1.0, abs(t))
+            z = pf(np.block([[K[a, b], 1j * one], [-1j * one, K[c, d]]]))
+            for x, y in (((a, b), (c, d)), ((c, d), (a, b))):
+                split = pf(K[y]) * pf(K[x] - np.linalg.inv(K[y]))
+                assert abs(split - z) < 1e-10 * max(1.0, abs(z))
+            # one representative per orbit, with the orbit's size
+            cp, cq = sorted(((b * R + a), (d * R + c)))
+            if p <= q and (cp, cq) >= (p, q):
+                total += (1 if p == q else 2) * (1 if (cp, cq) == (p, q) else 2) * t.real
+    assert -math.log(total) == pytest.approx(ob.renyi2(g, lam, tab.G, nA), abs=1e-12)
