@@ -147,11 +147,38 @@ def quartic_tensor(ham) -> Tuple[np.ndarray, np.ndarray]:
     return imp, U
 
 
+def word_fock(d: np.ndarray, word, coef: complex) -> np.ndarray:
+    """Transition Fock matrix of one word term coef * c_w0 ... c_w(m-1) (m even).
+
+    F = A + 6 U Delta (Sec. II.C) is minus the derivative of the transition
+    value <H>_t = e0 - sum_kl A_kl Delta_kl - sum_q u_q Pf(Delta[q]) with
+    respect to the entries Delta_kl, k < l, halved (each enters twice in the
+    quadratic part).  Read that way it extends to a word of any length, whose
+    value is i^(m/2) Pf(Delta[w]) (Wick's theorem, Sec. III.B): for positions
+    a < b of the word, with the Pfaffian cofactor of entry (a, b),
+      F[w_a, w_b] = -(1/2) coef i^(m/2) (-1)^(a+b+1) Pf(Delta[w without a, b]),
+    and F[w_b, w_a] = -F[w_a, w_b].  For quartic words this is 6 U Delta."""
+    idx = list(word)
+    m = len(idx)
+    out = np.zeros(d.shape, dtype=complex)
+    for a in range(m):
+        for b in range(a + 1, m):
+            rest = [idx[t] for t in range(m) if t != a and t != b]
+            pf = pfaffian(d[np.ix_(rest, rest)].astype(complex)) if rest else 1.0
+            v = -0.5 * coef * (1j ** (m // 2)) * (-1) ** (a + b + 1) * pf
+            out[idx[a], idx[b]] += v
+            out[idx[b], idx[a]] -= v
+    return out
+
+
 def fock_matrix(ham, d: np.ndarray, qt=None) -> np.ndarray:
-    """F = A + 6 sum_mn U_klmn Delta_mn (complex in general)."""
+    """F = A + 6 sum_mn U_klmn Delta_mn (complex in general), plus the
+    contribution of every word of 6 or 8 Majoranas (word_fock)."""
     imp, U = quartic_tensor(ham) if qt is None else qt
     F = ham.A.astype(complex)
     if len(imp):
         blk = d[np.ix_(imp, imp)]
         F[np.ix_(imp, imp)] += 6.0 * np.einsum("klmn,mn->kl", U, blk)
+    for w, v in zip(getattr(ham, "higher_idx", ()), getattr(ham, "higher_val", ())):
+        F += word_fock(d, w, v * ham.word_phase(len(w)))
     return F

@@ -14,6 +14,8 @@ from .models import (  # noqa: F401
     fermion_terms_to_majorana,
     anderson_terms,
     anderson,
+    anderson_multibody_terms,
+    anderson_multibody,
     two_channel_kondo_terms,
     two_channel_kondo,
     spin_dot_terms,

@@ -108,7 +108,13 @@ def fermion_terms_to_majorana(terms: Iterable[FermionTerm]) -> MajoranaPoly:
 
 @dataclass
 class MajoranaHamiltonian:
-    """H = e0 + i sum A_kl c_k c_l + sum_q u_q c_{q0} c_{q1} c_{q2} c_{q3}."""
+    """H = e0 + i sum A_kl c_k c_l + sum_q u_q c_{q0} c_{q1} c_{q2} c_{q3}
+    + sum_w h_w c_{w0} ... c_{w(m-1)} over words of m = 6 or 8 Majoranas.
+
+    A Hermitian word term has h_w = v_w i^((m/2) mod 2) with v_w real (the
+    reversed word is (-1)^(m(m-1)/2) times the word): imaginary for m = 6,
+    real for m = 8.  ``higher_val`` holds v_w.
+    """
 
     N: int
     A: np.ndarray  # (2N, 2N) real skew, float64
@@ -116,6 +122,13 @@ class MajoranaHamiltonian:
     quartic_val: np.ndarray  # (nq,) float64
     e0: float
     meta: Dict[str, object] = field(default_factory=dict)
+    higher_idx: Tuple[Tuple[int, ...], ...] = ()  # words of 6 or 8 indices, strictly increasing
+    higher_val: np.ndarray = field(default_factory=lambda: np.zeros(0))  # (nw,) float64, v_w
+
+    @staticmethod
+    def word_phase(m: int) -> complex:
+        """h_w / v_w for a Hermitian word term of m Majoranas."""
+        return 1j if (m // 2) % 2 else 1.0
 
     @property
     def n(self) -> int:
@@ -127,6 +140,8 @@ class MajoranaHamiltonian:
         A = np.zeros((n, n))
         qi: List[Word] = []
         qv: List[float] = []
+        hi: List[Word] = []
+        hv: List[float] = []
         e0 = 0.0
         for w, c in sorted(poly.items()):
             if len(w) == 0:
@@ -146,6 +161,12 @@ class MajoranaHamiltonian:
                     raise ValueError("non-Hermitian quartic term %r" % (w,))
                 qi.append(w)
                 qv.append(c.real)
+            elif len(w) in (6, 8):
+                v = c / MajoranaHamiltonian.word_phase(len(w))
+                if abs(v.imag) > tol:
+                    raise ValueError("non-Hermitian term %r" % (w,))
+                hi.append(tuple(int(x) for x in w))
+                hv.append(v.real)
             else:
                 raise ValueError("term of degree %d is not supported" % len(w))
         return MajoranaHamiltonian(
@@ -154,6 +175,8 @@ class MajoranaHamiltonian:
             quartic_idx=np.array(qi, dtype=np.int32).reshape(-1, 4),
             quartic_val=np.array(qv, dtype=np.float64),
             e0=float(e0),
+            higher_idx=tuple(hi),
+            higher_val=np.array(hv, dtype=np.float64),
         )
 
     def poly(self) -> MajoranaPoly:
@@ -168,11 +191,14 @@ class MajoranaHamiltonian:
                     p.add((k, l), 2j * self.A[k, l])
         for w, u in zip(self.quartic_idx, self.quartic_val):
             p.add(tuple(int(x) for x in w), complex(u))
+        for w, v in zip(self.higher_idx, self.higher_val):
+            p.add(tuple(w), v * self.word_phase(len(w)))
         return p
 
     def impurity_majoranas(self) -> np.ndarray:
-        """Sorted Majorana indices touched by the quartic terms (the M of Sec. II.A)."""
-        return np.unique(self.quartic_idx.reshape(-1)).astype(np.int32)
+        """Sorted Majorana indices touched by the interaction words (the M of Sec. II.A)."""
+        idx = [int(x) for x in self.quartic_idx.reshape(-1)] + [x for w in self.higher_idx for x in w]
+        return np.unique(np.array(idx, dtype=np.int64)).astype(np.int32)
 
 
 # ---------------------------------------------------------------------------
@@ -221,6 +247,30 @@ def anderson_terms(L: int, U: float, V: float, t: float = 1.0,
             for s in (0, 1):
                 terms += _num(-mu, siam_mode(r, s))
     return N, terms
+
+
+def anderson_multibody_terms(L: int, U: float, V: float, W3: float, W4: float,
+                             t: float = 1.0) -> Tuple[int, List[FermionTerm]]:
+    """The Anderson chain plus density interactions of three and four bodies
+    between the impurity and the first bath site,
+      W3 n_0up n_0dn n_1up + W4 n_0up n_0dn n_1up n_1dn,
+    which give Majorana words of 6 and 8 operators (interaction terms of
+    weight m > 4, Sec. III.C).  A synthetic model: the paper names no such
+    Hamiltonian."""
+    N, terms = anderson_terms(L, U, V, t)
+    n = lambda site, spin: ((siam_mode(site, spin), True), (siam_mode(site, spin), False))
+    if W3 != 0.0:
+        terms.append((W3, n(0, 0) + n(0, 1) + n(1, 0)))
+    if W4 != 0.0:
+        terms.append((W4, n(0, 0) + n(0, 1) + n(1, 0) + n(1, 1)))
+    return N, terms
+
+
+def anderson_multibody(L: int, U: float, V: float, W3: float, W4: float, t: float = 1.0) -> MajoranaHamiltonian:
+    N, terms = anderson_multibody_terms(L, U, V, W3, W4, t)
+    h = MajoranaHamiltonian.from_poly(N, fermion_terms_to_majorana(terms))
+    h.meta = dict(model="anderson_multibody", L=L, U=U, V=V, W3=W3, W4=W4, t=t)
+    return h
 
 
 def wilson_hoppings(L_W: int = 20, Lambda: float = 1.2, t: float = 1.0) -> List[float]:

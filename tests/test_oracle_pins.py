@@ -607,3 +607,52 @@ def test_renyi2_tensor_symmetries_and_split_form():
             if p <= q and (cp, cq) >= (p, q):
                 total += (1 if p == q else 2) * (1 if (cp, cq) == (p, q) else 2) * t.real
     assert -math.log(total) == pytest.approx(ob.renyi2(g, lam, tab.G, nA), abs=1e-12)
+
+
+# ------------------------------------------------- interaction words, m > 4
+
+def test_word_fock_reproduces_quartic_fock():
+    """The cofactor form of the transition Fock matrix, applied to quartic
+    words, is the paper's 6 U Delta (Sec. II.C)."""
+    from oracle import gaussian as ga
+    ham = si.anderson(2, 1.3, 0.6)
+    g = si.random_states(ham.N, 2, seed=5)
+    d = ga.delta(g[0], g[1])
+    ref = ga.fock_matrix(ham, d) - ham.A
+    got = sum(ga.word_fock(d, w, u) for w, u in zip(ham.quartic_idx, ham.quartic_val))
+    assert np.abs(got - ref).max() < 1e-14
+
+
+@pytest.mark.parametrize("mode", ["printed", "unit"])
+@pytest.mark.parametrize("W3,W4", [(0.7, 0.0), (0.0, 0.5), (0.6, -0.4)])
+def test_force_with_higher_words_matches_bruteforce(mode, W3, W4):
+    """Words of 6 and 8 Majoranas (three- and four-body densities): the
+    oracle's compact force (Eq. EOM-Gamma3 with the cofactor Fock matrix)
+    against the Fock-space derivative of Eq. (EOM-Gamma2), and the pair
+    tables against the projected Hamiltonian."""
+    ham = si.anderson_multibody(1, 1.1, 0.6, W3, W4)
+    assert len(ham.higher_idx) > 0
+    g = si.random_states(ham.N, 3, seed=8)
+    tab = sgs.pair_tables(ham, g)
+    vecs = fock.fix_gauge([fock.gaussian_state(x) for x in g], fock.gaussian_state(g[0]))
+    vecs = fock.fix_gauge(vecs, vecs[0])
+    V = np.stack(vecs, 1)
+    H = fock.majorana_poly_operator(ham.N, ham.poly())
+    N, terms = si.anderson_multibody_terms(1, 1.1, 0.6, W3, W4)
+    assert np.abs(H - fock.fermion_operator(N, terms)).max() < 1e-12
+    assert np.abs(tab.h - V.conj().T @ H @ V).max() < 1e-12
+    E, lam = sgs.solve_amplitudes(tab.G, tab.h)
+    dg = sgs.forces(ham, g, tab, E, lam, mode)
+    ref = _bruteforce_force(ham, g, mode)
+    assert np.abs(dg - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_multibody_energy_descends_to_ed():
+    """Imaginary-time steps with 6- and 8-Majorana words stay above the
+    even-sector ground energy and descend (Sec. III.C)."""
+    N, terms = si.anderson_multibody_terms(2, 1.0, 0.5, 0.8, -0.6)
+    ham = si.anderson_multibody(2, 1.0, 0.5, 0.8, -0.6)
+    e_ed = ed.even_sector_ground_energy(N, terms)
+    _, es = sgs.run(ham, si.random_states(N, 3, seed=2), 0.05, 40)
+    assert np.all(es >= e_ed - 1e-12)
+    assert np.all(np.diff(es) <= 1e-12)
