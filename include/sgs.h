@@ -106,6 +106,16 @@ typedef struct {
   const int32_t* q_idx;  /* nq*4 Majorana indices, each row strictly increasing*/
   const double* q_val;   /* nq coefficients u_q                                */
   double e0;             /* constant energy offset                             */
+  /* Interaction words of m = 6 or 8 Majoranas (the weight-m terms of
+   * Sec. III.C); all zero / NULL when there are none.  Word w is the
+   * Hermitian term v_w i^((m/2) mod 2) c_w0 ... c_w(m-1) (i for m = 6, 1 for
+   * m = 8); its transition value is i^(m/2) Pf(Delta[w]) (Sec. III.B) and it
+   * adds Pfaffian cofactors of order m - 2 to the transition Fock matrix. */
+  int32_t nw;            /* number of such words, 0 <= nw <= 256               */
+  const int32_t* w_len;  /* nw lengths, each 6 or 8                            */
+  const int32_t* w_idx;  /* sum of w_len Majorana indices, word after word,    */
+                         /* each word strictly increasing                      */
+  const double* w_val;   /* nw real coefficients v_w                           */
 } sgs_problem;
 
 /* One row of a tuning table (written by the project autotuner,
@@ -260,7 +270,8 @@ int sgs_energy(sgs_ctx* ctx, double* E, double* lambda);
  *                   Wick's theorem on every transition operator: the
  *                   quadratic part in matrix form (O(n^2 nnz(A)/n) per pair
  *                   of states), products with quartic words as Pfaffians of
- *                   6 and 8 Majoranas.  R <= 32.
+ *                   6 and 8 Majoranas.  R <= 32; not available for a
+ *                   problem with words of more than 4 Majoranas (nw > 0).
  * Errors: SGS_EINVAL (kind, sizes, indices), SGS_EHIP. */
 int sgs_observables(sgs_ctx* ctx, int32_t kind, const int32_t* iargs,
                     int32_t niargs, const double* dargs, int32_t ndargs,

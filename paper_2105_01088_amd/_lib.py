@@ -37,7 +37,9 @@ class SGSError(RuntimeError):
 
 class sgs_problem(ctypes.Structure):
     _fields_ = [("N", c_int32), ("R", c_int32), ("A", POINTER(c_double)), ("nq", c_int32),
-                ("q_idx", POINTER(c_int32)), ("q_val", POINTER(c_double)), ("e0", c_double)]
+                ("q_idx", POINTER(c_int32)), ("q_val", POINTER(c_double)), ("e0", c_double),
+                ("nw", c_int32), ("w_len", POINTER(c_int32)), ("w_idx", POINTER(c_int32)),
+                ("w_val", POINTER(c_double))]
 
 
 class sgs_tune(ctypes.Structure):
@@ -193,6 +195,16 @@ class _HostProblem:
         self.s.q_idx = self.q_idx.ctypes.data_as(POINTER(c_int32))
         self.s.q_val = self.q_val.ctypes.data_as(POINTER(c_double))
         self.s.e0 = float(ham.e0)
+        # words of 6 or 8 Majoranas (v_w real, see sgs_problem)
+        words = [tuple(int(x) for x in w) for w in getattr(ham, "higher_idx", ())]
+        self.w_len = np.ascontiguousarray([len(w) for w in words], dtype=np.int32)
+        self.w_idx = np.ascontiguousarray([x for w in words for x in w], dtype=np.int32)
+        self.w_val = np.ascontiguousarray(np.asarray(getattr(ham, "higher_val", ()), dtype=np.float64).reshape(-1))
+        self.s.nw = len(words)
+        if words:
+            self.s.w_len = self.w_len.ctypes.data_as(POINTER(c_int32))
+            self.s.w_idx = self.w_idx.ctypes.data_as(POINTER(c_int32))
+            self.s.w_val = self.w_val.ctypes.data_as(POINTER(c_double))
 
 
 class SGS:

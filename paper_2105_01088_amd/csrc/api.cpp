@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "sgs_internal.h"
@@ -60,6 +61,7 @@ struct PfBatch {
 
 struct Prob {
   int N = 0, n = 0, R = 0, P = 0, Q = 0, M = 0, nq = 0, nnz_up = 0, nnz = 0;
+  int nw = 0, nfe = 0, nfi = 0;  // higher words, Fock entries they touch, (word, a, b) items
   int gj_nb = 16;
   int gj_super = 128;  // super-panel width (a multiple of gj_nb)
   bool gj_first = false;  // pairs (0, a) inverted before the others start
@@ -78,6 +80,12 @@ struct Prob {
   double *pfacc, *logdet, *eps, *Fc, *coef, *Gt, *ht, *lam, *lamt, *E, *tab_la, *tab_arg, *tab_eps;
   double *up_v, *colval, *q_val;
   int *piv, *pa, *pb, *qa, *qb, *pidx, *qidx, *up_k, *up_l, *colptr, *rowidx, *imp, *impos, *q_idx, *q_loc;
+  // higher words: 8 indices (padded), lengths and v per word; per touched
+  // impurity entry (r < c) the range of its (word, a, b) cofactor items
+  int *w_idx = nullptr, *w_len = nullptr, *fe_off = nullptr;
+  int2* fe_ent = nullptr;
+  int4* fe_item = nullptr;
+  double* w_val = nullptr;
   unsigned long long* resid;
   unsigned long long* nsres;
   unsigned long long* dgnorm;
@@ -295,10 +303,17 @@ struct sgs_ctx {
 static int check_problem(const sgs_problem& p) {
   if (p.N < 1 || p.N > 2048 || p.R < 1 || p.R > 32 || !p.A || p.nq < 0 || p.nq > 256) return SGS_EINVAL;
   if (p.nq > 0 && (!p.q_idx || !p.q_val)) return SGS_EINVAL;
+  if (p.nw < 0 || p.nw > 256 || (p.nw > 0 && (!p.w_len || !p.w_idx || !p.w_val))) return SGS_EINVAL;
   const int n = 2 * p.N;
   for (int q = 0; q < p.nq; ++q) {
     const int* x = p.q_idx + 4 * q;
     for (int t = 0; t < 4; ++t)
+      if (x[t] < 0 || x[t] >= n || (t > 0 && x[t] <= x[t - 1])) return SGS_EINVAL;
+  }
+  for (int w = 0, o = 0; w < p.nw; o += p.w_len[w], ++w) {
+    if (p.w_len[w] != 6 && p.w_len[w] != 8) return SGS_EINVAL;
+    const int* x = p.w_idx + o;
+    for (int t = 0; t < p.w_len[w]; ++t)
       if (x[t] < 0 || x[t] >= n || (t > 0 && x[t] <= x[t - 1])) return SGS_EINVAL;
   }
   for (int i = 0; i < n; ++i)
@@ -307,11 +322,36 @@ static int check_problem(const sgs_problem& p) {
   return SGS_OK;
 }
 
-static int impurity_count(const sgs_problem& p) {
+// sorted Majorana indices touched by the interaction words (quartic and higher)
+static std::vector<int> impurity_list(const sgs_problem& p) {
   std::vector<int> v(p.q_idx, p.q_idx + 4 * p.nq);
+  for (int w = 0, o = 0; w < p.nw; o += p.w_len[w], ++w) v.insert(v.end(), p.w_idx + o, p.w_idx + o + p.w_len[w]);
   std::sort(v.begin(), v.end());
   v.erase(std::unique(v.begin(), v.end()), v.end());
-  return (int)v.size();
+  return v;
+}
+
+// Fock items of the higher words: for every position pair a < b of word w an
+// item (w, a, b) on the impurity entry (loc w_a, loc w_b), grouped by entry
+struct FockItems {
+  std::vector<int2> ent;
+  std::vector<int> off;
+  std::vector<int4> item;
+};
+static FockItems fock_items(const sgs_problem& p, const std::vector<int>& impos) {
+  std::map<std::pair<int, int>, std::vector<int4>> by;
+  for (int w = 0, o = 0; w < p.nw; o += p.w_len[w], ++w)
+    for (int a = 0; a < p.w_len[w]; ++a)
+      for (int b = a + 1; b < p.w_len[w]; ++b)
+        by[{impos[p.w_idx[o + a]], impos[p.w_idx[o + b]]}].push_back(make_int4(w, a, b, 0));
+  FockItems f;
+  f.off.push_back(0);
+  for (auto& kv : by) {
+    f.ent.push_back(make_int2(kv.first.first, kv.first.second));
+    f.item.insert(f.item.end(), kv.second.begin(), kv.second.end());
+    f.off.push_back((int)f.item.size());
+  }
+  return f;
 }
 
 static int nnz_count(const sgs_problem& p, int* up) {
@@ -433,6 +473,12 @@ static void carve(Prob& q, Arena& ar) {
   q.impos = ar.take<int>(n);
   q.q_idx = ar.take<int>(std::max(1, 4 * q.nq));
   q.q_loc = ar.take<int>(std::max(1, 4 * q.nq));
+  q.w_idx = ar.take<int>(std::max(1, 8 * q.nw));
+  q.w_len = ar.take<int>(std::max(1, q.nw));
+  q.w_val = ar.take<double>(std::max(1, q.nw));
+  q.fe_ent = ar.take<int2>(std::max(1, q.nfe));
+  q.fe_off = ar.take<int>(q.nfe + 1);
+  q.fe_item = ar.take<int4>(std::max(1, q.nfi));
   q.resid = ar.take<unsigned long long>(8);  // [0]: input validation
   q.nsctl = ar.take<int>(R + 4);  // [0] all done, [1] count, [2 + mu] per state
   q.nsres = ar.take<unsigned long long>(64 * (size_t)(R + 2));  // [it (R + 2) + 2 + mu]: polar residuals
@@ -567,7 +613,11 @@ static size_t plan(std::vector<Prob>& pr, const sgs_problem* probs, int nprob, c
     q.pf.m = q.n;
     q.pf.B = q.Q;
     q.nq = sp.nq; q.e0 = sp.e0;
-    q.M = sp.nq > 0 ? impurity_count(sp) : 0;
+    q.M = (int)impurity_list(sp).size();
+    q.nw = sp.nw;
+    q.nfi = 0;
+    for (int w = 0; w < sp.nw; ++w) q.nfi += sp.w_len[w] * (sp.w_len[w] - 1) / 2;
+    q.nfe = q.nfi;  // at most one entry per item
     q.nnz = nnz_count(sp, &q.nnz_up);
     q.denseA = q.nnz > DENSE_A_PER_COLUMN * q.n;
     (void)lds_max;
@@ -765,15 +815,25 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
   HIPCHK(up(q.up_k, uk)); HIPCHK(up(q.up_l, ul)); HIPCHK(up(q.up_v, uv));
   HIPCHK(up(q.colptr, colptr)); HIPCHK(up(q.rowidx, rowidx)); HIPCHK(up(q.colval, colval));
   // impurity Majoranas
-  std::vector<int> imp(sp.q_idx, sp.q_idx + 4 * sp.nq);
-  std::sort(imp.begin(), imp.end());
-  imp.erase(std::unique(imp.begin(), imp.end()), imp.end());
+  std::vector<int> imp = impurity_list(sp);
   std::vector<int> impos(n, -1), qloc(4 * sp.nq), qidxv(sp.q_idx, sp.q_idx + 4 * sp.nq);
   for (size_t t = 0; t < imp.size(); ++t) impos[imp[t]] = (int)t;
   for (int t = 0; t < 4 * sp.nq; ++t) qloc[t] = impos[sp.q_idx[t]];
   std::vector<double> qv(sp.q_val, sp.q_val + sp.nq);
   HIPCHK(up(q.imp, imp)); HIPCHK(up(q.impos, impos)); HIPCHK(up(q.q_loc, qloc));
   HIPCHK(up(q.q_idx, qidxv)); HIPCHK(up(q.q_val, qv));
+  if (sp.nw > 0) {
+    std::vector<int> widx(8 * sp.nw, -1), wlen(sp.w_len, sp.w_len + sp.nw);
+    for (int w = 0, o = 0; w < sp.nw; o += sp.w_len[w], ++w)
+      for (int t = 0; t < sp.w_len[w]; ++t) widx[8 * w + t] = sp.w_idx[o + t];
+    std::vector<double> wv(sp.w_val, sp.w_val + sp.nw);
+    const FockItems f = fock_items(sp, impos);
+    q.nfe = (int)f.ent.size();
+    HIPCHK(up(q.w_idx, widx)); HIPCHK(up(q.w_len, wlen)); HIPCHK(up(q.w_val, wv));
+    HIPCHK(up(q.fe_ent, f.ent)); HIPCHK(up(q.fe_off, f.off)); HIPCHK(up(q.fe_item, f.item));
+  } else {
+    q.nfe = 0;
+  }
 
   // --- GEMM job tables ---
   // Gauss-Jordan.  Pairs are ordered (0,1) .. (0,R-1), (1,2), ...: the first
@@ -1003,7 +1063,8 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
   }
   // Hamiltonian elements, Fock corrections, Y = Delta F
   tm.begin(SGS_STAGE_WICK, s);
-  HamDev h{n, q.nnz_up, q.nq, q.M, q.up_k, q.up_l, q.up_v, q.q_idx, q.q_loc, q.q_val, q.e0};
+  HamDev h{n, q.nnz_up, q.nq, q.M, q.up_k, q.up_l, q.up_v, q.q_idx, q.q_loc, q.q_val, q.e0,
+           q.nw, q.w_idx, q.w_len, q.w_val, q.nfe, q.fe_ent, q.fe_off, q.fe_item};
   HCHK(launch_eps_fock(h, P, R, q.W, q.Di, q.gam, q.pa, q.pb, q.eps, q.Fc, s));
   SparseA sa{q.colptr, q.rowidx, q.colval, q.imp, q.impos, q.M};
   if (q.denseA) {
@@ -1608,7 +1669,7 @@ int sgs_observables(sgs_ctx* c, int32_t kind, const int32_t* iargs, int32_t niar
   }
   if (kind == SGS_OBS_VARIANCE) {
     if (niargs != 1) return SGS_EINVAL;
-    if (q.R > 32) return SGS_EINVAL;
+    if (q.R > 32 || q.nw > 0) return SGS_EINVAL;
     if (ensure_tables(c, p) != hipSuccess) return SGS_EHIP;
     ObsState s{n, q.R, q.gam, q.W, q.Di, q.lam, q.Gt, q.pidx};
     VarHam h{q.Adense, q.nnz_up, q.up_k, q.up_l, q.up_v, q.colptr, q.rowidx, q.colval, q.nq, q.q_idx, q.q_val};

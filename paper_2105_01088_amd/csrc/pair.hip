@@ -13,6 +13,12 @@
 //            F_{q0q1} += u/2 D_{q2q3}, F_{q0q2} -= u/2 D_{q1q3}, F_{q0q3} += u/2 D_{q1q2},
 //            F_{q1q2} += u/2 D_{q0q3}, F_{q1q3} -= u/2 D_{q0q2}, F_{q2q3} += u/2 D_{q0q1}
 //            (and the skew partners).
+//   Words of m = 6 or 8 Majoranas (term v i^((m/2) mod 2) c_w, v real): the
+//   transition value is i^(m/2) Pf(Delta[w]), so eps gains v Pf(Delta[w]);
+//   F, minus half the derivative of <H>_t in the entries Delta_kl (k < l),
+//   which is A + 6 U Delta for quartic words, gains for positions a < b
+//            F_{w_a w_b} += -(v / 2) (-1)^(a+b+1) Pf(Delta[w without a, b])
+//   (the Pfaffian cofactor of entry (a, b)) and the skew partner.
 #include "sgs_internal.h"
 
 namespace sgs {
@@ -45,6 +51,28 @@ __device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.r - b.r, a.i - 
 __device__ __forceinline__ cplx dget(const double* W, const double* Di, const double* G, int n, int k, int l) {
   if (G) return {G[(long long)k * n + l], 0.0};
   return {-2.0 * W[(long long)k * n + l], Di[(long long)k * n + l]};
+}
+
+// Pfaffian of Delta[x, x] for K = 0, 2, 4, 6 or 8 increasing indices x, by
+// expansion along the first row (no pivots, no division)
+template <int K>
+__device__ cplx pf_idx(const double* W, const double* Di, const double* G, int n, const int* x) {
+  if constexpr (K == 0) {
+    return {1.0, 0.0};
+  } else if constexpr (K == 2) {
+    return dget(W, Di, G, n, x[0], x[1]);
+  } else {
+    cplx r{0.0, 0.0};
+#pragma unroll 1
+    for (int j = 1; j < K; ++j) {
+      int rest[K - 2];
+#pragma unroll
+      for (int i = 1; i < K - 1; ++i) rest[i - 1] = x[i < j ? i : i + 1];
+      const cplx v = cmul(dget(W, Di, G, n, x[0], x[j]), pf_idx<K - 2>(W, Di, G, n, rest));
+      r = (j & 1) ? cadd(r, v) : csub(r, v);  // sign (-1)^(j+1)
+    }
+    return r;
+  }
 }
 
 // grid: P + R blocks (pairs first, then the diagonal states), 256 threads.
@@ -118,6 +146,69 @@ __global__ __launch_bounds__(256) void k_eps_fock(HamDev h, int P, const double*
         fi[c * M + r] -= s * d.i;
       }
     }
+  }
+}
+
+// Words of 6 or 8 Majoranas, after k_eps_fock (same grid, 64 threads):
+// eps += v Pf(Delta[w]); one thread per touched impurity entry (r < c) adds
+// its cofactor items, in a fixed order, to F.  Kept apart so that the
+// quartic-only kernel keeps its registers.
+__global__ __launch_bounds__(64) void k_eps_fock_words(HamDev h, int P, const double* __restrict__ W,
+                                                       const double* __restrict__ Di,
+                                                       const double* __restrict__ gam,
+                                                       double* __restrict__ eps_out, double* __restrict__ Fc_out) {
+  __shared__ double redr[64], redi[64];
+  const int blk = blockIdx.x;
+  const int n = h.n, M = h.M;
+  const long long nn = (long long)n * n;
+  const double *w = nullptr, *di = nullptr, *g = nullptr;
+  if (blk < P) { w = W + blk * nn; di = Di + blk * nn; }
+  else g = gam + (long long)(blk - P) * nn;
+  double sr = 0.0, si = 0.0;
+  for (int q = threadIdx.x; q < h.nw; q += blockDim.x) {
+    const int* x = h.w_idx + 8 * q;
+    const cplx pf = h.w_len[q] == 6 ? pf_idx<6>(w, di, g, n, x) : pf_idx<8>(w, di, g, n, x);
+    sr += h.w_val[q] * pf.r;
+    si += h.w_val[q] * pf.i;
+  }
+  redr[threadIdx.x] = sr;
+  redi[threadIdx.x] = si;
+  __syncthreads();
+  for (int off = 32; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      redr[threadIdx.x] += redr[threadIdx.x + off];
+      redi[threadIdx.x] += redi[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    eps_out[2 * blk] += redr[0];
+    eps_out[2 * blk + 1] += redi[0];
+  }
+  double* fr = Fc_out + (long long)blk * 2 * M * M;
+  double* fi = fr + M * M;
+  // words of 6 or 8: one thread per impurity entry (r < c), its cofactor
+  // items in a fixed order
+  for (int e = threadIdx.x; e < h.nfe; e += blockDim.x) {
+    double ar = 0.0, ai = 0.0;
+    for (int t = h.fe_off[e]; t < h.fe_off[e + 1]; ++t) {
+      const int4 it = h.fe_item[t];
+      const int* x = h.w_idx + 8 * it.x;
+      const int m = h.w_len[it.x];
+      // the word without positions a < b
+      int rest[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) rest[i] = x[i < it.y ? i : (i + 1 < it.z ? i + 1 : i + 2)];
+      const cplx pf = m == 6 ? pf_idx<4>(w, di, g, n, rest) : pf_idx<6>(w, di, g, n, rest);
+      const double s = -0.5 * h.w_val[it.x] * (((it.y + it.z + 1) & 1) ? -1.0 : 1.0);
+      ar += s * pf.r;
+      ai += s * pf.i;
+    }
+    const int2 rc = h.fe_ent[e];
+    fr[rc.x * M + rc.y] += ar;
+    fi[rc.x * M + rc.y] += ai;
+    fr[rc.y * M + rc.x] -= ar;
+    fi[rc.y * M + rc.x] -= ai;
   }
 }
 
@@ -270,6 +361,7 @@ hipError_t launch_eps_fock(const HamDev& h, int P, int R, const double* W, const
                            const double* gam, const int* pa, const int* pb, double* eps,
                            double* Fc, hipStream_t s) {
   hipLaunchKernelGGL(k_eps_fock, dim3(P + R), dim3(256), 0, s, h, P, W, Di, gam, pa, pb, eps, Fc);
+  if (h.nw > 0) hipLaunchKernelGGL(k_eps_fock_words, dim3(P + R), dim3(64), 0, s, h, P, W, Di, gam, eps, Fc);
   return hipGetLastError();
 }
 

@@ -126,6 +126,17 @@ struct HamDev {
   const int* q_loc;    // nq x 4 positions in the impurity list
   const double* q_val;
   double e0;
+  // words of 6 or 8 Majoranas: nw x 8 indices (padded), lengths, v_w; the
+  // impurity entries (r < c) they touch with the ranges of their
+  // (word, a, b) cofactor items
+  int nw;
+  const int* w_idx;
+  const int* w_len;
+  const double* w_val;
+  int nfe;
+  const int2* fe_ent;
+  const int* fe_off;
+  const int4* fe_item;
 };
 
 // A in compressed-column form plus the impurity index maps (pair.hip)

@@ -71,3 +71,87 @@ def test_dense_hamiltonian_steps(weight):
     gam = si.random_states(ham.N, 3, 8)
     _say(f"[general] dense A n={ham.n} R=3 weight={weight}")
     _step_case(ham, gam, weight, 2)
+
+
+# ------------------------------------------ interaction words of 6 and 8
+
+def _multibody(L, W3=0.6, W4=-0.4):
+    ham = si.anderson_multibody(L, 1.0, 0.5, W3, W4)
+    assert {len(w) for w in ham.higher_idx} == {6, 8}
+    return ham
+
+
+@pytest.mark.parametrize("L,R", [(2, 3), (9, 4)])
+def test_multibody_tables_match_oracle(L, R):
+    """ln|G|, arg G and eps_ab with three- and four-body impurity terms
+    (words of 6 and 8 Majoranas, Sec. III.C) against the oracle."""
+    from paper_2105_01088_amd import SGS, default_options
+    ham = _multibody(L)
+    gam = si.random_states(ham.N, R, 21)
+    _say(f"[gen] multibody tables n={ham.n} R={R}")
+    ctx = SGS([ham], [gam], options=default_options())
+    la, ar, ep = ctx.pair_eval()
+    assert ctx.status() == 0
+    tab = osgs.pair_tables(ham, gam)
+    got = ep.cpu().numpy().reshape(R, R, 2)
+    got = got[..., 0] + 1j * got[..., 1]
+    assert np.abs(got - tab.eps).max() < 1e-9 * max(1.0, np.abs(tab.eps).max())
+    off = ~np.eye(R, dtype=bool)
+    assert np.abs(la.cpu().numpy().reshape(R, R) - tab.logabs)[off].max() < 1e-9
+    ctx.close()
+
+
+@pytest.mark.parametrize("weight", [0, 1])
+@pytest.mark.parametrize("L,R,nsteps", [(2, 3, 5), (9, 4, 3)])
+def test_multibody_steps_match_oracle(L, R, nsteps, weight):
+    """Steps with words of 6 and 8 Majoranas: the cofactor Fock terms enter
+    the force; Gamma and E against the oracle at 1e-10."""
+    from paper_2105_01088_amd import SGS, default_options
+    ham = _multibody(L)
+    gam = si.random_states(ham.N, R, 22)
+    _say(f"[gen] multibody steps n={ham.n} R={R} weight={weight}")
+    ctx = SGS([ham], [gam], options=default_options(weight=weight))
+    e = ctx.step(0.05, nsteps).cpu().numpy()
+    assert ctx.status() == 0
+    g = gam
+    es = []
+    for _ in range(nsteps):
+        r = osgs.step(ham, g, 0.05, mode="printed" if weight == 0 else "unit")
+        es.append(r.E)
+        g = r.gammas
+    assert np.abs(e - es).max() < TOL_E * np.abs(es).max()
+    assert np.abs(ctx.gammas(0).cpu().numpy() - g).max() < TOL_GAMMA
+    ctx.close()
+
+
+def test_multibody_larger_chain_one_step():
+    """n = 200 (L = 49), R = 6, one step."""
+    from paper_2105_01088_amd import SGS, default_options
+    ham = _multibody(49)
+    gam = si.random_states(ham.N, 6, 23)
+    _say(f"[gen] multibody n={ham.n} R=6 one step")
+    ctx = SGS([ham], [gam], options=default_options(weight=1))
+    e = ctx.step(0.05, 1).cpu().numpy()
+    assert ctx.status() == 0
+    r = osgs.step(ham, gam, 0.05, mode="unit")
+    assert abs(e[0] - r.E) < TOL_E * abs(r.E)
+    assert np.abs(ctx.gammas(0).cpu().numpy() - r.gammas).max() < TOL_GAMMA
+    ctx.close()
+
+
+def test_multibody_rejects_variance_and_bad_words():
+    from paper_2105_01088_amd import SGS, SGSError, default_options
+    ham = _multibody(2)
+    gam = si.random_states(ham.N, 2, 24)
+    _say("[gen] multibody argument checks")
+    ctx = SGS([ham], [gam], options=default_options())
+    with pytest.raises(SGSError):
+        ctx.variance()
+    ctx.close()
+    bad = si.anderson_multibody(2, 1.0, 0.5, 0.6, -0.4)
+    bad.higher_idx = ((0, 1, 2, 3, 4),) + tuple(bad.higher_idx[1:])  # odd length
+    with pytest.raises(SGSError):
+        SGS([bad], [gam], options=default_options())
+    bad.higher_idx = ((0, 2, 1, 3, 4, 5),) + tuple(bad.higher_idx[1:])  # not increasing
+    with pytest.raises(SGSError):
+        SGS([bad], [gam], options=default_options())
