@@ -138,7 +138,10 @@ typedef struct {
   int32_t force_elem;   /* elementwise force terms: 1 beside the products on */
                         /* a second stream, 2 after them on the same stream  */
   int32_t force_tile;   /* force products: output tile edge, 64 or 128      */
-  int32_t reserved[1];
+  int32_t gj_defer;     /* Gauss-Jordan inner updates deferred to one update */
+  /* per super-panel (each panel then first takes the earlier panels'       */
+  /* updates of its own columns): 1 in neither batch of pairs, 2 in the     */
+  /* pairs not involving state 0, 3 in both                                */
 } sgs_tune;
 
 typedef struct {

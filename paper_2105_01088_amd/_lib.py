@@ -45,10 +45,10 @@ class sgs_problem(ctypes.Structure):
 class sgs_tune(ctypes.Structure):
     _fields_ = [("n_max", c_int32), ("gj_super", c_int32), ("gj_first", c_int32), ("pf_super", c_int32),
                 ("force_split", c_int32), ("force_elem", c_int32), ("force_tile", c_int32),
-                ("reserved", c_int32 * 1)]
+                ("gj_defer", c_int32)]
 
 
-TUNE_FIELDS = ("n_max", "gj_super", "gj_first", "pf_super", "force_split", "force_elem", "force_tile")
+TUNE_FIELDS = ("n_max", "gj_super", "gj_first", "pf_super", "force_split", "force_elem", "force_tile", "gj_defer")
 
 
 class sgs_options(ctypes.Structure):

@@ -7,7 +7,7 @@ For each workload (one per size bucket) it times imaginary-time steps on the
 GPU while it varies one tuning field at a time over its candidates (coordinate
 descent from the library's built-in choices: Gauss-Jordan super-panel width,
 inverse order, Pfaffian super-panel depth, force term split and elementwise
-placement, force tile edge), keeps the fastest value of each field, and writes the rows as
+placement, force tile edge, deferral of the Gauss-Jordan inner updates), keeps the fastest value of each field, and writes the rows as
 JSON: {"rows": [{n_max, gj_super, ...}], "measured": {...}}.  The file is read
 by paper_2105_01088_amd.default_options(tune=path) and bench.py --tune.
 Every choice changes scheduling and blocking only; results agree with the
@@ -27,6 +27,7 @@ CANDIDATES = {
     "force_split": [1, 2, 3],
     "force_elem": [1, 2],
     "force_tile": [64, 128],
+    "gj_defer": [1, 2, 3],
 }
 DEFAULT_CONFIGS = ["anderson_L99_R16", "anderson_L199_R32_U1", "tck_L150_R24_J0.3"]
 

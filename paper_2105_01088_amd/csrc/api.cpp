@@ -65,6 +65,13 @@ struct Prob {
   int gj_nb = 16;
   int gj_super = 128;  // super-panel width (a multiple of gj_nb)
   bool gj_first = false;  // pairs (0, a) inverted before the others start
+  // deferred Gauss-Jordan inner updates: 1 neither batch, 2 the pairs
+  // (a >= 1, b), 3 both.  Measured at n = 400, 800, 1204 (ms per step):
+  // 5.72 / 5.82 / 6.06, 92.7 / 93.3 / 93.7, 185.9 / 185.7 / 186.5: the
+  // shorter inverse and Pfaffian chains do not shorten the step (the extra
+  // launch before every panel lengthens the chain the others wait on), so
+  // the built-in choice applies every panel's update at once
+  int gj_defer = 1;
   int force_split = 2;    // workgroups per force output tile (term ranges)
   int force_tile = 0;     // force output tile edge (64 or 128; 0: by size and precision)
   bool force_seq = false;  // elementwise force terms after the products, same stream
@@ -100,13 +107,17 @@ struct Prob {
   ExpCoef excf{};
   // Gauss-Jordan: inner updates per panel and trailing updates per
   // super-panel, for the pairs (0, a) (jgj0, jgs0) and the rest (jgj1, jgs1)
-  std::vector<JobTable> jgj0, jgj1, jgs0, jgs1;
+  std::vector<JobTable> jgj0, jgj1, jgs0, jgs1, jgf0, jgf1;
   std::vector<int> gj_k, gj_b, gj_s, gs_k, gs_nb;
   // Pfaffians of the Q matrices C_ab (order n)
   PfBatch pf;
 };
 
 // per pair: the panel's Brow (b x super-panel) or a super-panel's pivot rows (nb x n)
+// whether the batch half (0: pairs (0, a), 1: the others) defers its
+// Gauss-Jordan inner updates
+static bool gj_deferred(const Prob& q, int half) { return half == 0 ? q.gj_defer == 3 : q.gj_defer >= 2; }
+
 long long gj_brow_stride(int n) { return std::max((long long)GJ_NB_MAX * GJ_SUPER_MAX, (long long)GJ_SUPER_MAX * n); }
 
 int gemm_tiles(int M, int N, int mirror = 0) {
@@ -418,7 +429,7 @@ static void carve_scratch(Prob& q, Arena& ar) {
   q.T1 = ar.take<double>(std::max(1LL, (R - 1) * nn));
   q.Xr = ar.take<double>(std::max(1LL, (R - 1) * nn));
   pf_carve(q.pf, ar);
-  q.gjE = ar.take<double>(std::max(1LL, (long long)P * n * GJ_NB_MAX));
+  q.gjE = ar.take<double>(std::max(1LL, (long long)P * n * q.gj_super));  // E_all per pair
   q.gjB = ar.take<double>(std::max(1LL, (long long)P * gj_brow_stride(n)));
   q.dG = ar.take<double>(R * nn);
   q.dP = ar.take<double>(std::max(1LL, (FORCE_SPLIT_MAX - 1) * R * nn));  // partial force products, added into dG
@@ -514,10 +525,15 @@ static void carve_jobs(Prob& q, Arena& ar) {
   q.jgj1.assign(q.gj_k.size(), JobTable());
   q.jgs0.assign(q.gs_k.size(), JobTable());
   q.jgs1.assign(q.gs_k.size(), JobTable());
+  q.jgf0.assign(q.gs_k.size(), JobTable());
+  q.jgf1.assign(q.gs_k.size(), JobTable());
   for (auto& t : q.jgj0) table(t, P0);
   for (auto& t : q.jgj1) table(t, q.P - P0);
   for (auto& t : q.jgs0) table(t, 2 * P0);
   for (auto& t : q.jgs1) table(t, 2 * (q.P - P0));
+  const int pps = GJ_SUPER_MAX / std::max(1, q.gj_nb);  // panels per super-panel, at most
+  for (auto& t : q.jgf0) table(t, pps * P0);
+  for (auto& t : q.jgf1) table(t, pps * (q.P - P0));
   pf_schedule(q.pf, ar);
   table(q.jdi, q.P);
   table(q.jya, q.denseA ? 2 * q.P + q.R : 0);
@@ -582,6 +598,7 @@ static void pick_tuning(Prob& q, const sgs_options& o) {
     if (t.force_split > 0) q.force_split = t.force_split;
     if (t.force_elem > 0) q.force_seq = t.force_elem == 2;
     if (t.force_tile > 0) q.force_tile = t.force_tile;
+    if (t.gj_defer > 0) q.gj_defer = t.gj_defer;
     break;
   }
   q.gj_super = std::max(q.gj_nb, std::min(GJ_SUPER_MAX, q.gj_super / q.gj_nb * q.gj_nb));
@@ -837,22 +854,59 @@ static int build_tables(Prob& q, const sgs_problem& sp) {
 
   // --- GEMM job tables ---
   // Gauss-Jordan.  Pairs are ordered (0,1) .. (0,R-1), (1,2), ...: the first
-  // R - 1 feed the phases and form their own batch.  Inner update of panel t
-  // (columns [k, k + b) of super-panel [k0, k0 + nbs)):
-  //   M[:, k0:k0+nbs] -= E Brow   (E: n x b, Brow: b x nbs)
-  // trailing update of super-panel s, the columns left and right of it:
+  // R - 1 feed the phases and form their own batch.  Per pair E_all (n x ES)
+  // and Brow_all (ES x ES, in the Brow buffer), ES = gj_super; panel t covers
+  // columns [k, k + b), kl = k - k0, of super-panel [k0, k0 + nbs).  A batch
+  // with deferred inner updates runs before the panel (kl > 0)
+  //   M[:, k:k+b] -= E_all[:, 0:kl] Brow_all[0:kl, kl:kl+b]
+  // and after the super-panel's last panel, for every panel v = [kv, kv + bv)
+  // but the last (kv local),
+  //   M[:, k0+kv : k0+kv+bv] -= E_all[:, kv+bv : nbs] Brow_all[kv+bv : nbs, kv : kv+bv];
+  // a batch without runs after the panel
+  //   M[:, k0:k0+nbs] -= E_all[:, kl:kl+b] Brow_all[kl:kl+b, 0:nbs].
+  // Trailing update of super-panel s, the columns left and right of it:
   //   M[:, c] += M[:, k0:k0+nbs] Brow[:, c]   (Brow: nbs x n)
   const long long bstr = gj_brow_stride(n);
+  const int ES = q.gj_super;
   for (size_t t = 0; t < q.gj_k.size(); ++t) {
-    const int b = q.gj_b[t], s = q.gj_s[t], k0 = q.gs_k[s], nbs = q.gs_nb[s];
+    const int b = q.gj_b[t], s = q.gj_s[t], k0 = q.gs_k[s], nbs = q.gs_nb[s], kl = q.gj_k[t] - k0;
     for (int half = 0; half < 2; ++half) {
       JobTable& jt = half == 0 ? q.jgj0[t] : q.jgj1[t];
       jt.host.clear(); jt.ntiles = 0; jt.late_c = true;
       const int p0 = half == 0 ? 0 : std::min(P, R - 1), p1 = half == 0 ? std::min(P, R - 1) : P;
-      if (nbs > b)  // a super-panel of one panel has nothing else to update
-        for (int pp = p0; pp < p1; ++pp)
-          add_job(jt, job(q.gjE + (long long)pp * n * GJ_NB_MAX, b, 0, q.gjB + pp * bstr, nbs, 0,
-                          q.Di + pp * nn + k0, n, q.Di + pp * nn + k0, n, n, nbs, b, -1.0, 1.0));
+      const bool defer = gj_deferred(q, half);
+      for (int pp = p0; pp < p1; ++pp) {
+        const double* Ea = q.gjE + (long long)pp * n * ES;
+        const double* Ba = q.gjB + pp * bstr;
+        if (defer && kl > 0) {
+          double* Mk = q.Di + pp * nn + q.gj_k[t];
+          add_job(jt, job(Ea, ES, 0, Ba + kl, ES, 0, Mk, n, Mk, n, n, b, kl, -1.0, 1.0));
+        } else if (!defer && nbs > b) {  // a super-panel of one panel has nothing else to update
+          double* Ms = q.Di + pp * nn + k0;
+          add_job(jt, job(Ea + kl, ES, 0, Ba + (long long)kl * ES, ES, 0, Ms, n, Ms, n, n, nbs, b, -1.0, 1.0));
+        }
+      }
+      HIPCHK(upload_jobs(jt));
+    }
+  }
+  for (size_t s = 0; s < q.gs_k.size(); ++s) {
+    const int k0 = q.gs_k[s], nbs = q.gs_nb[s];
+    for (int half = 0; half < 2; ++half) {
+      JobTable& jt = half == 0 ? q.jgf0[s] : q.jgf1[s];
+      jt.host.clear(); jt.ntiles = 0; jt.late_c = true;
+      const int p0 = half == 0 ? 0 : std::min(P, R - 1);
+      const int p1 = !gj_deferred(q, half) ? p0 : (half == 0 ? std::min(P, R - 1) : P);
+      for (size_t t = 0; t < q.gj_k.size(); ++t) {
+        if (q.gj_s[t] != (int)s) continue;
+        const int kv = q.gj_k[t] - k0, bv = q.gj_b[t];
+        if (kv + bv >= nbs) continue;  // the last panel: no later panel
+        for (int pp = p0; pp < p1; ++pp) {
+          double* Mv = q.Di + pp * nn + k0 + kv;
+          const double* Ea = q.gjE + (long long)pp * n * ES + kv + bv;
+          const double* Bv = q.gjB + pp * bstr + (long long)(kv + bv) * ES + kv;
+          add_job(jt, job(Ea, ES, 0, Bv, ES, 0, Mv, n, Mv, n, n, bv, nbs - kv - bv, -1.0, 1.0));
+        }
+      }
       HIPCHK(upload_jobs(jt));
     }
   }
@@ -1004,15 +1058,20 @@ static hipError_t pair_stage(sgs_ctx* c, Prob& q, double* energy_slot, double* o
     auto inverses = [&](int half, hipStream_t st) -> hipError_t {
       const int off = half == 0 ? 0 : P0, cnt = half == 0 ? P0 : P - P0;
       const long long bstr = gj_brow_stride(n);
+      const int ES = q.gj_super;
       for (size_t t = 0; t < q.gj_k.size(); ++t) {
         const int s = q.gj_s[t], k0 = q.gs_k[s], nbs = q.gs_nb[s];
+        const bool defer = gj_deferred(q, half);
+        const JobTable& inner = half == 0 ? q.jgj0[t] : q.jgj1[t];
+        if (defer) HCHK(run_gemm(inner, st));  // the earlier panels' updates of this panel's columns
         HCHK(launch_gj_panel(q.Di + off * nn, nn, cnt, n, q.gj_k[t], q.gj_b[t],
-                             q.gjE + (long long)off * n * GJ_NB_MAX, (long long)n * GJ_NB_MAX,
-                             q.gjB + off * bstr, bstr, k0, k0 + nbs,
+                             q.gjE + (long long)off * n * ES, (long long)n * ES, ES,
+                             q.gjB + off * bstr, bstr, ES, k0, k0 + nbs, q.gj_nb, defer ? 1 : 0,
                              q.piv + (long long)off * n, q.piv + (long long)(P + off) * n, q.logdet + off,
                              c->status, st));
-        HCHK(run_gemm(half == 0 ? q.jgj0[t] : q.jgj1[t], st));
+        if (!defer) HCHK(run_gemm(inner, st));  // this panel's update of the whole super-panel
         if (t + 1 == q.gj_k.size() || q.gj_s[t + 1] != s) {  // the super-panel's last panel
+          HCHK(run_gemm(half == 0 ? q.jgf0[s] : q.jgf1[s], st));
           HCHK(launch_gj_gather(q.Di + off * nn, nn, cnt, n, k0, nbs, q.piv + (long long)off * n,
                                 q.gjB + off * bstr, bstr, st));
           HCHK(run_gemm(half == 0 ? q.jgs0[s] : q.jgs1[s], st));
@@ -1193,7 +1252,7 @@ static int check_options(const sgs_options& o) {
     if (t.n_max < 2 || (i > 0 && t.n_max <= o.tune[i - 1].n_max)) return SGS_EINVAL;
     if (t.gj_super > GJ_SUPER_MAX || t.gj_first > 2 || t.pf_super > PF_SUPER_MAX ||
         t.force_split > FORCE_SPLIT_MAX || t.force_elem > 2 ||
-        (t.force_tile != 0 && t.force_tile != 64 && t.force_tile != 128))
+        (t.force_tile != 0 && t.force_tile != 64 && t.force_tile != 128) || t.gj_defer > 3)
       return SGS_EINVAL;
   }
   return SGS_OK;
@@ -1249,7 +1308,7 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
   }
   size_t lds_gj = 0, lds_solve = 0;
   for (auto& q : c->pr) {
-    lds_gj = std::max(lds_gj, gj_panel_lds_bytes(q.n, 0, gj_panel_shape(q.n).B));
+    lds_gj = std::max(lds_gj, gj_panel_lds_bytes(q.n, q.gj_super - q.gj_nb, q.gj_nb));
     lds_solve = std::max(lds_solve, solve_lds_bytes(q.R));
   }
   int nmax = 2;

@@ -5,17 +5,32 @@
 //
 // Pivoting is virtual: rows never move.  Logical row r of the elimination is
 // physical row piv[r], the row chosen as pivot for column r.  Two levels of
-// column panels: super-panels Js = [k0, k0+nb) of up to 128 columns, each
-// swept by panels J = [k, k+b) of up to 32:
-//   1. k_gj_panel (one workgroup per matrix) sweeps the n x b panel with
-//      partial pivoting over the free rows; with D = (pivot block)^-1 it
-//      writes the multipliers E = M[:, J] D for every row (E_i = e_l - D_l on
-//      the pivot row of position l), the final panel columns (-E_i; D_l on
-//      the pivot rows) and Brow = the pivot rows on Js, zero on J.
-//   2. grouped GEMM: M[:, Js] <- M[:, Js] - E Brow (the other columns of the
-//      super-panel, earlier panels included, take the exchange of J).
-// After its last panel the super-panel holds the exchange of the whole block
-// (exchanges of column blocks compose): with P the pivot rows of Js,
+// column panels: super-panels Js = [k0, k0+S) of up to 256 columns, each
+// swept by panels J_t = [k, k+b) of up to 32 (position kl = k - k0 = t nbp
+// inside the super-panel).  Panel t's exchange updates the whole block,
+// B <- B - E_t Brow_t, with E_t = B[:, J_t] D (D = (pivot block)^-1; e_l - D_l
+// on the pivot row of position l) and Brow_t = the pivot rows on Js (zero on
+// J_t).  These updates are deferred: the stored block only changes in the
+// columns of the panels swept so far (each holding its panel's output), and
+// E_t, Brow_t are kept for the super-panel (E_all n x S, Brow_all S x S):
+//   1. grouped GEMM (t > 0): M[:, J_t] -= E_all[:, 0:kl] Brow_all[0:kl, J_t],
+//      the earlier panels' updates of this panel's columns only;
+//   2. k_gj_panel (one workgroup per matrix) sweeps the n x b panel with
+//      partial pivoting over the free rows and writes the final panel
+//      columns (-E_i; D_l on the pivot rows), E_t into E_all and Brow_t into
+//      Brow_all: its pivot rows as stored plus their deferred sums (columns
+//      of later panels take every earlier panel's update, columns of an
+//      earlier panel v those of the panels after v);
+//   3. after the last panel, grouped GEMM: for every panel v but the last,
+//      M[:, J_v] -= E_all[:, J_>v] Brow_all[J_>v, J_v] (the later panels'
+//      updates of its output).
+// The block is then read and written about twice per super-panel instead of
+// once per panel.  Without deferral (a small batch, where the extra launch
+// before every panel costs more than it saves) step 1 is absent, the panel
+// takes its pivot rows as stored, and after it
+//   M[:, Js] -= E_t Brow_t   (every column of the super-panel)
+// replaces step 3.  After the super-panel it holds the exchange of the whole
+// block (exchanges of column blocks compose): with P the pivot rows of Js,
 // M[P, Js] = (M_old[P, Js])^-1 and M[i, Js] = -M_old[i, Js] M_old[P, Js]^-1
 // elsewhere, and the rest of the matrix takes one rank-nb update:
 //   3. k_gj_gather copies Brow = M[P, :] (zero on Js) and clears M[P, :]
@@ -54,9 +69,9 @@ constexpr int GJ_MAX_WAVES = 8;
 template <int B, int RPT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gj_panel(double* __restrict__ Mall, long long mstride,
                                                   int n, int k, int b,
-                                                  double* __restrict__ Eall, long long estride,
-                                                  double* __restrict__ Ball, long long bstride,
-                                                  int bc0, int bc1,
+                                                  double* __restrict__ Eall, long long estride, int eld,
+                                                  double* __restrict__ Ball, long long bstride, int brld,
+                                                  int bc0, int bc1, int nbp, int defer,
                                                   int* __restrict__ pivall, int* __restrict__ srcall,
                                                   double* __restrict__ logdet,
                                                   int* __restrict__ status) {
@@ -77,6 +92,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   int* __restrict__ src = srcall + (long long)mat * n;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
+  const int kl = k - bc0;  // the panel's position in the super-panel
 
   for (int i = tid; i < n; i += nt) tag[i] = 0;
   // the panel into registers, through the wave's LDS tile: coalesced loads
@@ -264,21 +280,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     if (sing) atomicCAS(status, ST_OK, ST_SINGULAR);
   }
   __syncthreads();  // pivl complete
-  // Brow: the pivot rows on columns [bc0, bc1) (leading dimension
-  // bc1 - bc0), zero on J; 16 rows in flight per thread
-  const int ldbr = bc1 - bc0;
-  for (int l0 = 0; l0 < b; l0 += 16) {
-    for (int c = bc0 + tid; c < bc1; c += nt) {
-      const bool inj = c >= k && c < k + b;
-      double v[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        v[u] = (l0 + u < b && !inj) ? M[(long long)pivl[l0 + u] * n + c] : 0.0;
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (l0 + u < b) Br[(long long)(l0 + u) * ldbr + (c - bc0)] = v[u];
-    }
-  }
   // panel outputs (pivot rows M[i, J] = D_l, E_i = e_l - D_l; others
   // M[i, J] = -E_i), through the wave's LDS tile as coalesced row segments
   if (STG) {
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             const double v = stg[rr * (CB + 1) + cc];
             const int l = spos[rr];
             M[(long long)i * n + k + c] = l >= 0 ? v : -v;
-            E[(long long)i * b + c] = l >= 0 ? (c == l ? 1.0 : 0.0) - v : v;
+            E[(long long)i * eld + kl + c] = l >= 0 ? (c == l ? 1.0 : 0.0) - v : v;
           }
         }
         __builtin_amdgcn_wave_barrier();
@@ -315,11 +316,38 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           if (c < b) {
             const double v = x[r][c];
             M[(long long)i * n + k + c] = pos[r] >= 0 ? v : -v;
-            E[(long long)i * b + c] = pos[r] >= 0 ? (c == pos[r] ? 1.0 : 0.0) - v : v;
+            E[(long long)i * eld + kl + c] = pos[r] >= 0 ? (c == pos[r] ? 1.0 : 0.0) - v : v;
           }
         }
       }
     }
+  }
+  // Brow_t: the pivot rows on the super-panel's columns (row kl + l of
+  // Brow_all, leading dimension brld), zero on J_t, with the deferred sums of
+  // the earlier panels: a column of a later panel takes every earlier
+  // panel's update, a column of an earlier panel v those of panels v+1 ..
+  // t-1.  The pivot rows' E entries of the earlier panels go to LDS first
+  // (read as broadcasts); every thread then takes (row, column) items, a
+  // wave covering consecutive columns of one row.
+  // (after the per-wave row positions of every wave)
+  double* __restrict__ es = (double*)((int*)((double*)(tag + ((n + 3) & ~3)) + nw * 64 * (CB + 1)) + nw * 64);
+  const int kd = defer ? kl : 0;  // earlier panels whose updates are deferred
+  for (int e = tid; e < b * kd; e += nt) {
+    const int l = e / kd, j = e - l * kd;
+    es[e] = E[(long long)pivl[l] * eld + j];
+  }
+  __syncthreads();
+  const int sw = bc1 - bc0;
+  for (int e = tid; e < b * sw; e += nt) {
+    const int l = e / sw, lc = e - l * sw, c = bc0 + lc;
+    double v = 0.0;
+    if (c < k || c >= k + b) {
+      v = M[(long long)pivl[l] * n + c];
+      const int js = c < k ? (lc / nbp + 1) * nbp : 0;
+      const double* __restrict__ el = es + l * kd;
+      for (int j = js; j < kd; ++j) v = fma(-el[j], Br[(long long)j * brld + lc], v);
+    }
+    Br[(long long)(kl + l) * brld + lc] = v;
   }
   if (tid < b) piv[k + tid] = pivl[tid];
   // after the last panel: src = piv^-1 for the unscramble
@@ -393,26 +421,29 @@ GjPanelShape gj_panel_shape(int n) {
   return sh;
 }
 
-size_t gj_panel_lds_bytes(int n, int k, int b) {
-  (void)k;
-  (void)b;
+// tag, the per-wave staging tiles and row positions, then the b x kl pivot
+// rows' E entries (kl = the panel's position in its super-panel)
+size_t gj_panel_lds_bytes(int n, int kl, int b) {
   const GjPanelShape sh = gj_panel_shape(n);
   const int cb = sh.B < 16 ? sh.B : 16;
   const size_t nw = (size_t)sh.nt / 64;
-  return sizeof(int) * (size_t)((n + 3) & ~3) + nw * 64 * (cb + 1) * sizeof(double) + nw * 64 * sizeof(int) + 64;
+  return sizeof(int) * (size_t)((n + 3) & ~3) + nw * 64 * (cb + 1) * sizeof(double) + nw * 64 * sizeof(int) +
+         (size_t)b * kl * sizeof(double) + 64;
 }
 
 hipError_t launch_gj_panel(double* M, long long mstride, int nmat, int n, int k, int b,
-                           double* E, long long estride, double* Br, long long bstride, int bc0, int bc1,
-                           int* piv, int* src, double* logdet, int* status, hipStream_t s) {
+                           double* E, long long estride, int eld, double* Br, long long bstride, int brld,
+                           int bc0, int bc1, int nbp, int defer, int* piv, int* src, double* logdet,
+                           int* status, hipStream_t s) {
   const GjPanelShape sh = gj_panel_shape(n);
   if (b < 1 || b > sh.B || k < 0 || k + b > n || (long long)sh.nt * sh.rpt < n) return hipErrorInvalidValue;
-  if (bc0 < 0 || bc1 > n || bc0 > k || bc1 < k + b || (long long)b * (bc1 - bc0) > bstride)
+  if (bc0 < 0 || bc1 > n || bc0 > k || bc1 < k + b || nbp < b || (k - bc0) % nbp != 0 || eld < bc1 - bc0 ||
+      brld < bc1 - bc0 || (long long)n * eld > estride || (long long)(bc1 - bc0) * brld > bstride)
     return hipErrorInvalidValue;
-  const size_t lds = gj_panel_lds_bytes(n, k, sh.B);
+  const size_t lds = gj_panel_lds_bytes(n, defer ? k - bc0 : 0, b);
 #define GJ_LAUNCH(BB, RP)                                                                                    \
   hipLaunchKernelGGL((k_gj_panel<BB, RP>), dim3(nmat), dim3(sh.nt), lds, s, M, mstride, n, k, b, E, estride, \
-                     Br, bstride, bc0, bc1, piv, src, logdet, status)
+                     eld, Br, bstride, brld, bc0, bc1, nbp, defer, piv, src, logdet, status)
   if (sh.rpt == 1) GJ_LAUNCH(32, 1);
   else if (sh.rpt == 2) GJ_LAUNCH(32, 2);
   else if (sh.rpt == 3) GJ_LAUNCH(24, 3);

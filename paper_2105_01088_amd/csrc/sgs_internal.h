@@ -181,11 +181,15 @@ struct GjPanelShape {
   int B, rpt, nt;
 };
 GjPanelShape gj_panel_shape(int n);
-size_t gj_panel_lds_bytes(int n, int k, int b);
-// Brow of the panel covers columns [bc0, bc1) (leading dimension bc1 - bc0)
-hipError_t launch_gj_panel(double* M, long long mstride, int nmat, int n, int k, int b, double* E,
-                           long long estride, double* Br, long long bstride, int bc0, int bc1, int* piv, int* src,
-                           double* logdet, int* status, hipStream_t s);
+size_t gj_panel_lds_bytes(int n, int kl, int b);
+// Super-panel [bc0, bc1) of panels nbp wide: E_all (n x (bc1 - bc0), leading
+// dimension eld) and Brow_all ((bc1 - bc0) x (bc1 - bc0), leading dimension
+// brld) per matrix; the panel at k writes its columns of E_all and its rows
+// of Brow_all (k - bc0 onward)
+hipError_t launch_gj_panel(double* M, long long mstride, int nmat, int n, int k, int b,
+                           double* E, long long estride, int eld, double* Br, long long bstride, int brld,
+                           int bc0, int bc1, int nbp, int defer, int* piv, int* src, double* logdet,
+                           int* status, hipStream_t s);
 // super-panel [k0, k0 + nb) done: Br = its pivot rows (nb x n, zero on the
 // super-panel), which are then cleared outside it
 hipError_t launch_gj_gather(double* M, long long mstride, int nmat, int n, int k0, int nb, const int* piv,

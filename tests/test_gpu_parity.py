@@ -268,3 +268,28 @@ def test_force_tiles_match_oracle(tile, L, R, seed):
     assert abs(e.cpu().item() - ref.E) < TOL_E * abs(ref.E)
     assert np.abs(g_new - ref.gammas).max() < TOL_GAMMA
     ctx.close()
+
+
+@pytest.mark.parametrize("defer", [1, 2, 3])
+@pytest.mark.parametrize("L,R,seed", [(32, 5, 5), (64, 4, 6), (99, 5, 7)])
+def test_gj_deferral_matches_oracle(defer, L, R, seed):
+    """The Gauss-Jordan inner updates applied after every panel (1), deferred
+    for the pairs not involving state 0 (2) or for all pairs (3), on n = 132,
+    260 and 400 (super-panels of 128 plus a ragged one), whatever the built-in
+    choice: the pair tables at 1e-9 and one step at 1e-10."""
+    ham = si.anderson(L, 1.2, 0.7)
+    gam = si.random_states(ham.N, R, seed)
+    _say(f"[step] gj_defer {defer}, n={ham.n} R={R}")
+    ctx = _ctx(ham, gam, weight=1, tune=[{"n_max": 4096, "gj_defer": defer}])
+    la, ar, ep = _tables(ctx)
+    tab = osgs.pair_tables(ham, gam)
+    off = ~np.eye(R, dtype=bool)
+    assert np.abs(la - tab.logabs)[off].max() < TOL_TAB * max(1.0, np.abs(tab.logabs).max())
+    assert np.abs(ep - tab.eps).max() < TOL_TAB * max(1.0, np.abs(tab.eps).max())
+    e = ctx.step(0.05, 1)
+    assert ctx.status() == 0
+    g_new = ctx.gammas(0).cpu().numpy()
+    ref = osgs.step(ham, gam, 0.05, mode="unit")
+    assert abs(e.cpu().item() - ref.E) < TOL_E * abs(ref.E)
+    assert np.abs(g_new - ref.gammas).max() < TOL_GAMMA
+    ctx.close()
