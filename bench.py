@@ -143,6 +143,10 @@ def main(argv=None):
                     help="run the rank-growing protocol (Sec. III.C) on the workload: STEPS steps at "
                          "each rank from 1 to R, one rotated copy of the largest-amplitude state added "
                          "per rank; prints its own JSON line")
+    ap.add_argument("--renyi", default=None, metavar="NA[,NA...]",
+                    help="time the Renyi-2 entropy S_2 of the first NA Majoranas (impurity plus sites) "
+                         "on the workload after the warmup steps, automatic method and block form; "
+                         "prints its own JSON line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers (counter calibration) and exit")
     args = ap.parse_args(argv)
@@ -159,7 +163,7 @@ def main(argv=None):
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding of this path is described in DESIGN.md and not built.",
+              "the sharding of this path over several GPUs is not built.",
               file=sys.stderr)
         return 2
 
@@ -173,6 +177,8 @@ def main(argv=None):
         return bench_batched(args)
     if args.grow > 0:
         return bench_grow(args)
+    if args.renyi:
+        return bench_renyi(args)
 
     ham, gam, cfg = si.config_problem(args.config)
     n, R = ham.n, gam.shape[0]
@@ -357,7 +363,7 @@ def main(argv=None):
         # Rs chosen so that the sample is some 10-30 s of host work
         from oracle import sgs as osgs
         model, blas, cores = cpu_info()
-        Rs = R if n <= 400 else 4
+        Rs = R if n <= 400 else min(R, 8)  # 28 pairs: about 14 s at n = 1204 on 16 cores
         Ps = Rs * (Rs - 1) // 2
         hp = ham.poly()
         c0 = time.time()
@@ -448,6 +454,44 @@ def bench_batched(args):
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def bench_renyi(args) -> int:
+    """S_2 (Eq. S2_SGS, App. B) of A = Majoranas 0..NA-1 on the workload's
+    states after the warmup steps: milliseconds per evaluation (the call waits
+    for its stream) with the automatic method and with the block form for
+    every term, and the number of representative terms, about R^4 / 4."""
+    import torch
+
+    import sgs_inputs as si
+    from paper_2105_01088_amd import SGS, SGS_REN_AUTO, SGS_REN_BLOCK, default_options
+
+    ham, gam, cfg = si.config_problem(args.config)
+    R = gam.shape[0]
+    ctx = SGS([ham], [gam], options=default_options(weight=1 if args.weight == "unit" else 0))
+    ctx.step(float(args.dtau if args.dtau is not None else 0.05), max(1, args.warmup))
+    torch.cuda.synchronize()
+    out = []
+    for nA in (int(x) for x in args.renyi.split(",")):
+        for method in ((SGS_REN_AUTO, SGS_REN_BLOCK) if nA > 32 else (SGS_REN_AUTO,)):
+            v = ctx.renyi2(nA, method=method)  # buffers, tables
+            reps = max(1, args.steps)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                v = ctx.renyi2(nA, method=method)
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            out.append({"nA": nA, "method": "auto" if method == SGS_REN_AUTO else "block", "ms_per_eval": ms,
+                        "S2": v})
+            print(f"renyi2 nA={nA} {out[-1]['method']}: {ms:.2f} ms, S2 = {v:.12f}", file=sys.stderr, flush=True)
+    status = ctx.status()
+    ctx.close()
+    terms = sum(1 for p in range(R * R) for q in range(p, R * R)
+                if tuple(sorted(((p % R) * R + p // R, (q % R) * R + q // R))) >= (p, q))
+    print(json.dumps({"metric": "Renyi-2 evaluations", "unit": "ms/eval", "higher_is_better": False,
+                      "config": {"workload": args.config, "n_majoranas": ham.n, "R": R, "terms": terms,
+                                 "warmup_steps": max(1, args.warmup)},
+                      "status": status, "results": out}), flush=True)
+    return 0 if status == 0 else 1
 
 
 def bench_grow(args) -> int:
