@@ -155,8 +155,13 @@ typedef struct {
   int32_t purify_iters;    /* max Newton-Schulz polar iterations (default 24); */
                            /* not converging sets SGS_ENOCONV                  */
   int32_t streams;         /* independent problems run concurrently on up to  */
-                           /* this many HIP streams, each with its own scratch*/
-                           /* (1..4, default 4)                               */
+                           /* this many worker streams, each with its own     */
+                           /* scratch (1..8, default 4).  A worker uses three */
+                           /* HIP streams (its main stream, the phase chain,  */
+                           /* the inverses of the pairs not involving state   */
+                           /* 0); workers run truly concurrently only with as */
+                           /* many hardware queues (HIP's GPU_MAX_HW_QUEUES,  */
+                           /* default 4, set before the process starts HIP)   */
   int32_t update;          /* SGS_UPD_EULER (default) or SGS_UPD_EXP           */
   double exp_coef;         /* c of SGS_UPD_EXP, 0 < c <= 1e6 (default 1/4:    */
                            /* for a tangent dGamma [[Gamma, dGamma], Gamma] = */

@@ -568,7 +568,8 @@ static int device_lds_max() {
   return v;
 }
 
-constexpr int MAX_WORKERS = 4;  // concurrent streams for independent problems
+constexpr int MAX_WORKERS = 8;  // concurrent worker streams for independent problems
+constexpr int DEFAULT_WORKERS = 4;
 // more nonzeros of A per column than this: Y = Delta A by grouped GEMMs
 // instead of the compressed-column product
 constexpr int DENSE_A_PER_COLUMN = 16;
@@ -1229,7 +1230,7 @@ void sgs_default_options(sgs_options* o) {
   o->g_rel_threshold = 1e-12;
   o->purify_tol = 1e-12;
   o->purify_iters = 24;
-  o->streams = MAX_WORKERS;
+  o->streams = DEFAULT_WORKERS;
   o->update = SGS_UPD_EULER;
   o->exp_coef = 0.25;
   o->tune = nullptr;

@@ -41,7 +41,7 @@ def _ctx(probs, **kw):
     return SGS([h for h, _ in probs], [g for _, g in probs], options=default_options(**kw))
 
 
-@pytest.mark.parametrize("streams", [1, 4])
+@pytest.mark.parametrize("streams", [1, 4, 8])
 def test_batched_steps_match_oracle(streams):
     probs = _problems()
     _say(f"[batched] {len(probs)} problems, streams={streams}, 2 steps")
