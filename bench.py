@@ -66,6 +66,16 @@ def step_flops(n: int, R: int) -> float:
             + force_flops(n, R) + R * 12.0 * n ** 3)
 
 
+def dense_equiv_flops(n: int, R: int) -> float:
+    """The fixed dense-equivalent accounting of the measurement plan: 14.7 n^3
+    per pair-eval (a 2 n^3 factorization, a 2 n^3 real GEMM, an 8 n^3 complex
+    GEMM and an (8/3) n^3 complex Pfaffian) plus 18 n^3 per state (the force
+    sandwich, X_a and about three polar iterations), whatever the kernels
+    actually do."""
+    P = R * (R - 1) // 2
+    return P * (2 + 2 + 8 + 8.0 / 3.0) * n ** 3 + R * 18.0 * n ** 3
+
+
 def golden_step(config: str):
     """The oracle's stored one-step result for this workload, or None."""
     path = os.path.join(ROOT, "tests", "golden", f"{config}_step.json")
@@ -320,7 +330,10 @@ def main(argv=None):
             "inverse": frac(inverse_flops(n, P), stage_ms["inverse"]),
             "pfaffian": frac(pfaffian_flops(n, Q), stage_ms["pfaffian"]),
             "step": frac(step_flops(n, R), ms_step),
+            "step_dense_equivalent": frac(dense_equiv_flops(n, R), ms_step),
             "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS,
+            "note": "step: the method's own operation counts (skew outputs halved); step_dense_equivalent: "
+                    "14.7 n^3 per pair + 18 n^3 per state, the plan's fixed accounting",
         },
         "pair_eval": {"ms_per_call": ms_pe, "pair_evals_per_s": P / (ms_pe / 1e3)},
         "variance": {"ms_per_call": ms_var, "E": float(var[0]), "H2": float(var[1]), "delta_H2": float(var[2])},
