@@ -1166,14 +1166,15 @@ static hipError_t update_stage(sgs_ctx* c, Prob& q, double dtau) {
   if (q.force_seq) {
     // the elementwise terms after the dense products, on the same stream
     HCHK(launch_force(n, R, q.terms, q.coef, q.dG, q.dP, q.dgnorm, fmode, q.force_split, ftile, s));
-    HCHK(launch_force_elem(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, fmode == FORCE_FP32, q.dE, s));
+    HCHK(launch_force_elem(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, force_direct_y(fmode, ftile), q.dE, s));
     tm.end(SGS_STAGE_FORCE, s);
   } else {
     // the elementwise terms on the second stream (idle here: the phase chain
     // joined before the solve), concurrent with the dense products
     HCHK(hipEventRecord(wk.ev_f, s));
     HCHK(hipStreamWaitEvent(wk.s2, wk.ev_f, 0));
-    HCHK(launch_force_elem(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, fmode == FORCE_FP32, q.dE, wk.s2));
+    HCHK(launch_force_elem(n, R, q.terms, q.coef, q.Adense, q.impos, q.M, force_direct_y(fmode, ftile), q.dE,
+                           wk.s2));
     HCHK(hipEventRecord(wk.ev_fe, wk.s2));
     HCHK(launch_force(n, R, q.terms, q.coef, q.dG, q.dP, q.dgnorm, fmode, q.force_split, ftile, s));
     tm.end(SGS_STAGE_FORCE, s);

@@ -17,8 +17,12 @@
 // second buffer on another stream while the matrix cores run (few
 // registers, many waves to hide the loads), and k_force_join adds the two
 // and takes the 1-norm the Euler step needs.  Each part is skew-completed
-// the same way (strict upper triangle mirrored, diagonal tiles
-// antisymmetrized), which is exact for their sum, the skew force.
+// (strict upper triangle of tiles mirrored, diagonal tiles antisymmetrized).
+// That is exact for their sum, the skew force, when both parts use the same
+// tiles, or when each part is skew by itself: Re(c1 Y D) = Re(c1 D F D) is,
+// Re(c1 i Y) is not.  So only the 64 x 64 products, tiled like k_force_elem,
+// carry Re(c1 i Y); with 128 x 128 or 80 x 80 product tiles k_force_elem
+// adds it (direct_y), in float64.
 // The pair (a < b) stores Delta^{ba}; the term for mu = b uses its complex
 // conjugate (sgn = -1 on every imaginary part).
 //
@@ -522,7 +526,8 @@ constexpr size_t force_big_lds_bytes() {
              : (FB_T * (FB_T + 1) * sizeof(double));
 }
 
-template <typename TT, bool IY>
+// (no Re(c1 i Y) fold: its tiles are not those of k_force_elem)
+template <typename TT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_force_big(
     int n, int R, int T, int nsplit, const ForceTerm* __restrict__ terms, const double* __restrict__ coef,
     double* __restrict__ dG, double* __restrict__ dP, unsigned long long* __restrict__ nrm) {
@@ -590,9 +595,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     auto store = [&](int kc, int buf) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        // IY: B = c1 (D + i 1), so the product also carries Re(c1 i Y)
-        const double dr = ds * rd[0][r],
-                     di = sgi * rd[1][r] + (IY && kc + b_k + r == col0 + b_j && col0 + b_j < n ? 1.0 : 0.0);
+        const double dr = ds * rd[0][r], di = sgi * rd[1][r];
         As[2 * buf][a_k + r][a_i] = (TT)ra[0][r];
         As[2 * buf + 1][a_k + r][a_i] = (TT)(sgi * ra[1][r]);
         Bs[2 * buf][b_k + r][b_j] = (TT)(x1 * dr - y1 * di);
@@ -666,10 +669,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 }
 
 hipError_t set_force_lds_limit() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_force_big<double, true>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_force_big<double>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)force_big_lds_bytes<double>());
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_force_big<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  return hipFuncSetAttribute((const void*)k_force_big<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)force_big_lds_bytes<float>());
 }
 
@@ -699,10 +702,10 @@ hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef
     const int T = (n + FB_T - 1) / FB_T;
     const dim3 grid(8 * per_xcd * (T * (T + 1) / 2) * nsplit), block(512);
     if (mode == FORCE_FP64)
-      hipLaunchKernelGGL((k_force_big<double, true>), grid, block, force_big_lds_bytes<double>(), s, n, R, T, nsplit,
+      hipLaunchKernelGGL((k_force_big<double>), grid, block, force_big_lds_bytes<double>(), s, n, R, T, nsplit,
                          terms, coef, dG, dP, nrm);
     else
-      hipLaunchKernelGGL((k_force_big<float, false>), grid, block, force_big_lds_bytes<float>(), s, n, R, T, nsplit,
+      hipLaunchKernelGGL((k_force_big<float>), grid, block, force_big_lds_bytes<float>(), s, n, R, T, nsplit,
                          terms, coef, dG, dP, nrm);
     return hipGetLastError();
   }

@@ -264,9 +264,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
   }
   // after the groups column c sits at (c - U ceil(b / U)) mod B: rotate the
-  // rest of the way
+  // rest of the way to a multiple of B (U ceil(b / U) exceeds B when B is
+  // not a multiple of U, as for B = 6)
+  const int rot = (U * ((b + U - 1) / U)) % B;
 #pragma unroll 1
-  for (int j = U * ((b + U - 1) / U); j < B; ++j) {
+  for (int j = rot == 0 ? B : rot; j < B; ++j) {
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const double t0 = x[r][0];

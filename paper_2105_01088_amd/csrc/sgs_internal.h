@@ -300,11 +300,16 @@ enum : int { FORCE_FP64 = 0, FORCE_FP32 = 1 };
 constexpr int FORCE_SPLIT_MAX = 4;
 hipError_t set_force_lds_limit();  // the 128 x 128 tile kernels' LDS (once per context)
 int force_tile_default(int n, int mode);  // 64 or 128
+// whether k_force_elem adds Re(c1 i Y): every product but the FP64 64 x 64
+// one (whose tiles are k_force_elem's, so the fold into its B operand stays
+// exact under the skew completion)
+inline bool force_direct_y(int mode, int tile) { return mode != FORCE_FP64 || tile == 128; }
 // tile: output tile edge, 64 or 128
 hipError_t launch_force(int n, int R, const ForceTerm* terms, const double* coef, double* dG, double* dP,
                         unsigned long long* nrm, int mode, int nsplit, int tile, hipStream_t s);
-// direct_y = 0: the products carry Re(c1 i Y) (FP64: B = c1 (D + i 1)) and
-// k_force_elem leaves it out
+// direct_y = 0: the products carry Re(c1 i Y) (FP64 64 x 64 tiles: B =
+// c1 (D + i 1)) and k_force_elem leaves it out; any other product adds it
+// here (force_direct_y)
 hipError_t launch_force_elem(int n, int R, const ForceTerm* terms, const double* coef, const double* A,
                              const int* impos, int M, int direct_y, double* dE, hipStream_t s);
 hipError_t launch_force_join(double* dG, const double* dP, const double* dE, int n, int R, int nsplit,

@@ -8,6 +8,7 @@ Run from the repository root:
     python tests/golden/make_golden.py step1204     # tck_L150_R24_J0.3_step.json (minutes)
     python tests/golden/make_golden.py cond800      # adds phase-matrix conditions (minutes)
     python tests/golden/make_golden.py cond1204
+    python tests/golden/make_golden.py big          # big_steps.json: n = 1604, 2500, 4096 (minutes)
 
 Each value records the oracle routine that produced it and the passage of
 Boutin & Bauer (arXiv:2105.01088) it follows.  Inputs come from sgs_inputs
@@ -100,6 +101,37 @@ def one_step(name, seed):
         json.dump(out, f)
 
 
+BIG_CASES = [  # (L, R, eps, seed): n = 4 (L + 1) Majoranas
+    (400, 3, 1.5, 61),    # n = 1604: panel shapes of 1536 < n <= 2048
+    (624, 3, 1.5, 62),    # n = 2500: shapes above 2048
+    (1023, 2, 1.5, 63),   # n = 4096, N = 2048: the largest problem the library takes
+]
+
+
+def big_steps():
+    """One step (unit weights) at the largest sizes, from rotated near-copy
+    states (overlaps of order one, so every amplitude is well defined): E,
+    the tables and sampled entries of the new states."""
+    out = {"source": "oracle.sgs.step (unit weights)", "cite": STEP_CITE, "cases": []}
+    for L, R, eps, seed in BIG_CASES:
+        ham = si.anderson(L, 1.0, 0.5)
+        gam = si.near_copy_states(ham.N, R, eps, seed=seed)
+        t0 = time.time()
+        r = sgs.step(ham, gam, 0.05, mode="unit")
+        tab = r.tables
+        print(f"n = {ham.n}, R = {R}: one step in {time.time() - t0:.0f} s, E = {r.E}, "
+              f"cond(G) = {np.linalg.cond(tab.G):.2e}", flush=True)
+        case = dict(L=L, R=R, eps=eps, seed=seed, n=ham.n, E=float(r.E),
+                    logabs=tab.logabs.tolist(), arg=tab.arg.tolist(),
+                    eps_re=tab.eps.real.tolist(), eps_im=tab.eps.imag.tolist(),
+                    dgamma_max=float(np.abs(r.dgamma).max()))
+        case.update(_samples(r.gammas, seed=seed, count=2048))
+        case["phase_cond"] = phase_conditions(gam)
+        out["cases"].append(case)
+    with open(os.path.join(HERE, "big_steps.json"), "w") as f:
+        json.dump(out, f)
+
+
 def phase_conditions(gam):
     """2-norm condition number of every matrix C_ab (1 <= a < b) whose Pfaffian
     gives the phase of G_ab (Schur-reduced triple product, Sec. II.B):
@@ -140,5 +172,7 @@ if __name__ == "__main__":
         add_phase_conditions("anderson_L199_R32_U1")
     elif what == "cond1204":
         add_phase_conditions("tck_L150_R24_J0.3")
+    elif what == "big":
+        big_steps()
     else:
         raise SystemExit(f"unknown golden: {what}")

@@ -263,3 +263,55 @@ def test_printed_weights_n400_random_states():
         _say(f"  state {mu:2d} |lambda| {abs(ref.lam[mu]):.2e} amp {amp[mu]:.1e} err {err[mu]:.2e} tol {tol[mu]:.2e}")
     assert abs(e - ref.E) < TOL_E * abs(ref.E)
     assert np.all(err < tol)
+
+
+# ------------------------------------------------------------ largest sizes
+
+def _big_cases():
+    path = os.path.join(GOLDEN, "big_steps.json")
+    if not os.path.exists(path):
+        return []
+    with open(path) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _big_cases(), ids=lambda c: f"n{c['n']}_R{c['R']}")
+def test_largest_sizes_one_step(case):
+    """One FP64 step (unit weights) at n = 1604 and 2500 (R = 3) and at the
+    library's largest problem, N = 2048 (n = 4096, R = 2), from rotated
+    near-copy states: the panel shapes above n = 1536 and above 2048, which
+    the benchmark workloads never reach.  Tables at 1e-9 (phase: n cond(C_ab)
+    eps per pair), E at 1e-10 relative, 2048 sampled entries of the new
+    states at 1e-10."""
+    ham = si.anderson(case["L"], 1.0, 0.5)
+    gam = si.near_copy_states(ham.N, case["R"], case["eps"], seed=case["seed"])
+    R, n = gam.shape[0], gam.shape[1]
+    assert n == case["n"]
+    _say(f"[step] largest sizes: n={n} R={R} against the oracle golden")
+    ctx = _ctx(ham, gam, weight=1)
+    la, ar, ep = ctx.pair_eval()
+    la = la.cpu().numpy().reshape(R, R)
+    ar = ar.cpu().numpy().reshape(R, R)
+    ep = ep.cpu().numpy().reshape(R, R, 2)
+    ep = ep[..., 0] + 1j * ep[..., 1]
+    off = ~np.eye(R, dtype=bool)
+    rla = np.array(case["logabs"])
+    reps = np.array(case["eps_re"]) + 1j * np.array(case["eps_im"])
+    e_la = np.abs(la - rla)[off].max() / max(1.0, np.abs(rla).max())
+    e_ep = np.abs(ep - reps).max() / max(1.0, np.abs(reps).max())
+    dph = np.abs(np.exp(1j * ar) - np.exp(1j * np.array(case["arg"])))
+    bound = np.full((R, R), 1e-9)
+    for a, b, k in case["phase_cond"]:
+        bound[a, b] = bound[b, a] = max(1e-9, n * k * EPS)
+    _say(f"  tables: log|G| {e_la:.2e}  phase {dph.max():.2e}  eps {e_ep:.2e}")
+    assert e_la < TOL_TAB and e_ep < TOL_TAB
+    assert np.all(dph <= bound)
+    e = ctx.step(0.05, 1)
+    assert ctx.status() == 0
+    e = e.cpu().item()
+    got, want = _samples(ctx.gammas(0).cpu().numpy(), case)
+    err = np.abs(got - want).max()
+    _say(f"  E err {abs(e - case['E']) / abs(case['E']):.2e}  Gamma sample err {err:.2e}")
+    assert abs(e - case["E"]) < TOL_E * abs(case["E"])
+    assert err < TOL_GAMMA
+    ctx.close()
