@@ -31,11 +31,11 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 
 # HBM bytes per launch of the force products, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE counters on the workload (FETCH_SIZE scaled by 1.99989,
+# WRITE_SIZE counters on the workload (FETCH_SIZE scaled by 1.99992,
 # WRITE_SIZE by 1.0: the factors a 1 GiB device copy reads back), in
 # profiles/force_tck_L150_R24_fp64.md.  Only valid for the kernel and workload
 # they were taken on; any other combination reports null.
-FORCE_TRAFFIC_BYTES = {("tck_L150_R24_J0.3", "fp64", "k_force_big"): 6.6228e10}
+FORCE_TRAFFIC_BYTES = {("tck_L150_R24_J0.3", "fp64", "k_force_big"): 6.6405e10}
 
 
 def force_kernel(n: int, precision: str) -> str:

@@ -256,9 +256,12 @@ def test_fp32_plain_error_bound():
 def test_force_tiles_match_oracle(tile, L, R, seed):
     """Both force tile edges (64 x 64, 128 x 128 with eight waves) on ragged
     sizes n = 132 and 260 (one tile plus a sliver; two plus a sliver),
-    whatever the built-in choice for that n: one step at 1e-10."""
+    whatever the built-in choice for that n: one step at 1e-10.  Rotated
+    near-copy states give overlaps of order one, so the cross terms and the
+    complex coefficients weigh as much as the self terms (with seeded random
+    states they are negligible)."""
     ham = si.anderson(L, 1.2, 0.7)
-    gam = si.random_states(ham.N, R, seed)
+    gam = si.near_copy_states(ham.N, R, 1.5, seed=seed)
     _say(f"[step] force tile {tile}, n={ham.n} R={R}")
     ctx = _ctx(ham, gam, weight=1, tune=[{"n_max": 4096, "force_tile": tile}])
     e = ctx.step(0.05, 1)
