@@ -315,3 +315,27 @@ def test_largest_sizes_one_step(case):
     assert abs(e - case["E"]) < TOL_E * abs(case["E"])
     assert err < TOL_GAMMA
     ctx.close()
+
+
+def test_largest_size_fp32_force():
+    """The FP32 force (128 x 128 FP32 tiles) at n = 1604 on the near-copy
+    states of the FP64 golden: E of the entering states in float64 (1e-10),
+    the new states within 1e-5 dtau max|dGamma| (float rounding over products
+    of depth 2n)."""
+    cases = [c for c in _big_cases() if c["n"] == 1604]
+    if not cases:
+        pytest.skip("big_steps.json not generated")
+    case = cases[0]
+    ham = si.anderson(case["L"], 1.0, 0.5)
+    gam = si.near_copy_states(ham.N, case["R"], case["eps"], seed=case["seed"])
+    _say(f"[step] fp32 force at n={ham.n} R={case['R']} against the FP64 golden")
+    ctx = _ctx(ham, gam, weight=1, precision=1)
+    e = ctx.step(0.05, 1).cpu().item()
+    assert ctx.status() == 0
+    got, want = _samples(ctx.gammas(0).cpu().numpy(), case)
+    err = np.abs(got - want).max()
+    tol = 1e-5 * 0.05 * case["dgamma_max"]
+    _say(f"  E err {abs(e - case['E']) / abs(case['E']):.2e}  Gamma sample err {err:.2e} (tol {tol:.1e})")
+    assert abs(e - case["E"]) < TOL_E * abs(case["E"])
+    assert err < tol
+    ctx.close()

@@ -117,3 +117,14 @@ def test_benchmark_workload_impurity_plus_eight_sites():
     ham, gam, cfg = si.config_problem("anderson_L99_R16")
     _say("[renyi] anderson_L99_R16 nA=36")
     _check(ham, gam, 36, 0, weight=1)
+
+
+@pytest.mark.parametrize("method", [0, 1, 2])
+def test_near_copy_states_nA_48(method):
+    """Rotated near-copy states (overlaps of order one): every cross term of
+    the rank-4 tensor weighs as much as the diagonal ones, through the
+    batched block and split forms at nA = 48."""
+    ham = si.anderson(24, 1.0, 0.5)
+    gam = si.near_copy_states(ham.N, 3, 1.5, seed=15)
+    _say(f"[renyi] near-copy n={ham.n} R=3 nA=48 method={method}")
+    _check(ham, gam, 48, method)
