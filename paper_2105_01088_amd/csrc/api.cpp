@@ -380,7 +380,9 @@ static void pf_carve(PfBatch& b, Arena& ar) {
   const long long mm = (long long)b.m * b.m;
   b.uvstride = 2LL * b.m * 2 * PF_SUPER_MAX;  // planar: re block then im block
   b.uv_im = (long long)b.m * 2 * PF_SUPER_MAX;
-  b.pdstride = 4LL * b.m * PF_SUPER_MAX;  // deferred columns: [row][step][U re, U im, V re, V im]
+  // deferred columns, twice: [row][step][U re, U im, V re, V im], then
+  // step-major (U then V planes of complex pairs [step][row])
+  b.pdstride = 8LL * b.m * PF_SUPER_MAX;
   b.A0 = ar.take<double>(std::max(1LL, 2 * b.B * mm));
   b.A1 = ar.take<double>(std::max(1LL, 2 * b.B * mm));
   b.perm = ar.take<int>(std::max(1LL, (long long)b.B * b.m));

@@ -48,6 +48,12 @@ namespace sgs {
 
 constexpr int GJ_MAX_WAVES = 8;
 
+// Columns per LDS staging pass of a panel of width B: a divisor of B, at most
+// 16 (a wave's 64 x (CB + 1) tile, 8.7 KB at CB = 16).
+__host__ __device__ constexpr int gj_stage_cols(int B) {
+  return B <= 16 ? B : B % 16 == 0 ? 16 : B % 12 == 0 ? 12 : B % 8 == 0 ? 8 : 1;
+}
+
 // Panel kernel.  Thread t owns the physical rows i = t + r nt (r < RPT) and
 // keeps their b panel entries in registers.  The panel is swept column by
 // column with the exchange (Gauss-Jordan pivot) operation: for the pivot row
@@ -75,9 +81,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                                                   int* __restrict__ pivall, int* __restrict__ srcall,
                                                   double* __restrict__ logdet,
                                                   int* __restrict__ status) {
-  constexpr int CB = B < 16 ? B : 16;  // columns per LDS staging pass
-  constexpr int RPI = 64 / CB;          // rows per coalesced load / store
-  constexpr bool STG = RPT == 1;        // staged loads / stores (register budget)
+  constexpr int CB = gj_stage_cols(B);  // columns per LDS staging pass
+  static_assert(B % CB == 0, "staging passes must tile the panel");
   // dynamic LDS: tag (n ints: 1 if the row is a pivot of an earlier panel),
   // then per wave a 64 x (CB + 1) staging tile, then per wave 64 ints
   extern __shared__ int tag[];
@@ -95,35 +100,31 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int kl = k - bc0;  // the panel's position in the super-panel
 
   for (int i = tid; i < n; i += nt) tag[i] = 0;
-  // the panel into registers, through the wave's LDS tile: coalesced loads
-  // of RPI rows x CB columns, then every lane takes its row
+  // the panel into registers, through the wave's LDS tile: element e of a
+  // 64 x CB chunk (row e / CB, column e % CB) goes to lane e % 64 of pass
+  // e / 64, so a load instruction reads whole row segments; then every lane
+  // takes its row
   double* __restrict__ stg = (double*)(tag + ((n + 3) & ~3)) + w * 64 * (CB + 1);
   int* __restrict__ spos = (int*)((double*)(tag + ((n + 3) & ~3)) + nw * 64 * (CB + 1)) + w * 64;
   double x[RPT][B];
-  if (STG) {
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int rbase = r * nt + w * 64;
+  for (int r = 0; r < RPT; ++r) {
+    const int rbase = r * nt + w * 64;
 #pragma unroll
-      for (int h = 0; h < B / CB; ++h) {
+    for (int h = 0; h < B / CB; ++h) {
 #pragma unroll
-        for (int s = 0; s < CB; ++s) {
-          const int rr = s * RPI + lane / CB, cc = lane % CB;
-          const int i = rbase + rr, c = h * CB + cc;
-          stg[rr * (CB + 1) + cc] = (i < n && c < b) ? M[(long long)i * n + k + c] : 0.0;
-        }
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int cc = 0; cc < CB; ++cc) x[r][h * CB + cc] = stg[lane * (CB + 1) + cc];
-        __builtin_amdgcn_wave_barrier();
+      for (int s = 0; s < CB; ++s) {
+        const int e = s * 64 + lane, rr = e / CB, cc = e % CB;
+        const int i = rbase + rr, c = h * CB + cc;
+        stg[rr * (CB + 1) + cc] = (i < n && c < b) ? M[(long long)i * n + k + c] : 0.0;
       }
-    }
-  } else {
+      __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int i = tid + r * nt;
-#pragma unroll
-      for (int c = 0; c < B; ++c) x[r][c] = (i < n && c < b) ? M[(long long)i * n + k + c] : 0.0;
+      for (int cc = 0; cc < CB; ++cc) x[r][h * CB + cc] = stg[lane * (CB + 1) + cc];
+      __builtin_amdgcn_wave_barrier();
+      // (no global load of a later pass is hoisted above this one: their
+      // registers would be live at once)
+      __asm__ volatile("" ::: "memory");
     }
   }
   __syncthreads();
@@ -283,20 +284,25 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
   __syncthreads();  // pivl complete
   // panel outputs (pivot rows M[i, J] = D_l, E_i = e_l - D_l; others
-  // M[i, J] = -E_i), through the wave's LDS tile as coalesced row segments
-  if (STG) {
+  // M[i, J] = -E_i), through the wave's LDS tile as row segments (the map of
+  // the loads).  The lane index is passed through an empty asm statement so
+  // that the addresses are formed here, not kept live across the column loop
+  // from the loads (a register budget that otherwise spills).
+  {
+    int ln = lane;
+    __asm__ volatile("" : "+v"(ln));
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const int rbase = r * nt + w * 64;
-      spos[lane] = pos[r];
+      spos[ln] = pos[r];
 #pragma unroll
       for (int h = 0; h < B / CB; ++h) {
 #pragma unroll
-        for (int cc = 0; cc < CB; ++cc) stg[lane * (CB + 1) + cc] = x[r][h * CB + cc];
+        for (int cc = 0; cc < CB; ++cc) stg[ln * (CB + 1) + cc] = x[r][h * CB + cc];
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int s = 0; s < CB; ++s) {
-          const int rr = s * RPI + lane / CB, cc = lane % CB;
+          const int e = s * 64 + ln, rr = e / CB, cc = e % CB;
           const int i = rbase + rr, c = h * CB + cc;
           if (i < n && c < b) {
             const double v = stg[rr * (CB + 1) + cc];
@@ -306,21 +312,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           }
         }
         __builtin_amdgcn_wave_barrier();
-      }
-    }
-  } else {
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int i = tid + r * nt;
-      if (i < n) {
-#pragma unroll
-        for (int c = 0; c < B; ++c) {
-          if (c < b) {
-            const double v = x[r][c];
-            M[(long long)i * n + k + c] = pos[r] >= 0 ? v : -v;
-            E[(long long)i * eld + kl + c] = pos[r] >= 0 ? (c == pos[r] ? 1.0 : 0.0) - v : v;
-          }
-        }
+        __asm__ volatile("" ::: "memory");
       }
     }
   }
@@ -339,17 +331,35 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     es[e] = E[(long long)pivl[l] * eld + j];
   }
   __syncthreads();
-  const int sw = bc1 - bc0;
-  for (int e = tid; e < b * sw; e += nt) {
-    const int l = e / sw, lc = e - l * sw, c = bc0 + lc;
-    double v = 0.0;
-    if (c < k || c >= k + b) {
-      v = M[(long long)pivl[l] * n + c];
-      const int js = c < k ? (lc / nbp + 1) * nbp : 0;
-      const double* __restrict__ el = es + l * kd;
-      for (int j = js; j < kd; ++j) v = fma(-el[j], Br[(long long)j * brld + lc], v);
+  // (BU items per thread and pass, their loads issued together: one
+  // dependent load after another cost more than the rest of the panel)
+  const int sw = bc1 - bc0, tot = b * sw;
+  constexpr int BU = 8;
+  for (int e0 = tid; e0 < tot; e0 += BU * nt) {
+    double v[BU];
+#pragma unroll
+    for (int u = 0; u < BU; ++u) {
+      const int e = e0 + u * nt;
+      v[u] = 0.0;
+      if (e < tot) {
+        const int l = e / sw, lc = e - l * sw, c = bc0 + lc;
+        if (c < k || c >= k + b) v[u] = M[(long long)pivl[l] * n + c];
+      }
     }
-    Br[(long long)(kl + l) * brld + lc] = v;
+#pragma unroll
+    for (int u = 0; u < BU; ++u) {
+      const int e = e0 + u * nt;
+      if (e < tot) {
+        const int l = e / sw, lc = e - l * sw, c = bc0 + lc;
+        double y = v[u];
+        if (c < k || c >= k + b) {
+          const int js = c < k ? (lc / nbp + 1) * nbp : 0;
+          const double* __restrict__ el = es + l * kd;
+          for (int j = js; j < kd; ++j) y = fma(-el[j], Br[(long long)j * brld + lc], y);
+        }
+        Br[(long long)(kl + l) * brld + lc] = y;
+      }
+    }
   }
   if (tid < b) piv[k + tid] = pivl[tid];
   // after the last panel: src = piv^-1 for the unscramble
@@ -427,7 +437,7 @@ GjPanelShape gj_panel_shape(int n) {
 // rows' E entries (kl = the panel's position in its super-panel)
 size_t gj_panel_lds_bytes(int n, int kl, int b) {
   const GjPanelShape sh = gj_panel_shape(n);
-  const int cb = sh.B < 16 ? sh.B : 16;
+  const int cb = gj_stage_cols(sh.B);
   const size_t nw = (size_t)sh.nt / 64;
   return sizeof(int) * (size_t)((n + 3) & ~3) + nw * 64 * (cb + 1) * sizeof(double) + nw * 64 * sizeof(int) +
          (size_t)b * kl * sizeof(double) + 64;

@@ -25,9 +25,13 @@ namespace sgs {
 constexpr int PF_MAX_WAVES = 8;
 
 // Deferred columns of one super-panel: for every earlier step t < kd of the
-// super-panel, U_t and V_t of every stored row, row-major: entry
-// [(row * PF_DEFER + t) * 4 + {U re, U im, V re, V im}], so a row's entries
-// are contiguous (16-byte loads per lane, uniform loads for a gathered row).
+// super-panel, U_t and V_t of every stored row, kept twice per matrix:
+//  * row-major, entry [(row * PF_DEFER + t) * 4 + {U re, U im, V re, V im}]:
+//    a gathered row's entries are contiguous (uniform loads);
+//  * step-major (after 4 m0 PF_DEFER doubles), complex U_t[row] at pair
+//    t m0 + row and V_t[row] at pair (PF_DEFER + t) m0 + row: the lanes' own
+//    rows at one step are consecutive, so a load instruction reads one
+//    contiguous segment instead of a cache line per lane.
 // The current matrix of the super-panel is
 //   B[i][j] = A[i][j] + sum_t (U_t[i] V_t[j] - V_t[i] U_t[j])
 // over those steps and the panel's own (held in registers); a gather of row g
@@ -89,6 +93,11 @@ void k_pf_panel(const double* __restrict__ Aall, long long astride, long long pl
   const dpair* __restrict__ Db = (const dpair*)(Dall + (long long)mat * dstride);
   dpair* __restrict__ Dw = (dpair*)(Dwall + (long long)mat * dstride);
   constexpr int RS = 2 * PF_DEFER;  // row stride in pairs
+  const long long tm = 2LL * m0 * PF_DEFER;  // the step-major copy, in pairs
+  const dpair* __restrict__ Tu = Db + tm;
+  const dpair* __restrict__ Tv = Tu + (long long)PF_DEFER * m0;
+  dpair* __restrict__ Twu = Dw + tm;
+  dpair* __restrict__ Twv = Twu + (long long)PF_DEFER * m0;
 
   for (int l = p0 + tid; l < m; l += nt) perm[l] = first ? l : gperm[l];
   for (int e = tid; e < 4 * NBH; e += nt) bc[e] = 0.0;  // row p0's U, V before the first step
@@ -112,8 +121,8 @@ void k_pf_panel(const double* __restrict__ Aall, long long astride, long long pl
       const dpair u2 = B2[2 * t], v2 = B2[2 * t + 1];
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
-        const dpair* __restrict__ own = Db + (long long)pl[r] * RS;
-        const dpair ou = own[2 * t], ov = own[2 * t + 1];
+        const long long o = (long long)t * m0 + pl[r];
+        const dpair ou = Tu[o], ov = Tv[o];
         d1r[r] = fma(ou.x, v1.x, d1r[r]); d1r[r] = fma(-ou.y, v1.y, d1r[r]);
         d1r[r] = fma(-ov.x, u1.x, d1r[r]); d1r[r] = fma(ov.y, u1.y, d1r[r]);
         d1i[r] = fma(ou.x, v1.y, d1i[r]); d1i[r] = fma(ou.y, v1.x, d1i[r]);
@@ -348,8 +357,11 @@ void k_pf_panel(const double* __restrict__ Aall, long long astride, long long pl
 #pragma unroll
         for (int t = 0; t < NBH; ++t) {
           if (t < ns) {
-            own[2 * (kd + t)] = dpair{ur[r][t], ui[r][t]};
-            own[2 * (kd + t) + 1] = dpair{vr[r][t], vi[r][t]};
+            const dpair u = dpair{ur[r][t], ui[r][t]}, v = dpair{vr[r][t], vi[r][t]};
+            own[2 * (kd + t)] = u;
+            own[2 * (kd + t) + 1] = v;
+            Twu[(long long)(kd + t) * m0 + pl[r]] = u;
+            Twv[(long long)(kd + t) * m0 + pl[r]] = v;
           }
         }
         gperm[l] = pl[r];
@@ -370,9 +382,9 @@ void k_pf_panel(const double* __restrict__ Aall, long long astride, long long pl
       const int l = p0 + tid + r * nt;
       if (l >= pe && l < m) {
         const int i = l - pe;
-        const dpair* __restrict__ own = Db + (long long)pl[r] * RS;
         for (int t = 0; t < kd; ++t) {
-          const dpair xu = own[2 * t], xv = own[2 * t + 1];
+          const long long o = (long long)t * m0 + pl[r];
+          const dpair xu = Tu[o], xv = Tv[o];
           const long long ou = (long long)t * mp + i, ov = (long long)(kall + t) * mp + i;
           Lr[ou] = xu.x; Li[ou] = xu.y;
           Lr[ov] = xv.x; Li[ov] = xv.y;
@@ -433,7 +445,7 @@ hipError_t launch_pf_panel(const double* A, long long astride, long long plane, 
   const PfPanelShape sh = pf_panel_shape(m0 - p0);
   if (p0 < 0 || (p0 & 1) || ns < 1 || ns > sh.nbh || p0 + 2 * ns > m0 || kd < 0 || kd + ns > kall ||
       kall > PF_DEFER || (last && kd + ns != kall) || (long long)sh.nt * sh.rpt < m0 - p0 || m0 > 0xffff ||
-      (long long)m0 * 4 * PF_DEFER > dstride)
+      (long long)m0 * 8 * PF_DEFER > dstride)
     return hipErrorInvalidValue;
   const size_t lds = pf_panel_lds_bytes(m0, sh.nbh);
 #define PF_LAUNCH(NB, RP)                                                                                        \
