@@ -122,7 +122,10 @@ def default_options(tune=None, **kw) -> sgs_options:
     autotuner writes."""
     o = sgs_options()
     load_library().sgs_default_options(ctypes.byref(o))
+    names = {f[0] for f in sgs_options._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"sgs_options has no field {k!r}")
         setattr(o, k, v)
     if tune is not None:
         if isinstance(tune, str):

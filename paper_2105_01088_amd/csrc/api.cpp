@@ -291,16 +291,19 @@ struct sgs_ctx {
     if (ren) (void)hipFree(ren);
   }
   // fork: every worker stream waits for the work enqueued so far on s
+  // (workers run on streams of their own, so that the caller's stream, which
+  // may be the null stream, holds only these events while they work)
   hipError_t fork() {
-    if (wk.size() < 2) return hipSuccess;
     hipError_t e = hipEventRecord(ev_start, s);
-    for (size_t w = 1; w < wk.size() && e == hipSuccess; ++w) e = hipStreamWaitEvent(wk[w].s, ev_start, 0);
+    for (size_t w = 0; w < wk.size() && e == hipSuccess; ++w)
+      if (wk[w].s != s) e = hipStreamWaitEvent(wk[w].s, ev_start, 0);
     return e;
   }
   // join: s waits for every worker stream
   hipError_t join() {
     hipError_t e = hipSuccess;
-    for (size_t w = 1; w < wk.size() && e == hipSuccess; ++w) {
+    for (size_t w = 0; w < wk.size() && e == hipSuccess; ++w) {
+      if (wk[w].s == s) continue;
       e = hipEventRecord(wk[w].ev_done, wk[w].s);
       if (e == hipSuccess) e = hipStreamWaitEvent(s, wk[w].ev_done, 0);
     }
@@ -1325,18 +1328,15 @@ int sgs_init(sgs_ctx** out, const sgs_problem* probs, int32_t nprob, double* gam
   }
   for (int p = 0; p < nprob; ++p)
     if ((rc = build_tables(c->pr[p], probs[p]))) { delete c; return rc; }
-  // worker streams (default priority; worker 0 is the context's stream), each
-  // with a second stream for its phase chain, and the fork / join events
+  // worker streams (default priority, non-blocking, forked from and joined to
+  // the context's stream), each with a second stream for its phase chain and
+  // a third for the other pairs' inverses, and the fork / join events
   c->wk.assign(nworkers, Worker());
   if (hipEventCreateWithFlags(&c->ev_start, hipEventDisableTiming) != hipSuccess) { delete c; return SGS_EHIP; }
   for (int w = 0; w < nworkers; ++w) {
     Worker& k = c->wk[w];
-    if (w == 0) {
-      k.s = c->s;
-    } else {
-      if (hipStreamCreateWithFlags(&k.s, hipStreamNonBlocking) != hipSuccess) { delete c; return SGS_EHIP; }
-      k.own_s = true;
-    }
+    if (hipStreamCreateWithFlags(&k.s, hipStreamNonBlocking) != hipSuccess) { delete c; return SGS_EHIP; }
+    k.own_s = true;
     if (hipStreamCreateWithFlags(&k.s2, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&k.s3, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&k.ev_gj, hipEventDisableTiming) != hipSuccess ||
@@ -1421,9 +1421,9 @@ static int step_graph(sgs_ctx* c, double dtau, int nsteps, double* energies) {
     if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
     if (!c->gs && hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking) != hipSuccess) return SGS_EHIP;
     hipGraph_t g = nullptr;
-    // the private stream stands in for the context's stream (worker 0's)
+    // the private stream stands in for the context's stream and worker 0's
     // while the step is captured; the graph is launched on the context's
-    hipStream_t s0 = c->s;
+    hipStream_t s0 = c->s, w0 = c->wk[0].s;
     c->s = c->gs;
     c->wk[0].s = c->gs;
     hipError_t e = hipStreamBeginCapture(c->gs, hipStreamCaptureModeThreadLocal);
@@ -1436,7 +1436,7 @@ static int step_graph(sgs_ctx* c, double dtau, int nsteps, double* energies) {
     }
     const hipError_t e2 = began ? hipStreamEndCapture(c->gs, &g) : e;
     c->s = s0;
-    c->wk[0].s = s0;
+    c->wk[0].s = w0;
     if (e != hipSuccess || e2 != hipSuccess || !g) {
       if (g) (void)hipGraphDestroy(g);
       return SGS_EHIP;

@@ -40,6 +40,13 @@ def test_default_options():
     assert o.update == 0 and o.exp_coef == 0.25  # Euler + purification; App. A coefficient read as 1/4
 
 
+def test_default_options_rejects_unknown_fields():
+    """A misspelt option must not be dropped silently by the ctypes mirror."""
+    from paper_2105_01088_amd import default_options
+    with pytest.raises(TypeError):
+        default_options(stream=2)
+
+
 def _ws(ham, R, **opt):
     from paper_2105_01088_amd._lib import _HostProblem, default_options, load_library, sgs_problem
     lib = load_library()
