@@ -68,6 +68,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2105_01088_amd.build`")
+    # torch first: it ships its own HIP runtime, and libsgs.so then binds to
+    # that one.  Loaded the other way round, the process holds two runtimes
+    # and torch finds no GPU.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     lib.sgs_default_options.argtypes = [POINTER(sgs_options)]
     lib.sgs_default_options.restype = None

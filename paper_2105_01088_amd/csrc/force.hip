@@ -517,7 +517,10 @@ __global__ __launch_bounds__(256) void k_force_join(double* __restrict__ dG, con
 // term split and skew write-out as in k_force; diagonal tiles are made
 // exactly skew through LDS.
 constexpr int FB_T = 128;            // tile edge
-constexpr int FB_LP = FB_T + 4;      // LDS pitch (elements)
+// LDS pitch (elements), 1 mod 4: a 16-lane group stores 4 slab rows 4 apart
+// (4 columns each), which then fall on disjoint banks; a pitch of 132 put
+// them on the same ones (4-way conflicts on every A-operand store).
+constexpr int FB_LP = FB_T + 1;
 
 template <typename TT>
 constexpr size_t force_big_lds_bytes() {

@@ -45,3 +45,17 @@ def energy_tol(ref, base=1e-10):
     R = G.shape[0]
     lam2 = np.linalg.norm(ref.lam) ** 2
     return base + R * EPS * lam2 * (np.linalg.norm(h, 2) + abs(ref.E) * np.linalg.norm(G, 2)) / abs(ref.E)
+
+
+def phase_tol(g0, ga_, gb, base=1e-9, factor=16.0):
+    """Tolerance on exp(i arg) of a Gram-matrix entry computed through the
+    Schur-reduced triple product (Sec. II.B): its phase is that of Pf(C_ab),
+    C_ab = i (G_b + G_0) - i X_a.  To first order a perturbation changes
+    ln Pf(C) by tr(C^-1 dC) / 2, at most kappa(C) / 2 times the relative
+    perturbation of C; a GPU C_ab carries a few ulps per entry (from the
+    products that form X_a).  factor covers that count with margin:
+    measured errors at n = 800 and 1204 stay 3-15 times below
+    factor kappa(C) eps on both Gauss-Jordan variants."""
+    from oracle import gaussian as ga
+    s = np.linalg.svd(ga.schur_matrix(g0, ga_, gb), compute_uv=False)
+    return max(base, factor * (s[0] / s[-1]) * EPS)

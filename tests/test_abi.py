@@ -32,6 +32,19 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_one_hip_runtime_per_process():
+    """Loading the library must not bring in a second HIP runtime beside
+    torch's (two runtimes in one process leave torch without a GPU)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r); from paper_2105_01088_amd._lib import load_library; "
+            "load_library(); import torch; "
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
+
+
 def test_default_options():
     from paper_2105_01088_amd import default_options, SGS_FP64, SGS_W_PRINTED
     o = default_options()

@@ -22,7 +22,7 @@ import pytest
 
 import sgs_inputs as si
 from oracle import sgs as osgs
-from parity_tol import printed_tol
+from parity_tol import phase_tol, printed_tol
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -196,7 +196,10 @@ def _sampled_tables(name, pairs, phase_pairs):
     g0 = gam[0]
     for a, b in phase_pairs:
         _, ph = ga.triple_product_schur(g0, gam[a], gam[b])
-        assert abs(np.exp(1j * ar[a, b]) - ph) < TOL_TAB
+        tol = phase_tol(g0, gam[a], gam[b])
+        err = abs(np.exp(1j * ar[a, b]) - ph)
+        _say(f"  phase ({a}, {b}): error {err:.3g}, tolerance {tol:.3g}")
+        assert err < tol
         assert abs(ar[b, a] + ar[a, b]) < 1e-15
     for a in range(R):
         assert ar[0, a] == 0.0
