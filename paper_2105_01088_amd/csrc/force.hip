@@ -517,15 +517,30 @@ __global__ __launch_bounds__(256) void k_force_join(double* __restrict__ dG, con
 // term split and skew write-out as in k_force; diagonal tiles are made
 // exactly skew through LDS.
 constexpr int FB_T = 128;            // tile edge
-// LDS pitch (elements), 1 mod 4: a 16-lane group stores 4 slab rows 4 apart
-// (4 columns each), which then fall on disjoint banks; a pitch of 132 put
-// them on the same ones (4-way conflicts on every A-operand store).
-constexpr int FB_LP = FB_T + 1;
+// LDS layout of the slabs: element (k, i) at row k, column i ^ swz(k), rows
+// LP elements apart.  A-operand stores put 4 slab rows 4 apart in one pass
+// (4 columns each for float64, 8 for float32); reads put one row (float64)
+// or two consecutive rows (float32) in a pass.
+//  * float64, 16 lanes a pass: a pitch of 1 mod 4 puts the store rows on
+//    disjoint banks (132 made every A store a 4-way conflict);
+//  * float32, 32 lanes a pass: no pitch serves both patterns, so the column
+//    is swizzled by the row: bit 4 by its parity (two consecutive rows on
+//    disjoint halves) and bits 3-4 by row / 4 (the 4 store rows on distinct
+//    groups of 8).
+template <typename TT> struct FbLds;
+template <> struct FbLds<double> {
+  static constexpr int LP = FB_T + 1;
+  static __device__ __forceinline__ int swz(int) { return 0; }
+};
+template <> struct FbLds<float> {
+  static constexpr int LP = FB_T;
+  static __device__ __forceinline__ int swz(int k) { return ((k & 1) << 4) ^ (((k >> 2) & 3) << 3); }
+};
 
 template <typename TT>
 constexpr size_t force_big_lds_bytes() {
-  return (2 * 2 * 2 * FTK * FB_LP * sizeof(TT)) > (FB_T * (FB_T + 1) * sizeof(double))
-             ? (2 * 2 * 2 * FTK * FB_LP * sizeof(TT))
+  return (2 * 2 * 2 * FTK * FbLds<TT>::LP * sizeof(TT)) > (FB_T * (FB_T + 1) * sizeof(double))
+             ? (2 * 2 * 2 * FTK * FbLds<TT>::LP * sizeof(TT))
              : (FB_T * (FB_T + 1) * sizeof(double));
 }
 
@@ -536,7 +551,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     double* __restrict__ dG, double* __restrict__ dP, unsigned long long* __restrict__ nrm) {
   typedef typename Vec4<TT>::type V4;
   extern __shared__ __attribute__((aligned(16))) char lds_big[];
-  typedef TT Slab[FTK][FB_LP];
+  typedef TT Slab[FTK][FbLds<TT>::LP];
   Slab* As = (Slab*)lds_big;      // As[buf * 2 + part]
   Slab* Bs = (Slab*)lds_big + 4;  // Bs[buf * 2 + part]
   double (*Tt)[FB_T + 1] = (double (*)[FB_T + 1])lds_big;
@@ -599,10 +614,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const double dr = ds * rd[0][r], di = sgi * rd[1][r];
-        As[2 * buf][a_k + r][a_i] = (TT)ra[0][r];
-        As[2 * buf + 1][a_k + r][a_i] = (TT)(sgi * ra[1][r]);
-        Bs[2 * buf][b_k + r][b_j] = (TT)(x1 * dr - y1 * di);
-        Bs[2 * buf + 1][b_k + r][b_j] = (TT)(-(x1 * di + y1 * dr));
+        const int ai = a_i ^ FbLds<TT>::swz(a_k + r), bj = b_j ^ FbLds<TT>::swz(b_k + r);
+        As[2 * buf][a_k + r][ai] = (TT)ra[0][r];
+        As[2 * buf + 1][a_k + r][ai] = (TT)(sgi * ra[1][r]);
+        Bs[2 * buf][b_k + r][bj] = (TT)(x1 * dr - y1 * di);
+        Bs[2 * buf + 1][b_k + r][bj] = (TT)(-(x1 * di + y1 * dr));
       }
     };
     __syncthreads();  // the previous term's last slab has been read
@@ -620,9 +636,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
 #pragma unroll
-          for (int q = 0; q < 2; ++q) ah[u][q] = As[2 * buf + u][kr][wm * 32 + q * 16 + (lane & 15)];
+          for (int q = 0; q < 2; ++q) ah[u][q] = As[2 * buf + u][kr][(wm * 32 + q * 16 + (lane & 15)) ^ FbLds<TT>::swz(kr)];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) bh[u][q] = Bs[2 * buf + u][kr][wn * 64 + q * 16 + (lane & 15)];
+          for (int q = 0; q < 4; ++q) bh[u][q] = Bs[2 * buf + u][kr][(wn * 64 + q * 16 + (lane & 15)) ^ FbLds<TT>::swz(kr)];
         }
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
