@@ -53,3 +53,30 @@ def test_worker_streams_and_graph_give_identical_results():
     assert np.array_equal(e1, e3) and np.array_equal(e1, eg)
     for a, b, c in zip(g1, g3, gg):
         assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_step_follows_work_on_the_callers_stream():
+    """Work the caller enqueues on its own stream before sgs_step, here new
+    covariance matrices written into the context's buffer behind a long
+    matrix product, is seen by the step: the workers, which run on streams
+    of their own, are forked from the caller's stream."""
+    from paper_2105_01088_amd import SGS, default_options
+    ham = si.anderson(40, 1.2, 0.5)
+    gam_a = si.random_states(ham.N, 5, 41)
+    gam_b = si.random_states(ham.N, 5, 42)
+    _say("[determinism] caller stream: new states written on it, then 2 steps")
+    e_ref, g_ref = _run([ham], [gam_b], 2, weight=1)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx = SGS([ham], [gam_a], options=default_options(weight=1), stream=s)
+        src = torch.as_tensor(gam_b, dtype=torch.float64, device="cuda:0")
+        big = torch.full((2048, 2048), 1e-4, dtype=torch.float64, device="cuda:0")
+        for _ in range(6):
+            big = big @ big
+        ctx.gammas(0).copy_(src + 0.0 * big[0, 0])
+        e = ctx.step(0.05, 2)
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    assert np.array_equal(e.cpu().numpy(), e_ref)
+    assert np.array_equal(ctx.gammas(0).cpu().numpy(), g_ref[0])
+    ctx.close()
