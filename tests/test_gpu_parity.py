@@ -276,6 +276,40 @@ def test_force_tiles_match_oracle(tile, L, R, seed):
     ctx.close()
 
 
+@pytest.mark.parametrize("row", [
+    {"gj_super": 32}, {"gj_super": 96}, {"gj_super": 256},
+    {"gj_first": 1}, {"gj_first": 2},
+    {"pf_super": 1}, {"pf_super": 8}, {"pf_super": 24}, {"pf_super": 32},
+    {"force_split": 1}, {"force_split": 3}, {"force_elem": 2},
+    {"gj_super": 64, "gj_defer": 3, "pf_super": 24, "force_split": 2, "force_elem": 2},
+])
+def test_tuning_choices_match_oracle(row):
+    """Every scheduling and blocking choice a tuning row can make (the
+    autotuner may pick any of them) leaves the results those of the oracle:
+    Gauss-Jordan super-panels of one panel up to 256 columns, the order of
+    the two inverse batches, Pfaffian super-panels of 1 to 32 steps (ragged
+    against the 16-step register panels), the force's term split and the
+    elementwise terms on either stream; n = 260 (two panels plus a sliver),
+    rotated near-copy states.  Pair tables at 1e-9, one step at 1e-10."""
+    ham = si.anderson(64, 1.1, 0.6)
+    gam = si.near_copy_states(ham.N, 4, 1.5, seed=21)
+    _say(f"[step] tuning {row}, n={ham.n} R=4")
+    ctx = _ctx(ham, gam, weight=1, tune=[dict(n_max=4096, **row)])
+    la, ar, ep = _tables(ctx)
+    tab = osgs.pair_tables(ham, gam)
+    off = ~np.eye(4, dtype=bool)
+    assert np.abs(la - tab.logabs)[off].max() < TOL_TAB * max(1.0, np.abs(tab.logabs).max())
+    assert np.abs(np.exp(1j * ar) - np.exp(1j * tab.arg))[off].max() < TOL_TAB
+    assert np.abs(ep - tab.eps).max() < TOL_TAB * max(1.0, np.abs(tab.eps).max())
+    e = ctx.step(0.05, 1)
+    assert ctx.status() == 0
+    g_new = ctx.gammas(0).cpu().numpy()
+    ref = osgs.step(ham, gam, 0.05, mode="unit")
+    assert abs(e.cpu().item() - ref.E) < TOL_E * abs(ref.E)
+    assert np.abs(g_new - ref.gammas).max() < TOL_GAMMA
+    ctx.close()
+
+
 @pytest.mark.parametrize("defer", [1, 2, 3])
 @pytest.mark.parametrize("L,R,seed", [(32, 5, 5), (64, 4, 6), (99, 5, 7)])
 def test_gj_deferral_matches_oracle(defer, L, R, seed):
