@@ -621,40 +621,52 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         Bs[2 * buf + 1][b_k + r][bj] = (TT)(-(x1 * di + y1 * dr));
       }
     };
-    __syncthreads();  // the previous term's last slab has been read
-    load(0);
-    store(0, 0);
-    __syncthreads();
-    int buf = 0;
-    for (int kc = 0; kc < n; kc += FTK) {
-      const bool more = kc + FTK < n;
-      if (more) load(kc + FTK);
-#pragma unroll
-      for (int kk = 0; kk < FTK / 4; ++kk) {
-        const int kr = kk * 4 + (lane >> 4);
-        TT ah[2][2], bh[2][4];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-#pragma unroll
-          for (int q = 0; q < 2; ++q) ah[u][q] = As[2 * buf + u][kr][(wm * 32 + q * 16 + (lane & 15)) ^ FbLds<TT>::swz(kr)];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) bh[u][q] = Bs[2 * buf + u][kr][(wn * 64 + q * 16 + (lane & 15)) ^ FbLds<TT>::swz(kr)];
-        }
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-          for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma_t(ah[0][bi], bh[0][bj], acc[bi][bj]);
-        if (im) {
-#pragma unroll
-          for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma_t(ah[1][bi], bh[1][bj], acc[bi][bj]);
-        }
-      }
-      if (more) store(kc + FTK, buf ^ 1);
+    // the slab loop, compiled once for complex and once for real terms (no
+    // branch between the matrix instructions); the operand fragments of
+    // k-step kk + 1 are read from LDS while the matrix cores work on kk
+    auto slabs = [&](auto im_tag) {
+      constexpr bool IM = decltype(im_tag)::value;
+      constexpr int NU = IM ? 2 : 1;
+      __syncthreads();  // the previous term's last slab has been read
+      load(0);
+      store(0, 0);
       __syncthreads();
-      buf ^= 1;
-    }
+      int buf = 0;
+      for (int kc = 0; kc < n; kc += FTK) {
+        const bool more = kc + FTK < n;
+        if (more) load(kc + FTK);
+        TT ah[2][2][2], bh[2][2][4];  // [fragment buffer][re / im][q]
+        auto frag = [&](int kk, int fb) {
+          const int kr = kk * 4 + (lane >> 4);
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+              ah[fb][u][q] = As[2 * buf + u][kr][(wm * 32 + q * 16 + (lane & 15)) ^ FbLds<TT>::swz(kr)];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              bh[fb][u][q] = Bs[2 * buf + u][kr][(wn * 64 + q * 16 + (lane & 15)) ^ FbLds<TT>::swz(kr)];
+          }
+        };
+        frag(0, 0);
+#pragma unroll
+        for (int kk = 0; kk < FTK / 4; ++kk) {
+          const int cur = kk & 1;
+          if (kk + 1 < FTK / 4) frag(kk + 1, cur ^ 1);
+#pragma unroll
+          for (int u = 0; u < NU; ++u)
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+              for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma_t(ah[cur][u][bi], bh[cur][u][bj], acc[bi][bj]);
+        }
+        if (more) store(kc + FTK, buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+      }
+    };
+    if (im) slabs(std::true_type{});
+    else slabs(std::false_type{});
   }
 
   // ---- total, skew write-out ----
