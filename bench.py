@@ -35,7 +35,7 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 # WRITE_SIZE by 1.0: the factors a 1 GiB device copy reads back), in
 # profiles/force_tck_L150_R24_fp64.md.  Only valid for the kernel and workload
 # they were taken on; any other combination reports null.
-FORCE_TRAFFIC_BYTES = {("tck_L150_R24_J0.3", "fp64", "k_force_big"): 6.6399e10}
+FORCE_TRAFFIC_BYTES = {("tck_L150_R24_J0.3", "fp64", "k_force_big"): 6.6751e10}
 
 
 def force_kernel(n: int, precision: str) -> str:
