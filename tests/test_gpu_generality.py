@@ -73,6 +73,31 @@ def test_dense_hamiltonian_steps(weight):
     _step_case(ham, gam, weight, 2)
 
 
+def test_sparse_hamiltonian_with_dense_columns_steps():
+    """A sparse A (the compressed-column path) with a few dense columns: 16
+    impurity-like Majoranas coupled to 130 others each, on top of the
+    n = 400 Anderson chain, so that column lengths range from 2 to over 130
+    within one block of 256 columns."""
+    base = si.anderson(99, 1.0, 0.5)
+    A = base.A.copy()
+    rng = np.random.default_rng(17)
+    n = base.n
+    for c in range(10, 26):
+        others = rng.choice(np.setdiff1d(np.arange(n), np.arange(10, 26)), size=130, replace=False)
+        v = 0.05 * rng.standard_normal(130)
+        A[others, c] += v
+        A[c, others] -= v
+    assert np.abs(A + A.T).max() == 0.0
+    nnz = int(np.count_nonzero(A))
+    assert nnz <= 16 * n  # the library keeps the compressed-column path
+    assert int(np.count_nonzero(A[:, :256])) > 2048
+    ham = si.MajoranaHamiltonian(N=base.N, A=A, quartic_idx=base.quartic_idx, quartic_val=base.quartic_val,
+                                 e0=base.e0)
+    gam = si.random_states(ham.N, 3, 9)
+    _say(f"[general] sparse A with dense columns n={n} nnz={nnz} R=3")
+    _step_case(ham, gam, 1, 1)
+
+
 # ------------------------------------------ interaction words of 6 and 8
 
 def _multibody(L, W3=0.6, W4=-0.4):
