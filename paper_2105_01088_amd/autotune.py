@@ -11,7 +11,7 @@ placement, force tile edge, deferral of the Gauss-Jordan inner updates), keeps t
 JSON: {"rows": [{n_max, gj_super, ...}], "measured": {...}}.  The file is read
 by paper_2105_01088_amd.default_options(tune=path) and bench.py --tune.
 Every choice changes scheduling and blocking only; results agree with the
-built-in choices to rounding (the parity tests cover the defaults).
+built-in choices to rounding (the parity tests cover every choice).
 """
 
 from __future__ import annotations

@@ -72,7 +72,7 @@ struct Prob {
   // launch before every panel lengthens the chain the others wait on), so
   // the built-in choice applies every panel's update at once
   int gj_defer = 1;
-  int force_split = 2;    // workgroups per force output tile (term ranges)
+  int force_split = 2;    // workgroups per force output tile (term ranges; set by pick_tuning)
   int force_tile = 0;     // force output tile edge (64 or 128; 0: by size and precision)
   bool force_seq = false;  // elementwise force terms after the products, same stream
   int worker = 0;  // stream (and scratch region) this problem runs on
@@ -587,13 +587,17 @@ static int pf_super_default(int m) { return m <= 512 ? 16 : PF_SUPER_MAX; }
 
 // Built-in scheduling choices by size, then the caller's tuning row (if any).
 static void pick_tuning(Prob& q, const sgs_options& o) {
+  // measured at n = 400, 800, 1204, alternating the settings in one
+  // session: both batches of inverses start together (with the pairs (0, a)
+  // first the phase chain shares the GPU with the other inverses for its
+  // whole length); Gauss-Jordan super-panels of 128 (256 ties at n = 1204,
+  // 180.3 ms per step either way); force tiles of one workgroup between
+  // n = 600 and 1002 (89.5 instead of 91.0 ms at n = 800), of two elsewhere
+  // (5.72 instead of 5.80 ms at n = 400, 180.9 instead of 181.2 at 1204)
   q.gj_nb = pick_gj_nb(q.n, 0);
   q.gj_super = 128;
   q.pf.super = pf_super_default(q.n);
-  // measured at n = 400, 800, 1204: both batches of inverses start together
-  // (with the pairs (0, a) first the phase chain then shares the GPU with the
-  // other inverses for its whole length: 256 instead of 253 ms per step at
-  // n = 1204); super-panels of 128 beat 64 and 256 at all three sizes
+  q.force_split = q.n > 600 && q.n <= 1002 ? 1 : 2;
   q.gj_first = false;
   for (int i = 0; i < o.ntune; ++i) {
     const sgs_tune& t = o.tune[i];
