@@ -125,6 +125,40 @@ def test_small_rank_edge_cases(R):
     ctx.close()
 
 
+def _tiny_ham(N, seed, quartic):
+    rng = np.random.default_rng(seed)
+    n = 2 * N
+    z = rng.standard_normal((n, n))
+    qi = np.array([[0, 1, 2, 3]], dtype=np.int32) if quartic else np.zeros((0, 4), dtype=np.int32)
+    qv = np.array([0.6]) if quartic else np.zeros(0)
+    return si.MajoranaHamiltonian(N=N, A=0.5 * (z - z.T), quartic_idx=qi, quartic_val=qv, e0=0.1)
+
+
+@pytest.mark.parametrize("N,R", [(2, 1), (2, 2), (2, 3), (2, 4), (1, 1), (1, 2)])
+def test_tiny_systems(N, R):
+    """The degenerate sizes: two modes (n = 4, one quartic word; the even
+    sector has dimension 2, so R >= 2 is exact and R = 3, 4 leave G
+    singular) and one mode (n = 2: every pure even state is the same one,
+    so R = 2 gives two identical states).  Matrices narrower than every
+    panel and tile, Pfaffians of order 2, canonical orthogonalization
+    dropping vectors; two steps at 1e-10."""
+    ham = _tiny_ham(N, N, N == 2)
+    gam = si.random_states(N, R, 3 + R)
+    _say(f"[step] tiny n={ham.n} R={R}")
+    ctx = _ctx(ham, gam, weight=1)
+    e = ctx.step(0.05, 2).cpu().numpy().ravel()
+    assert ctx.status() == 0
+    g = gam
+    es = []
+    for _ in range(2):
+        r = osgs.step(ham, g, 0.05, mode="unit")
+        es.append(r.E)
+        g = r.gammas
+    assert np.abs(e - es).max() < TOL_E * max(1.0, np.abs(es).max())
+    assert np.abs(ctx.gammas(0).cpu().numpy() - g).max() < TOL_GAMMA
+    ctx.close()
+
+
 def test_two_channel_kondo_step():
     ham = si.two_channel_kondo(3, 0.5, U=8.0)
     gam = si.random_states(ham.N, 3, 2)
